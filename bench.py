@@ -1,0 +1,216 @@
+#!/usr/bin/env python3
+"""Throughput of one DARC coordinate-descent sweep on one MI355X.
+
+A step is one sweep of Eq. (3) / Algorithm 1 over the whole cohort: K2 inner
+iterations per subject (Exp by scaling and squaring, warp, dissimilarity and
+regulariser, adjoint through warp and squarings, Adam, Gaussian smoothing of
+v), then Exp, centrality activation, mean atlas and group loss.  Inputs are a
+seeded synthetic cohort already resident in GPU memory when timing starts.
+
+Prints one JSON line: subject-voxel-iterations per second (n * V * K2 per
+sweep time), the roofline position of the kernel class that takes the most
+time, the per-class achieved bandwidth, and the FP64 CPU oracle timed on a
+bounded sample of the same workload on one host core.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+
+DEFAULT_WORKLOAD = "brain-16x160x192x160-lncc9"
+
+
+def algorithmic_bytes(w, batch):
+    """Bytes each kernel class must move per sweep (FP32 state, one pass per
+    step, gathers served from cache), keyed like the library's timing classes."""
+    n, V, k2, N = w.n, w.voxels, w.k2, w.n_sq
+    lncc = w.metric == "lncc"
+    b = {
+        # per squaring step: read u_t (12 B), write u_{t+1} (12 B)
+        "exp_fwd_step": N * (k2 + 1) * n * V * 24,
+        # per adjoint step: read u_t and g_{t+1}, accumulate g_t (12 B each)
+        "exp_bwd_step": N * k2 * n * V * 36,
+        # zeroing the adjoint accumulator before each step
+        "fill": N * k2 * n * V * 12,
+        # read g, v, m, s; write v, m, s
+        "adam": k2 * n * V * 84,
+        # read u of every subject, write centred u
+        "center": n * V * 24,
+        # read u and the image of every subject, write the atlas
+        "atlas": n * V * 16 + V * 4,
+    }
+    if lncc:
+        b["warp"] = (k2 + 1) * n * V * 20           # read u, image; write warped
+        b["lncc_fwd"] = k2 * n * V * 24 + n * V * 8  # read warped, atlas; write 4 factors
+        b["lncc_bwd"] = k2 * n * V * 52              # read 4 factors, warped, atlas, u, image; write g
+        if w.lam:
+            b["diffusion"] = n * V * 12
+    else:
+        b["mse"] = k2 * n * V * 32 + n * V * 20      # fused warp + MSE (+ adjoint)
+    if w.smooth_sigma > 0:
+        b["gauss"] = k2 * n * V * 24
+    return b
+
+
+def cpu_baseline(w, seconds_hint=True):
+    """The FP64 oracle on one subject's central crop (1/8 of the voxels),
+    two inner iterations, one thread."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import darc_oracle as O
+    from synthetic.cohorts import make_cohort
+
+    imgs = make_cohort(w, n=2)
+    d0, d1, d2 = w.dims
+    sl = (slice(d0 // 4, d0 // 4 + d0 // 2), slice(d1 // 4, d1 // 4 + d1 // 2),
+          slice(d2 // 4, d2 // 4 + d2 // 2))
+    subj = imgs[0][sl].astype(np.float64)
+    atlas = imgs[1][sl].astype(np.float64)
+    p = O.SweepParams(metric=w.metric, win=w.win, ncc_eps=w.ncc_eps, lam=w.lam,
+                      smooth_sigma=w.smooth_sigma, n_sq=w.n_sq, k2=w.k2)
+    iters = 2
+    with threadpool_limits(limits=1):
+        v = np.zeros((3,) + subj.shape)
+        m = np.zeros_like(v)
+        s = np.zeros_like(v)
+        t0 = time.perf_counter()
+        for k in range(iters):
+            _, g = O.subject_loss_grad(subj, v, atlas, p)
+            v, m, s = O.adam_step(v, m, s, g, k + 1)
+            if p.smooth_sigma > 0:
+                v = O.gauss_smooth(v, p.smooth_sigma)
+        dt = time.perf_counter() - t0
+    vox = subj.size
+    return {
+        "value": vox * iters / dt,
+        "unit": "subject-voxel-iters/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": f"1 subject, central {subj.shape[0]}x{subj.shape[1]}x{subj.shape[2]} crop "
+                  f"of {w.name}, {iters} inner iterations (Exp, warp, dissimilarity, adjoint, "
+                  f"Adam, smoothing), FP64 NumPy, {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed sweeps")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed sweeps before timing")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--batch", type=int, default=0, help="subjects per launch (0 = all)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: the DARC path here runs on a single MI355X and has "
+              f"no multi-GPU mode (asked for --gpus {args.gpus})", file=sys.stderr)
+        sys.exit(2)
+
+    from synthetic.cohorts import WORKLOADS, make_cohort
+
+    w = WORKLOADS[args.workload]
+    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+
+    import torch
+
+    from paper_2508_10743_amd import darc as D
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda", 0)
+    print(f"# generating {w.name}", file=sys.stderr, flush=True)
+    images = torch.from_numpy(make_cohort(w)).to(dev)
+    params = D.SweepParams(metric=w.metric, win=w.win, ncc_eps=w.ncc_eps, lam=w.lam,
+                           smooth_sigma=w.smooth_sigma, n_sq=w.n_sq, k2=w.k2, lr=w.lr,
+                           beta1=w.beta1, beta2=w.beta2, adam_eps=w.adam_eps, batch=args.batch)
+    cohort = D.Cohort(images, params)
+    torch.cuda.synchronize()
+    for i in range(args.warmup):
+        cohort.sweep()
+        torch.cuda.synchronize()
+        print(f"# warmup sweep {i + 1}/{args.warmup}: F = {cohort.group_loss():.6f}",
+              file=sys.stderr, flush=True)
+
+    profile = not args.no_profile
+    if profile:
+        D.profile_reset()
+        D.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        cohort.sweep()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kernels = {}
+    roofline = None
+    if profile:
+        D.profile_enable(False)
+        prof = D.profile_collect()
+        algo = algorithmic_bytes(w, args.batch)
+        for cls, (cnt, ms) in prof.items():
+            if cnt == 0:
+                continue
+            entry = {"launches": cnt, "ms": round(ms, 4), "avg_us": round(1e3 * ms / cnt, 2)}
+            if cls in algo:
+                gbs = algo[cls] * args.steps / (ms * 1e-3) / 1e9
+                entry["algo_GB_per_launch"] = round(algo[cls] * args.steps / cnt / 1e9, 4)
+                entry["GB/s"] = round(gbs, 1)
+            kernels[cls] = entry
+        dom = max((c for c in kernels if "GB/s" in kernels[c]), key=lambda c: kernels[c]["ms"])
+        achieved = kernels[dom]["GB/s"]
+        roofline = {
+            "kernel": dom,
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": None,
+        }
+
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    value = w.n * w.voxels * w.k2 / (ms_per_step * 1e-3)
+    out = {
+        "metric": "subject-voxel-iters/s per DARC sweep",
+        "value": round(value, 1),
+        "unit": "subject-voxel-iters/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": w.name,
+            "n_subjects": w.n,
+            "dims": list(w.dims),
+            "metric": f"{w.metric}{w.win if w.metric == 'lncc' else ''}",
+            "k2": w.k2,
+            "n_sq": w.n_sq,
+            "smooth_sigma": w.smooth_sigma,
+            "lam": w.lam,
+            "batch": args.batch or w.n,
+        },
+        "group_loss": cohort.group_loss(),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

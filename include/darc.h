@@ -1,0 +1,287 @@
+/*
+ * darc.h -- C ABI of libdarc, the gfx950 hot path of DARC (Diffeomorphic
+ * Atlas Registration via Coordinate descent), the groupwise atlas
+ * construction method of "An Efficient Model-Driven Groupwise Approach for
+ * Atlas Construction" (arXiv 2508.10743).
+ *
+ * What the library computes (Section 3 of the paper):
+ *   - the group objective of Eq. (1)-(2): for every subject i a dissimilarity
+ *     between the warped image I_i o phi_i and the atlas A, plus a diffusion
+ *     regulariser lambda ||grad phi_i||^2, under the centrality constraint
+ *     sum_i phi_i = 0;
+ *   - phi_i = Exp(v_i) for a stationary velocity field v_i, by scaling and
+ *     squaring (Section 3, "Diffeomorphisms": seven squarings);
+ *   - one coordinate-descent sweep of Eq. (3) / Algorithm 1: per-subject
+ *     gradient steps against a fixed atlas, the centrality activation
+ *     phi_i - (1/n) sum_j phi_j (fourth line of Eq. (3)), then the atlas
+ *     update, which for MSE is the mean of the warped subjects (first equation
+ *     of Section 3, "Dissimilarity metrics").
+ *
+ * Conventions shared by every call
+ *   - A volume has dims (d0, d1, d2) with d2 fastest: voxel (x0, x1, x2) sits
+ *     at linear index (x0 * d1 + x1) * d2 + x2.  V = d0 * d1 * d2.  Each dim is
+ *     at least 2 and V is at most 2^29.
+ *   - A field (velocity v, displacement u, their gradients) is [3][V] per
+ *     subject; component c displaces axis c, in voxel units.  phi is handled as
+ *     the displacement u = phi - id (the reading under which sum_i phi_i = 0
+ *     is meaningful).  A batch of n subjects is [n][3][V] (fields) or [n][V]
+ *     (images), contiguous.
+ *   - Positions are voxel coordinates with voxel centres at integers.
+ *     Sampling is trilinear.  Images are sampled with zero padding (a corner
+ *     outside the volume contributes 0); fields are sampled with border
+ *     clamping (the position is clamped into [0, D-1] per axis).
+ *   - All float arrays are FP32 device memory owned by the caller, at least
+ *     4-byte aligned; double arrays are FP64 device memory.  The library never
+ *     frees or retains a caller pointer beyond the call.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Every call only enqueues work on that stream and returns without
+ *     synchronising; results are ready once the stream has reached that point.
+ *   - Scratch memory is passed in by the caller: `ws`/`ws_bytes` must hold at
+ *     least what the matching *_ws_bytes query returns (256-byte aligned).
+ *     The library allocates no device memory.
+ *   - Every call returns DARC_OK (0) or a negative status; on error nothing is
+ *     enqueued (argument errors) or the HIP error is reported (DARC_EHIP), and
+ *     darc_last_error() returns a message for the calling thread.
+ *   - Calls on different streams that write the same memory race; calls on
+ *     one stream are ordered.
+ */
+#ifndef DARC_H
+#define DARC_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DARC_ABI_VERSION 1
+
+/* status codes */
+#define DARC_OK 0
+#define DARC_EINVAL (-1)       /* null pointer, bad dims or parameter */
+#define DARC_EHIP (-2)         /* a HIP launch or runtime call failed */
+#define DARC_EWORKSPACE (-3)   /* ws is null, misaligned or too small */
+#define DARC_EUNSUPPORTED (-4) /* valid but not built (e.g. window size) */
+
+/* dissimilarity metrics (Section 3, "Dissimilarity metrics") */
+#define DARC_MSE 0   /* (1/V) sum_x (Iw - A)^2 */
+#define DARC_LNCC 1  /* -(1/V) sum_x cc(x), squared local NCC over a win^3 window */
+
+/* smoothing modes */
+#define DARC_GAUSS 0     /* separable Gaussian, replicated border */
+#define DARC_DIFFUSION 1 /* gradient of the diffusion regulariser of Eq. (2) */
+
+/* what the centrality activation acts on */
+#define DARC_CENTER_DISPLACEMENT 0 /* u_i <- u_i - mean_j u_j (Eq. (3), line 4) */
+#define DARC_CENTER_VELOCITY 1     /* v_i <- v_i - mean_j v_j, then u_i = Exp(v_i) */
+
+/* Version of this header's ABI (DARC_ABI_VERSION). */
+int darc_abi_version(void);
+
+/* Message describing the last error on the calling thread ("" if none).
+ * The pointer stays valid until the next call on that thread. */
+const char* darc_last_error(void);
+
+/* ------------------------------------------------------------------------
+ * darc_exp_svf -- phi = Exp(v) by scaling and squaring (Section 3,
+ * "Diffeomorphisms").
+ *
+ *   u_0 = v / 2^n_sq;  u_{t+1}(x) = u_t(x) + u_t(x + u_t(x))  (t = 0..n_sq-1)
+ *   u   = u_{n_sq}, the displacement of Exp(v).
+ *
+ * The inner u_t(.) is sampled trilinearly with border clamping.
+ *   v     [n][3][V] in.
+ *   u     [n][3][V] out; must not alias v or ckpt.
+ *   ckpt  [n_sq-1][n][3][V] out, or NULL: the intermediate u_1..u_{n_sq-1}
+ *         (step-major: slot j holds u_{j+1} of all n subjects), which
+ *         darc_exp_svf_bwd needs.  Unused when n_sq < 2.
+ *   ws    scratch of darc_exp_svf_ws_bytes(); only needed when ckpt is NULL.
+ *   n_sq  0..16 (n_sq = 0 gives u = v).
+ * ---------------------------------------------------------------------- */
+size_t darc_exp_svf_ws_bytes(int n, int d0, int d1, int d2, int n_sq, int has_ckpt);
+int darc_exp_svf(const float* v, float* u, float* ckpt, int n, int d0, int d1, int d2,
+                 int n_sq, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_exp_svf_bwd -- adjoint of darc_exp_svf (the gradient that automatic
+ * differentiation of the squaring steps gives, Algorithm 1 `loss.backward()`).
+ *
+ * Given g_u = dL/du, returns g_v = dL/dv = (du/dv)^T g_u.  One squaring step
+ * u_{t+1}(x) = u_t(x) + S(u_t, x + u_t(x)) has the adjoint
+ *   g_t(y) = g_{t+1}(y) + J_t(y)^T g_{t+1}(y) + sum_x sum_k [corner_k(x) = y] w_k(x) g_{t+1}(x)
+ * where J_t is the position derivative of the sampled field at x + u_t(x)
+ * (zero along an axis whose coordinate was clamped) and w_k the trilinear
+ * weights; dL/dv = g_0 / 2^n_sq.
+ *   v     [n][3][V] in (u_0 is recomputed from it).
+ *   ckpt  [n_sq-1][n][3][V] in: the checkpoints written by darc_exp_svf.
+ *         Required when n_sq >= 2.
+ *   g_u   [n][3][V] in.   g_v [n][3][V] out (overwritten, not accumulated).
+ *   ws    scratch of darc_exp_svf_bwd_ws_bytes().
+ * The scatter uses floating-point atomics: results are reproducible only up
+ * to FP32 summation order.
+ * ---------------------------------------------------------------------- */
+size_t darc_exp_svf_bwd_ws_bytes(int n, int d0, int d1, int d2, int n_sq);
+int darc_exp_svf_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, int n,
+                     int d0, int d1, int d2, int n_sq, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_warp3d -- I o phi (the warping operator of Eq. (2)):
+ *   out_i(x) = I_i(x + u_i(x)), trilinear, zero outside the volume.
+ *   img [n][V] in, u [n][3][V] in, out [n][V] out (must not alias img).
+ *
+ * darc_warp3d_bwd -- its adjoint with respect to u:
+ *   g_u_i(x) += g_out_i(x) * grad_p I_i(p) at p = x + u_i(x),
+ * the derivative of the trilinear interpolant inside the cell
+ * [floor p, floor p + 1] (right-sided at integer positions).
+ *   g_u [n][3][V] in/out, accumulated.
+ * ---------------------------------------------------------------------- */
+int darc_warp3d(const float* img, const float* u, float* out, int n, int d0, int d1, int d2,
+                void* stream);
+int darc_warp3d_bwd(const float* img, const float* u, const float* g_out, float* g_u, int n,
+                    int d0, int d1, int d2, void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_sim_grad -- dissimilarity between each warped subject and the atlas
+ * (Section 3, "Dissimilarity metrics") and its gradient.
+ *
+ *   DARC_MSE : D_i = (1/V) sum_x (W_i - A)^2;   dD_i/dW_i = (2/V)(W_i - A).
+ *   DARC_LNCC: window sums over the win^3 cube centred at x, zero outside the
+ *              volume, with the fixed count N = win^3:
+ *              cross = S_IJ - S_I S_J / N, Ivar = S_II - S_I^2 / N,
+ *              Jvar = S_JJ - S_J^2 / N, cc = cross^2 / (Ivar Jvar + eps),
+ *              D_i = -(1/V) sum_x cc(x)  (I = W_i, J = A).
+ *              Window sums are accumulated in FP64.
+ *   warped   [n][V] in, atlas [V] in (shared by the n subjects).
+ *   loss     [n] FP64 in/out: loss[i] += D_i.
+ *   g_warped [n][V] out (overwritten), or NULL for the loss only.
+ *   win      LNCC window, odd, 3..11 (ignored for MSE).  eps > 0 (LNCC).
+ *   ws       scratch of darc_sim_grad_ws_bytes() (LNCC with gradient only).
+ * ---------------------------------------------------------------------- */
+size_t darc_sim_grad_ws_bytes(int metric, int n, int d0, int d1, int d2);
+int darc_sim_grad(const float* warped, const float* atlas, int metric, int win, float eps,
+                  double* loss, float* g_warped, int n, int d0, int d1, int d2, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_smooth3d -- smoothing of ncomp-component volumes [n][ncomp][V].
+ *
+ *   DARC_GAUSS (param = sigma > 0): out = G_sigma * in per component,
+ *     separable 1-D weights proportional to exp(-k^2 / (2 sigma^2)) for
+ *     |k| <= r = int(3 sigma + 0.5) (r <= 8), normalised to sum 1, replicated
+ *     border.  out must not alias in.  loss is ignored.
+ *   DARC_DIFFUSION (param = lambda): the diffusion regulariser of Eq. (2) on a
+ *     displacement u,
+ *       R(u) = (1/3) sum_d mean_{c, x: x_d < D_d - 1} (u_c(x + e_d) - u_c(x))^2,
+ *     out += lambda dR/din and, if loss is not NULL, loss[i] += lambda R(in_i).
+ *     out must not alias in.
+ *   ws  unused (pass NULL, 0).
+ * ---------------------------------------------------------------------- */
+int darc_smooth3d(const float* in, float* out, int n, int ncomp, int d0, int d1, int d2,
+                  int mode, float param, double* loss, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_adam_step -- one Adam step (the paper's optimiser, Section 5: Adam
+ * with learning rate 1e-2; Kingma & Ba's bias-corrected update):
+ *   m <- b1 m + (1 - b1) g;  s <- b2 s + (1 - b2) g^2;
+ *   v <- v - lr (m / (1 - b1^t)) / (sqrt(s / (1 - b2^t)) + eps)
+ * over `count` floats.  t >= 1 is the step number after this update.  The
+ * betas are doubles because 1 - beta2 magnifies the rounding of beta2 to FP32
+ * (0.999f is 1.3e-5 off in 1 - beta2).
+ * v, m, s in/out; g in.
+ * ---------------------------------------------------------------------- */
+int darc_adam_step(float* v, float* m, float* s, const float* g, long long count, long long t,
+                   float lr, double beta1, double beta2, float eps, void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_center -- the centrality activation (fourth line of Eq. (3)):
+ *   mean = (1/n) sum_j u_j;  u_i <- u_i - mean  for every i.
+ *   u [n][3][V] in/out.  mean_out [3][V] out, or NULL.
+ * The mean is accumulated in FP64.
+ * ---------------------------------------------------------------------- */
+int darc_center(float* u, float* mean_out, int n, int d0, int d1, int d2, void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_atlas_update -- the MSE atlas closed form (Section 3, "Dissimilarity
+ * metrics"): A = (1/n) sum_i I_i o phi_hat_i, i.e.
+ *   A(x) = (1/n) sum_i I_i(x + u_i(x) - mean(x)),  trilinear, zero padding.
+ *   images [n][V] in, u [n][3][V] in.
+ *   mean   [3][V] in, or NULL (u is then taken as already centred).
+ *   atlas  [V] out.  Accumulated in FP64.
+ * ---------------------------------------------------------------------- */
+int darc_atlas_update(const float* images, const float* u, const float* mean, float* atlas,
+                      int n, int d0, int d1, int d2, void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_sweep -- one coordinate-descent sweep (Eq. (3), Algorithm 1 `main`).
+ *
+ *   step 1: for every subject i (independent given the atlas, Section 3 after
+ *           Eq. (3)), k2 times: u = Exp(v_i); L = D(I_i o phi, A) + lam R(u);
+ *           g = dL/dv_i; Adam step on v_i; if smooth_sigma > 0, v_i <- G * v_i.
+ *   step 2: u_i = Exp(v_i); centrality activation (center_mode).
+ *   step 3: A <- (1/n) sum_i I_i o phi_hat_i.
+ *   then the group loss F = (1/n) sum_i [D(I_i o phi_hat_i, A) + lam R(u_hat_i)].
+ *
+ * The atlas update is the MSE closed form for both metrics (with LNCC it is
+ * the mean of the warped subjects, not an SGD atlas).
+ * ---------------------------------------------------------------------- */
+typedef struct darc_state {
+  const float* images; /* [n][V] subject images I_i, in */
+  float* v;            /* [n][3][V] stationary velocity fields, in/out */
+  float* m;            /* [n][3][V] Adam first moments, in/out */
+  float* s;            /* [n][3][V] Adam second moments, in/out */
+  float* atlas;        /* [V] atlas: A^k in, A^{k+1} out */
+  float* u_hat;        /* [n][3][V] centred displacements out, or NULL */
+  long long step;      /* Adam step count shared by all subjects, in/out (host) */
+  int n, d0, d1, d2;
+} darc_state;
+
+typedef struct darc_params {
+  int metric;         /* DARC_MSE or DARC_LNCC */
+  int win;            /* LNCC window (odd, 3..11) */
+  float ncc_eps;      /* LNCC epsilon (> 0) */
+  float lam;          /* diffusion regulariser weight (>= 0) */
+  float smooth_sigma; /* Gaussian sigma applied to v after every step; 0 = off */
+  int n_sq;           /* squaring steps, 1..16 (7 in the paper) */
+  int k2;             /* inner iterations per subject per sweep (>= 1) */
+  float lr;           /* Adam learning rate */
+  double beta1, beta2; /* Adam moment decay rates, in [0, 1) */
+  float adam_eps;     /* Adam epsilon (> 0) */
+  int center_mode;    /* DARC_CENTER_DISPLACEMENT or DARC_CENTER_VELOCITY */
+  int reinit_v;       /* 1: v, m, s and step reset to zero before step 1 */
+  int batch;          /* subjects per launch in step 1: 1 = per subject, n = all */
+} darc_params;
+
+/* sizeof(darc_state) and sizeof(darc_params) as compiled into the library,
+ * for bindings that mirror the two structs. */
+size_t darc_sizeof_state(void);
+size_t darc_sizeof_params(void);
+
+/* Scratch needed by darc_sweep for this state shape and parameters (0 when
+ * the state or parameters are invalid). */
+size_t darc_sweep_ws_bytes(const darc_state* st, const darc_params* p);
+
+/* losses: FP64 device array [n * k2 + 1], overwritten: losses[i * k2 + k] is
+ * subject i's loss before its (k+1)-th step, losses[n * k2] the group loss F
+ * after the sweep.  st->step is advanced by k2 on the host. */
+int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, size_t ws_bytes,
+               void* stream);
+
+/* ------------------------------------------------------------------------
+ * Kernel timing for measurement.  When enabled, every kernel launched by the
+ * library records HIP events on its stream; darc_profile_collect()
+ * synchronises those events and returns, per kernel class, the number of
+ * launches and their summed duration in milliseconds since the last reset.
+ * Class names come from darc_profile_name().  Not thread-safe; meant for a
+ * benchmark driving one stream.
+ * ---------------------------------------------------------------------- */
+int darc_profile_enable(int on);
+int darc_profile_reset(void);
+int darc_profile_num_classes(void);
+const char* darc_profile_name(int cls);
+int darc_profile_collect(long long* counts, double* ms, int max_classes);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DARC_H */

@@ -1,0 +1,531 @@
+// C ABI of libdarc: argument validation, workspace sizing, the coordinate-
+// descent sweep (Eq. (3), Algorithm 1 of the paper) and kernel timing.
+#include <cstdarg>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "darc.h"
+#include "darc_kernels.hpp"
+
+using namespace darc;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  std::vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int ok() {
+  g_err.clear();
+  return DARC_OK;
+}
+
+int check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(DARC_EHIP, "%s: %s", what, hipGetErrorString(e));
+  return ok();
+}
+
+constexpr long long kMaxVoxels = 1ll << 29;
+
+int check_dims(const char* fn, int n, int d0, int d1, int d2) {
+  if (n < 0) return fail(DARC_EINVAL, "%s: n = %d < 0", fn, n);
+  if (d0 < 2 || d1 < 2 || d2 < 2)
+    return fail(DARC_EINVAL, "%s: every dim must be >= 2 (got %d x %d x %d)", fn, d0, d1, d2);
+  const long long V = static_cast<long long>(d0) * d1 * d2;
+  if (V > kMaxVoxels)
+    return fail(DARC_EINVAL, "%s: %lld voxels exceed the limit of %lld", fn, V, kMaxVoxels);
+  return DARC_OK;
+}
+
+size_t align256(size_t b) { return (b + 255) & ~static_cast<size_t>(255); }
+
+int check_ws(const char* fn, void* ws, size_t ws_bytes, size_t need) {
+  if (need == 0) return DARC_OK;
+  if (!ws) return fail(DARC_EWORKSPACE, "%s: workspace of %zu bytes required, got NULL", fn, need);
+  if (reinterpret_cast<uintptr_t>(ws) % 256 != 0)
+    return fail(DARC_EWORKSPACE, "%s: workspace must be 256-byte aligned", fn);
+  if (ws_bytes < need)
+    return fail(DARC_EWORKSPACE, "%s: workspace of %zu bytes is smaller than %zu", fn, ws_bytes,
+                need);
+  return DARC_OK;
+}
+
+size_t field_bytes(int n, int d0, int d1, int d2) {
+  return static_cast<size_t>(n) * 3 * d0 * d1 * d2 * sizeof(float);
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+#define DARC_TRY(expr)          \
+  do {                          \
+    const int rc__ = (expr);    \
+    if (rc__ != DARC_OK) return rc__; \
+  } while (0)
+
+// ------------------------------------------------------------- kernel timing
+
+struct ProfRec {
+  int cls;
+  hipEvent_t a, b;
+};
+
+bool g_prof_on = false;
+std::vector<ProfRec> g_prof_recs;
+std::vector<hipEvent_t> g_event_pool;
+long long g_prof_counts[KC_NUM];
+double g_prof_ms[KC_NUM];
+
+const char* const kClassNames[KC_NUM] = {
+    "exp_fwd_step", "exp_bwd_step", "warp", "warp_bwd", "mse", "lncc_fwd", "lncc_bwd",
+    "gauss", "diffusion", "adam", "center", "atlas", "fill", "misc"};
+
+hipEvent_t take_event() {
+  if (!g_event_pool.empty()) {
+    hipEvent_t e = g_event_pool.back();
+    g_event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+}  // namespace
+
+namespace darc {
+
+void prof_begin(hipStream_t s, int cls) {
+  if (!g_prof_on) return;
+  hipEvent_t a = take_event();
+  if (!a) return;
+  hipEventRecord(a, s);
+  g_prof_recs.push_back(ProfRec{cls, a, nullptr});
+}
+
+void prof_end(hipStream_t s, int cls) {
+  if (!g_prof_on || g_prof_recs.empty()) return;
+  ProfRec& r = g_prof_recs.back();
+  if (r.cls != cls || r.b != nullptr) return;
+  hipEvent_t b = take_event();
+  if (!b) return;
+  hipEventRecord(b, s);
+  r.b = b;
+}
+
+}  // namespace darc
+
+extern "C" {
+
+int darc_abi_version(void) { return DARC_ABI_VERSION; }
+
+const char* darc_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------ Exp(v)
+
+size_t darc_exp_svf_ws_bytes(int n, int d0, int d1, int d2, int n_sq, int has_ckpt) {
+  if (n <= 0 || n_sq < 2 || has_ckpt) return 0;
+  return field_bytes(n, d0, d1, d2);
+}
+
+int darc_exp_svf(const float* v, float* u, float* ckpt, int n, int d0, int d1, int d2, int n_sq,
+                 void* ws, size_t ws_bytes, void* stream) {
+  DARC_TRY(check_dims("darc_exp_svf", n, d0, d1, d2));
+  if (n == 0) return ok();
+  if (!v || !u) return fail(DARC_EINVAL, "darc_exp_svf: v and u must not be NULL");
+  if (u == v) return fail(DARC_EINVAL, "darc_exp_svf: u must not alias v");
+  if (n_sq < 0 || n_sq > 16) return fail(DARC_EINVAL, "darc_exp_svf: n_sq = %d not in 0..16", n_sq);
+  const size_t need = darc_exp_svf_ws_bytes(n, d0, d1, d2, n_sq, ckpt != nullptr);
+  DARC_TRY(check_ws("darc_exp_svf", ws, ws_bytes, need));
+  const Geom g = make_geom(d0, d1, d2);
+  run_exp_fwd(v, u, n_sq >= 2 ? ckpt : nullptr, static_cast<float*>(ws), g, n, n_sq,
+              as_stream(stream));
+  return check_launch("darc_exp_svf");
+}
+
+size_t darc_exp_svf_bwd_ws_bytes(int n, int d0, int d1, int d2, int n_sq) {
+  if (n <= 0 || n_sq < 2) return 0;
+  const size_t f = align256(field_bytes(n, d0, d1, d2));
+  return n_sq == 2 ? f : 2 * f;
+}
+
+int darc_exp_svf_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, int n, int d0,
+                     int d1, int d2, int n_sq, void* ws, size_t ws_bytes, void* stream) {
+  DARC_TRY(check_dims("darc_exp_svf_bwd", n, d0, d1, d2));
+  if (n == 0) return ok();
+  if (!v || !g_u || !g_v) return fail(DARC_EINVAL, "darc_exp_svf_bwd: v, g_u, g_v must not be NULL");
+  if (g_v == g_u) return fail(DARC_EINVAL, "darc_exp_svf_bwd: g_v must not alias g_u");
+  if (n_sq < 0 || n_sq > 16)
+    return fail(DARC_EINVAL, "darc_exp_svf_bwd: n_sq = %d not in 0..16", n_sq);
+  if (n_sq >= 2 && !ckpt)
+    return fail(DARC_EINVAL, "darc_exp_svf_bwd: ckpt is required when n_sq >= 2");
+  const size_t need = darc_exp_svf_bwd_ws_bytes(n, d0, d1, d2, n_sq);
+  DARC_TRY(check_ws("darc_exp_svf_bwd", ws, ws_bytes, need));
+  const Geom g = make_geom(d0, d1, d2);
+  float* tmp_a = static_cast<float*>(ws);
+  float* tmp_b = n_sq >= 3 ? reinterpret_cast<float*>(static_cast<char*>(ws) +
+                                                      align256(field_bytes(n, d0, d1, d2)))
+                           : nullptr;
+  run_exp_bwd(v, ckpt, g_u, g_v, tmp_a, tmp_b, g, n, n_sq, as_stream(stream));
+  return check_launch("darc_exp_svf_bwd");
+}
+
+// -------------------------------------------------------------------- warp
+
+int darc_warp3d(const float* img, const float* u, float* out, int n, int d0, int d1, int d2,
+                void* stream) {
+  DARC_TRY(check_dims("darc_warp3d", n, d0, d1, d2));
+  if (n == 0) return ok();
+  if (!img || !u || !out) return fail(DARC_EINVAL, "darc_warp3d: NULL pointer");
+  if (out == img) return fail(DARC_EINVAL, "darc_warp3d: out must not alias img");
+  launch_warp(img, u, out, make_geom(d0, d1, d2), n, as_stream(stream));
+  return check_launch("darc_warp3d");
+}
+
+int darc_warp3d_bwd(const float* img, const float* u, const float* g_out, float* g_u, int n, int d0,
+                    int d1, int d2, void* stream) {
+  DARC_TRY(check_dims("darc_warp3d_bwd", n, d0, d1, d2));
+  if (n == 0) return ok();
+  if (!img || !u || !g_out || !g_u) return fail(DARC_EINVAL, "darc_warp3d_bwd: NULL pointer");
+  launch_warp_bwd(img, u, g_out, g_u, make_geom(d0, d1, d2), n, as_stream(stream));
+  return check_launch("darc_warp3d_bwd");
+}
+
+// --------------------------------------------------------- dissimilarities
+
+size_t darc_sim_grad_ws_bytes(int metric, int n, int d0, int d1, int d2) {
+  if (metric != DARC_LNCC || n <= 0) return 0;
+  return static_cast<size_t>(n) * 4 * d0 * d1 * d2 * sizeof(float);
+}
+
+int darc_sim_grad(const float* warped, const float* atlas, int metric, int win, float eps,
+                  double* loss, float* g_warped, int n, int d0, int d1, int d2, void* ws,
+                  size_t ws_bytes, void* stream) {
+  DARC_TRY(check_dims("darc_sim_grad", n, d0, d1, d2));
+  if (metric != DARC_MSE && metric != DARC_LNCC)
+    return fail(DARC_EINVAL, "darc_sim_grad: unknown metric %d", metric);
+  if (metric == DARC_LNCC) {
+    if (win < 1 || win % 2 == 0)
+      return fail(DARC_EINVAL, "darc_sim_grad: window %d must be odd and positive", win);
+    if (!lncc_window_supported(win))
+      return fail(DARC_EUNSUPPORTED, "darc_sim_grad: window %d not built (3, 5, 7, 9, 11)", win);
+    if (!(eps > 0.0f)) return fail(DARC_EINVAL, "darc_sim_grad: eps must be > 0");
+  }
+  if (n == 0) return ok();
+  if (!warped || !atlas || !loss) return fail(DARC_EINVAL, "darc_sim_grad: NULL pointer");
+  const Geom g = make_geom(d0, d1, d2);
+  hipStream_t st = as_stream(stream);
+  if (metric == DARC_MSE) {
+    launch_mse(warped, atlas, loss, 1, g_warped, g, n, st);
+  } else {
+    const size_t need = g_warped ? darc_sim_grad_ws_bytes(metric, n, d0, d1, d2) : 0;
+    DARC_TRY(check_ws("darc_sim_grad", ws, ws_bytes, need));
+    float* fields = g_warped ? static_cast<float*>(ws) : nullptr;
+    launch_lncc_fwd(warped, atlas, fields, loss, 1, win, eps, g, n, st);
+    if (g_warped) launch_lncc_bwd(fields, warped, atlas, g_warped, win, g, n, st);
+  }
+  return check_launch("darc_sim_grad");
+}
+
+// ------------------------------------------------------------- smoothing
+
+int darc_smooth3d(const float* in, float* out, int n, int ncomp, int d0, int d1, int d2, int mode,
+                  float param, double* loss, void* ws, size_t ws_bytes, void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  DARC_TRY(check_dims("darc_smooth3d", n, d0, d1, d2));
+  if (ncomp < 1) return fail(DARC_EINVAL, "darc_smooth3d: ncomp = %d < 1", ncomp);
+  if (mode != DARC_GAUSS && mode != DARC_DIFFUSION)
+    return fail(DARC_EINVAL, "darc_smooth3d: unknown mode %d", mode);
+  if (mode == DARC_GAUSS) {
+    if (!(param > 0.0f)) return fail(DARC_EINVAL, "darc_smooth3d: sigma must be > 0");
+    const int r = gauss_radius(param);
+    if (r < 1 || r > 8)
+      return fail(DARC_EUNSUPPORTED, "darc_smooth3d: radius int(3 sigma + 0.5) = %d not in 1..8", r);
+  }
+  if (n == 0) return ok();
+  if (!in) return fail(DARC_EINVAL, "darc_smooth3d: in must not be NULL");
+  if (out == in) return fail(DARC_EINVAL, "darc_smooth3d: out must not alias in");
+  const Geom g = make_geom(d0, d1, d2);
+  hipStream_t st = as_stream(stream);
+  if (mode == DARC_GAUSS) {
+    if (!out) return fail(DARC_EINVAL, "darc_smooth3d: out must not be NULL");
+    launch_gauss(in, out, param, g, n * ncomp, st);
+  } else {
+    if (!out && !loss) return fail(DARC_EINVAL, "darc_smooth3d: out and loss are both NULL");
+    launch_diffusion(in, out, loss, 1, make_regw(g, ncomp, param), g, n, ncomp, st);
+  }
+  return check_launch("darc_smooth3d");
+}
+
+// ------------------------------------------------- Adam, centring, atlas
+
+int darc_adam_step(float* v, float* m, float* s, const float* g, long long count, long long t,
+                   float lr, double beta1, double beta2, float eps, void* stream) {
+  if (count < 0) return fail(DARC_EINVAL, "darc_adam_step: count < 0");
+  if (t < 1) return fail(DARC_EINVAL, "darc_adam_step: step t must be >= 1");
+  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0))
+    return fail(DARC_EINVAL, "darc_adam_step: betas must lie in [0, 1)");
+  if (!(eps > 0.0f)) return fail(DARC_EINVAL, "darc_adam_step: eps must be > 0");
+  if (count == 0) return ok();
+  if (!v || !m || !s || !g) return fail(DARC_EINVAL, "darc_adam_step: NULL pointer");
+  launch_adam(v, v, m, s, g, count, t, lr, beta1, beta2, eps, as_stream(stream));
+  return check_launch("darc_adam_step");
+}
+
+int darc_center(float* u, float* mean_out, int n, int d0, int d1, int d2, void* stream) {
+  DARC_TRY(check_dims("darc_center", n, d0, d1, d2));
+  if (n == 0) return ok();
+  if (!u) return fail(DARC_EINVAL, "darc_center: u must not be NULL");
+  launch_center(u, mean_out, make_geom(d0, d1, d2), n, as_stream(stream));
+  return check_launch("darc_center");
+}
+
+int darc_atlas_update(const float* images, const float* u, const float* mean, float* atlas, int n,
+                      int d0, int d1, int d2, void* stream) {
+  DARC_TRY(check_dims("darc_atlas_update", n, d0, d1, d2));
+  if (n < 1) return fail(DARC_EINVAL, "darc_atlas_update: n must be >= 1");
+  if (!images || !u || !atlas) return fail(DARC_EINVAL, "darc_atlas_update: NULL pointer");
+  launch_atlas(images, u, mean, atlas, make_geom(d0, d1, d2), n, as_stream(stream));
+  return check_launch("darc_atlas_update");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------- sweep
+
+namespace {
+
+struct SweepLayout {
+  int B;
+  size_t ckpt, uN, gU, gA, gB, gV, iw, fields, vtmp, uhat, sloss, total;
+};
+
+SweepLayout sweep_layout(const darc_state* st, const darc_params* p) {
+  SweepLayout L{};
+  const int n = st->n;
+  L.B = (p->batch <= 0 || p->batch > n) ? n : p->batch;
+  const size_t V = static_cast<size_t>(st->d0) * st->d1 * st->d2;
+  const size_t fb = static_cast<size_t>(L.B) * 3 * V * sizeof(float);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  L.ckpt = take(p->n_sq >= 2 ? static_cast<size_t>(p->n_sq - 1) * fb : 0);
+  L.uN = take(fb);
+  L.gU = take(fb);
+  L.gA = take(fb);
+  L.gB = take(fb);
+  L.gV = take(fb);
+  const bool lncc = p->metric == DARC_LNCC;
+  L.iw = take(lncc ? static_cast<size_t>(L.B) * V * sizeof(float) : 0);
+  L.fields = take(lncc ? static_cast<size_t>(L.B) * 4 * V * sizeof(float) : 0);
+  L.vtmp = take(p->smooth_sigma > 0.0f ? fb : 0);
+  L.uhat = take(st->u_hat ? 0 : static_cast<size_t>(n) * 3 * V * sizeof(float));
+  L.sloss = take(static_cast<size_t>(n) * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+int check_sweep(const darc_state* st, const darc_params* p) {
+  if (!st || !p) return fail(DARC_EINVAL, "darc_sweep: state and params must not be NULL");
+  DARC_TRY(check_dims("darc_sweep", st->n, st->d0, st->d1, st->d2));
+  if (st->n < 1) return fail(DARC_EINVAL, "darc_sweep: n must be >= 1");
+  if (!st->images || !st->v || !st->m || !st->s || !st->atlas)
+    return fail(DARC_EINVAL, "darc_sweep: images, v, m, s and atlas must not be NULL");
+  if (p->metric != DARC_MSE && p->metric != DARC_LNCC)
+    return fail(DARC_EINVAL, "darc_sweep: unknown metric %d", p->metric);
+  if (p->metric == DARC_LNCC) {
+    if (p->win < 1 || p->win % 2 == 0)
+      return fail(DARC_EINVAL, "darc_sweep: window %d must be odd and positive", p->win);
+    if (!lncc_window_supported(p->win))
+      return fail(DARC_EUNSUPPORTED, "darc_sweep: window %d not built (3, 5, 7, 9, 11)", p->win);
+    if (!(p->ncc_eps > 0.0f)) return fail(DARC_EINVAL, "darc_sweep: ncc_eps must be > 0");
+  }
+  if (!(p->lam >= 0.0f)) return fail(DARC_EINVAL, "darc_sweep: lam must be >= 0");
+  if (!(p->smooth_sigma >= 0.0f)) return fail(DARC_EINVAL, "darc_sweep: smooth_sigma must be >= 0");
+  if (p->smooth_sigma > 0.0f) {
+    const int r = gauss_radius(p->smooth_sigma);
+    if (r < 1 || r > 8)
+      return fail(DARC_EUNSUPPORTED, "darc_sweep: Gaussian radius %d not in 1..8", r);
+  }
+  if (p->n_sq < 1 || p->n_sq > 16) return fail(DARC_EINVAL, "darc_sweep: n_sq must be in 1..16");
+  if (p->k2 < 1) return fail(DARC_EINVAL, "darc_sweep: k2 must be >= 1");
+  if (!(p->beta1 >= 0.0 && p->beta1 < 1.0 && p->beta2 >= 0.0 && p->beta2 < 1.0))
+    return fail(DARC_EINVAL, "darc_sweep: betas must lie in [0, 1)");
+  if (!(p->adam_eps > 0.0f)) return fail(DARC_EINVAL, "darc_sweep: adam_eps must be > 0");
+  if (p->center_mode != DARC_CENTER_DISPLACEMENT && p->center_mode != DARC_CENTER_VELOCITY)
+    return fail(DARC_EINVAL, "darc_sweep: unknown center_mode %d", p->center_mode);
+  if (st->step < 0) return fail(DARC_EINVAL, "darc_sweep: step must be >= 0");
+  return DARC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t darc_sizeof_state(void) { return sizeof(darc_state); }
+size_t darc_sizeof_params(void) { return sizeof(darc_params); }
+
+size_t darc_sweep_ws_bytes(const darc_state* st, const darc_params* p) {
+  if (check_sweep(st, p) != DARC_OK) return 0;
+  return sweep_layout(st, p).total;
+}
+
+int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, size_t ws_bytes,
+               void* stream) {
+  DARC_TRY(check_sweep(st, p));
+  if (!losses) return fail(DARC_EINVAL, "darc_sweep: losses must not be NULL");
+  const SweepLayout L = sweep_layout(st, p);
+  DARC_TRY(check_ws("darc_sweep", ws, ws_bytes, L.total));
+  hipStream_t s = as_stream(stream);
+  const Geom g = make_geom(st->d0, st->d1, st->d2);
+  const int n = st->n, k2 = p->k2, N = p->n_sq, B = L.B;
+  const size_t fsv = 3 * static_cast<size_t>(g.V);
+  char* w = static_cast<char*>(ws);
+  float* ckpt = N >= 2 ? reinterpret_cast<float*>(w + L.ckpt) : nullptr;
+  float* uN = reinterpret_cast<float*>(w + L.uN);
+  float* gU = reinterpret_cast<float*>(w + L.gU);
+  float* gA = reinterpret_cast<float*>(w + L.gA);
+  float* gB = reinterpret_cast<float*>(w + L.gB);
+  float* gV = reinterpret_cast<float*>(w + L.gV);
+  float* iw = reinterpret_cast<float*>(w + L.iw);
+  float* fields = reinterpret_cast<float*>(w + L.fields);
+  float* vtmp = reinterpret_cast<float*>(w + L.vtmp);
+  float* uh = st->u_hat ? st->u_hat : reinterpret_cast<float*>(w + L.uhat);
+  double* sloss = reinterpret_cast<double*>(w + L.sloss);
+  const RegW rw = make_regw(g, 3, p->lam);
+  const bool lncc = p->metric == DARC_LNCC;
+  const bool smooth = p->smooth_sigma > 0.0f;
+
+  launch_fill_f64(losses, static_cast<long long>(n) * k2 + 1, 0.0, s);
+  long long step = st->step;
+  if (p->reinit_v) {
+    const long long cnt = static_cast<long long>(n) * fsv;
+    launch_fill_f32(st->v, cnt, 0.0f, s);
+    launch_fill_f32(st->m, cnt, 0.0f, s);
+    launch_fill_f32(st->s, cnt, 0.0f, s);
+    step = 0;
+  }
+
+  // step 1: K2 gradient steps per subject against the fixed atlas; subjects
+  // are independent, so a launch covers a batch of them.
+  for (int b0 = 0; b0 < n; b0 += B) {
+    const int nb = n - b0 < B ? n - b0 : B;
+    float* vb = st->v + b0 * fsv;
+    float* mb = st->m + b0 * fsv;
+    float* sb = st->s + b0 * fsv;
+    const float* ib = st->images + static_cast<size_t>(b0) * g.V;
+    for (int k = 0; k < k2; ++k) {
+      double* lslot = losses + static_cast<size_t>(b0) * k2 + k;
+      run_exp_fwd(vb, uN, ckpt, nullptr, g, nb, N, s);
+      if (!lncc) {
+        launch_mse_fused(ib, st->atlas, uN, gU, lslot, k2, rw, g, nb, s);
+      } else {
+        launch_warp(ib, uN, iw, g, nb, s);
+        launch_lncc_fwd(iw, st->atlas, fields, lslot, k2, p->win, p->ncc_eps, g, nb, s);
+        launch_lncc_bwd_fused(fields, iw, st->atlas, ib, uN, gU, lslot, k2, rw, p->win, g, nb, s);
+      }
+      run_exp_bwd(vb, ckpt, gU, gV, gA, gB, g, nb, N, s);
+      const long long cnt = static_cast<long long>(nb) * fsv;
+      if (smooth) {
+        launch_adam(vb, vtmp, mb, sb, gV, cnt, step + k + 1, p->lr, p->beta1, p->beta2,
+                    p->adam_eps, s);
+        launch_gauss(vtmp, vb, p->smooth_sigma, g, nb * 3, s);
+      } else {
+        launch_adam(vb, vb, mb, sb, gV, cnt, step + k + 1, p->lr, p->beta1, p->beta2, p->adam_eps,
+                    s);
+      }
+    }
+  }
+
+  // step 2: u_i = Exp(v_i), centrality activation
+  if (p->center_mode == DARC_CENTER_VELOCITY) launch_center(st->v, nullptr, g, n, s);
+  for (int b0 = 0; b0 < n; b0 += B) {
+    const int nb = n - b0 < B ? n - b0 : B;
+    run_exp_fwd(st->v + b0 * fsv, uh + b0 * fsv, nullptr, gA, g, nb, N, s);
+  }
+  if (p->center_mode == DARC_CENTER_DISPLACEMENT) launch_center(uh, nullptr, g, n, s);
+
+  // step 3: atlas = mean of the warped subjects
+  launch_atlas(st->images, uh, nullptr, st->atlas, g, n, s);
+
+  // group loss at the new atlas
+  launch_fill_f64(sloss, n, 0.0, s);
+  for (int b0 = 0; b0 < n; b0 += B) {
+    const int nb = n - b0 < B ? n - b0 : B;
+    const float* ib = st->images + static_cast<size_t>(b0) * g.V;
+    if (!lncc) {
+      launch_mse_fused(ib, st->atlas, uh + b0 * fsv, nullptr, sloss + b0, 1, rw, g, nb, s);
+    } else {
+      launch_warp(ib, uh + b0 * fsv, iw, g, nb, s);
+      launch_lncc_fwd(iw, st->atlas, nullptr, sloss + b0, 1, p->win, p->ncc_eps, g, nb, s);
+      if (rw.on) launch_diffusion(uh + b0 * fsv, nullptr, sloss + b0, 1, rw, g, nb, 3, s);
+    }
+  }
+  launch_sum_f64(sloss, n, 1.0 / n, losses + static_cast<size_t>(n) * k2, s);
+  st->step = step + k2;
+  return check_launch("darc_sweep");
+}
+
+// ------------------------------------------------------------- timing API
+
+int darc_profile_enable(int on) {
+  g_prof_on = on != 0;
+  return ok();
+}
+
+int darc_profile_reset(void) {
+  for (const ProfRec& r : g_prof_recs) {
+    if (r.a) g_event_pool.push_back(r.a);
+    if (r.b) g_event_pool.push_back(r.b);
+  }
+  g_prof_recs.clear();
+  for (int i = 0; i < KC_NUM; ++i) {
+    g_prof_counts[i] = 0;
+    g_prof_ms[i] = 0.0;
+  }
+  return ok();
+}
+
+int darc_profile_num_classes(void) { return KC_NUM; }
+
+const char* darc_profile_name(int cls) {
+  if (cls < 0 || cls >= KC_NUM) return "";
+  return kClassNames[cls];
+}
+
+int darc_profile_collect(long long* counts, double* ms, int max_classes) {
+  for (const ProfRec& r : g_prof_recs) {
+    if (r.a && r.b) {
+      if (hipEventSynchronize(r.b) != hipSuccess) return check_launch("darc_profile_collect");
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        g_prof_counts[r.cls] += 1;
+        g_prof_ms[r.cls] += t;
+      }
+    }
+    if (r.a) g_event_pool.push_back(r.a);
+    if (r.b) g_event_pool.push_back(r.b);
+  }
+  g_prof_recs.clear();
+  const int m = max_classes < KC_NUM ? max_classes : KC_NUM;
+  for (int i = 0; i < m; ++i) {
+    if (counts) counts[i] = g_prof_counts[i];
+    if (ms) ms[i] = g_prof_ms[i];
+  }
+  return ok();
+}
+
+}  // extern "C"

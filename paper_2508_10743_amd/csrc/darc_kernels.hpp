@@ -1,0 +1,82 @@
+// Internal launchers of libdarc.  Every launcher enqueues on `st` and checks
+// nothing: argument validation happens in the C ABI layer.  `n` is the number
+// of subjects handled by one launch; array strides between subjects are 3V
+// (fields) and V (images) unless stated.
+#pragma once
+
+#include "darc_common.hpp"
+
+namespace darc {
+
+RegW make_regw(const Geom& g, int ncomp, float lam);
+
+// --- scaling and squaring -------------------------------------------------
+void launch_exp_step(const float* src, float* dst, const Geom& g, int n, bool first, float scale,
+                     hipStream_t st);
+void launch_exp_step_bwd(const float* ut, const float* gin, float* gout, const Geom& g, int n,
+                         bool first, float scale, float oscale, hipStream_t st);
+// Full Exp(v): ckpt ([n_sq-1][n][3][V]) or tmp ([n][3][V]) must be given when n_sq >= 2.
+void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, const Geom& g, int n, int n_sq,
+                 hipStream_t st);
+// Full adjoint; tmp_a, tmp_b are [n][3][V]; g_v must not alias g_u.
+void run_exp_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, float* tmp_a,
+                 float* tmp_b, const Geom& g, int n, int n_sq, hipStream_t st);
+
+// --- warp -----------------------------------------------------------------
+void launch_warp(const float* img, const float* u, float* out, const Geom& g, int n,
+                 hipStream_t st);
+void launch_warp_bwd(const float* img, const float* u, const float* gout, float* gu, const Geom& g,
+                     int n, hipStream_t st);
+
+// --- dissimilarities and regulariser --------------------------------------
+// MSE on given warped images: loss[i * loss_stride] += D_i; gw may be null.
+void launch_mse(const float* w, const float* atlas, double* loss, int loss_stride, float* gw,
+                const Geom& g, int n, hipStream_t st);
+// Warp + MSE + (optional) diffusion regulariser, fused.  With gu non-null it
+// also writes gu = dL/du (overwrite); loss[i * loss_stride] += D_i + lam R(u_i).
+void launch_mse_fused(const float* img, const float* atlas, const float* u, float* gu,
+                      double* loss, int loss_stride, const RegW& rw, const Geom& g, int n,
+                      hipStream_t st);
+// Diffusion regulariser of an ncomp-component field: out += lam dR/din
+// (when out is non-null) and loss[i * loss_stride] += lam R (when non-null).
+void launch_diffusion(const float* in, float* out, double* loss, int loss_stride, const RegW& rw,
+                      const Geom& g, int n, int ncomp, hipStream_t st);
+
+// LNCC forward.  fields ([n][4][V], may be null) receives alpha, alpha*Jbar,
+// beta, beta*Ibar; loss[i * loss_stride] += -(1/V) sum cc.  Returns false when
+// the window size is not built.
+bool launch_lncc_fwd(const float* w, const float* atlas, float* fields, double* loss,
+                     int loss_stride, int win, double eps, const Geom& g, int n, hipStream_t st);
+// LNCC adjoint: gw = dD/dw from the fields (gw [n][V]).
+bool launch_lncc_bwd(const float* fields, const float* w, const float* atlas, float* gw, int win,
+                     const Geom& g, int n, hipStream_t st);
+// LNCC adjoint fused with the warp adjoint and the regulariser: gu = dL/du
+// (overwrite); loss[i * loss_stride] += lam R(u_i).
+bool launch_lncc_bwd_fused(const float* fields, const float* w, const float* atlas,
+                           const float* img, const float* u, float* gu, double* loss,
+                           int loss_stride, const RegW& rw, int win, const Geom& g, int n,
+                           hipStream_t st);
+
+bool lncc_window_supported(int win);
+int gauss_radius(float sigma);
+
+// Separable Gaussian of `nchan` volumes (out != in).  Returns false when the
+// radius int(3 sigma + 0.5) is outside 1..8.
+bool launch_gauss(const float* in, float* out, float sigma, const Geom& g, int nchan,
+                  hipStream_t st);
+
+// --- optimiser, centring, atlas -------------------------------------------
+void launch_adam(const float* v_in, float* v_out, float* m, float* s, const float* g,
+                 long long count, long long t, float lr, double b1, double b2, float eps,
+                 hipStream_t st);
+void launch_center(float* u, float* mean_out, const Geom& g, int n, hipStream_t st);
+void launch_atlas(const float* images, const float* u, const float* mean, float* atlas,
+                  const Geom& g, int n, hipStream_t st);
+
+// --- small helpers --------------------------------------------------------
+void launch_fill_f32(float* p, long long count, float value, hipStream_t st);
+void launch_fill_f64(double* p, long long count, double value, hipStream_t st);
+// out[0] = scale * sum_{i < n} in[i]
+void launch_sum_f64(const double* in, int n, double scale, double* out, hipStream_t st);
+
+}  // namespace darc

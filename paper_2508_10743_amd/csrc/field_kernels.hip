@@ -1,0 +1,542 @@
+// Voxel-parallel kernels of libdarc: scaling and squaring and its adjoint,
+// warping and its adjoint, MSE, the diffusion regulariser, Adam, the
+// centrality activation and the mean atlas.  One thread per voxel, 256-thread
+// blocks, blocks remapped so that each XCD walks a contiguous range of voxels
+// (the gathers of neighbouring voxels then share that XCD's L2).
+#include "darc_kernels.hpp"
+
+namespace darc {
+
+namespace {
+
+struct VoxelBlock {
+  uint32_t s;  // subject within the launch
+  int lin;     // voxel index, may be >= V in the last block
+};
+
+__device__ __forceinline__ VoxelBlock voxel_block(uint32_t nbx, uint32_t total) {
+  const uint32_t b = xcd_remap(blockIdx.x, total);
+  const uint32_t s = b / nbx;
+  VoxelBlock r;
+  r.s = s;
+  r.lin = static_cast<int>((b - s * nbx) * kBlock + threadIdx.x);
+  return r;
+}
+
+// ------------------------------------------------------------------ Exp(v)
+
+// One squaring step u_{t+1}(x) = u_t(x) + u_t(x + u_t(x)), border sampling.
+// FIRST: src is v and u_0 = scale * v (scale = 2^-N, exact).
+template <bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_exp_step(const float* __restrict__ src,
+                                                     float* __restrict__ dst, Geom g, float scale,
+                                                     uint32_t nbx, uint32_t total) {
+  const VoxelBlock vb = voxel_block(nbx, total);
+  if (vb.lin >= g.V) return;
+  const size_t off = static_cast<size_t>(vb.s) * 3 * g.V;
+  const float* f = src + off;
+  float* o = dst + off;
+  const int lin = vb.lin;
+  int x0, x1, x2;
+  voxel_coords(g, lin, x0, x1, x2);
+  float u0 = f[lin], u1 = f[g.V + lin], u2 = f[2 * g.V + lin];
+  if (FIRST) {
+    u0 *= scale;
+    u1 *= scale;
+    u2 *= scale;
+  }
+  const BorderCell bc = border_cell(g, x0, x1, x2, u0, u1, u2);
+  float c[8];
+  corners_border(f, g, bc.base, c);
+  float s0 = tri_value(c, bc.t0, bc.t1, bc.t2);
+  corners_border(f + g.V, g, bc.base, c);
+  float s1 = tri_value(c, bc.t0, bc.t1, bc.t2);
+  corners_border(f + 2 * g.V, g, bc.base, c);
+  float s2 = tri_value(c, bc.t0, bc.t1, bc.t2);
+  if (FIRST) {
+    s0 *= scale;
+    s1 *= scale;
+    s2 *= scale;
+  }
+  o[lin] = u0 + s0;
+  o[g.V + lin] = u1 + s1;
+  o[2 * g.V + lin] = u2 + s2;
+}
+
+// Adjoint of one squaring step, accumulated into gout (zeroed beforehand):
+//   gout(y) += oscale * [g(y) + J_t(y)^T g(y)]           at y = x
+//   gout(corner_k(x)) += oscale * w_k(x) g(x)             (trilinear scatter)
+template <bool FIRST>
+__global__ __launch_bounds__(kBlock) void k_exp_step_bwd(const float* __restrict__ ut,
+                                                         const float* __restrict__ gin,
+                                                         float* __restrict__ gout, Geom g,
+                                                         float scale, float oscale, uint32_t nbx,
+                                                         uint32_t total) {
+  const VoxelBlock vb = voxel_block(nbx, total);
+  if (vb.lin >= g.V) return;
+  const size_t off = static_cast<size_t>(vb.s) * 3 * g.V;
+  const float* f = ut + off;
+  const float* gi = gin + off;
+  float* go = gout + off;
+  const int lin = vb.lin;
+  int x0, x1, x2;
+  voxel_coords(g, lin, x0, x1, x2);
+  float u0 = f[lin], u1 = f[g.V + lin], u2 = f[2 * g.V + lin];
+  if (FIRST) {
+    u0 *= scale;
+    u1 *= scale;
+    u2 *= scale;
+  }
+  const BorderCell bc = border_cell(g, x0, x1, x2, u0, u1, u2);
+  const float g0 = gi[lin], g1 = gi[g.V + lin], g2 = gi[2 * g.V + lin];
+  const float gc[3] = {g0, g1, g2};
+  // J^T g: sum_c dS_c/dp_d * g_c
+  float jt0 = 0.0f, jt1 = 0.0f, jt2 = 0.0f;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float cv[8];
+    corners_border(f + c * g.V, g, bc.base, cv);
+    const Tri t = tri_eval(cv, bc.t0, bc.t1, bc.t2);
+    jt0 += t.d0 * gc[c];
+    jt1 += t.d1 * gc[c];
+    jt2 += t.d2 * gc[c];
+  }
+  const float js = FIRST ? scale : 1.0f;
+  jt0 = bc.k0 ? 0.0f : jt0 * js;
+  jt1 = bc.k1 ? 0.0f : jt1 * js;
+  jt2 = bc.k2 ? 0.0f : jt2 * js;
+  unsafeAtomicAdd(go + lin, (g0 + jt0) * oscale);
+  unsafeAtomicAdd(go + g.V + lin, (g1 + jt1) * oscale);
+  unsafeAtomicAdd(go + 2 * g.V + lin, (g2 + jt2) * oscale);
+  // scatter of g through the trilinear weights
+  const float w0[2] = {1.0f - bc.t0, bc.t0};
+  const float w1[2] = {1.0f - bc.t1, bc.t1};
+  const float w2[2] = {1.0f - bc.t2, bc.t2};
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const float w = w0[a] * w1[b] * w2[e] * oscale;
+        const int idx = bc.base + a * g.plane + b * g.d2 + e;
+        unsafeAtomicAdd(go + idx, w * g0);
+        unsafeAtomicAdd(go + g.V + idx, w * g1);
+        unsafeAtomicAdd(go + 2 * g.V + idx, w * g2);
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------------- warp
+
+__global__ __launch_bounds__(kBlock) void k_warp(const float* __restrict__ img,
+                                                 const float* __restrict__ u,
+                                                 float* __restrict__ out, Geom g, uint32_t nbx,
+                                                 uint32_t total) {
+  const VoxelBlock vb = voxel_block(nbx, total);
+  if (vb.lin >= g.V) return;
+  const int lin = vb.lin;
+  const float* I = img + static_cast<size_t>(vb.s) * g.V;
+  const float* f = u + static_cast<size_t>(vb.s) * 3 * g.V;
+  int x0, x1, x2;
+  voxel_coords(g, lin, x0, x1, x2);
+  out[static_cast<size_t>(vb.s) * g.V + lin] =
+      sample_zero_value(I, g, x0, x1, x2, f[lin], f[g.V + lin], f[2 * g.V + lin]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_warp_bwd(const float* __restrict__ img,
+                                                     const float* __restrict__ u,
+                                                     const float* __restrict__ gout,
+                                                     float* __restrict__ gu, Geom g, uint32_t nbx,
+                                                     uint32_t total) {
+  const VoxelBlock vb = voxel_block(nbx, total);
+  if (vb.lin >= g.V) return;
+  const int lin = vb.lin;
+  const float* I = img + static_cast<size_t>(vb.s) * g.V;
+  const size_t off = static_cast<size_t>(vb.s) * 3 * g.V;
+  const float* f = u + off;
+  float* o = gu + off;
+  int x0, x1, x2;
+  voxel_coords(g, lin, x0, x1, x2);
+  const Tri t = sample_zero(I, g, x0, x1, x2, f[lin], f[g.V + lin], f[2 * g.V + lin]);
+  const float go = gout[static_cast<size_t>(vb.s) * g.V + lin];
+  o[lin] += go * t.d0;
+  o[g.V + lin] += go * t.d1;
+  o[2 * g.V + lin] += go * t.d2;
+}
+
+// -------------------------------------------------------------------- MSE
+
+__global__ __launch_bounds__(kBlock) void k_mse(const float* __restrict__ w,
+                                                const float* __restrict__ atlas,
+                                                double* __restrict__ loss, int loss_stride,
+                                                float* __restrict__ gw, Geom g, double inv_v,
+                                                uint32_t nbx, uint32_t total) {
+  __shared__ double red[kBlock / 64];
+  const VoxelBlock vb = voxel_block(nbx, total);
+  double acc = 0.0;
+  if (vb.lin < g.V) {
+    const size_t idx = static_cast<size_t>(vb.s) * g.V + vb.lin;
+    const double diff = static_cast<double>(w[idx]) - static_cast<double>(atlas[vb.lin]);
+    acc = diff * diff;
+    if (gw) gw[idx] = static_cast<float>(2.0 * inv_v * diff);
+  }
+  const double tot = block_sum<kBlock>(acc, red);
+  if (threadIdx.x == 0) atomicAdd(loss + static_cast<size_t>(vb.s) * loss_stride, tot * inv_v);
+}
+
+// Warp + MSE + diffusion regulariser (+ their adjoints when GRAD).
+template <bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_mse_fused(const float* __restrict__ img,
+                                                      const float* __restrict__ atlas,
+                                                      const float* __restrict__ u,
+                                                      float* __restrict__ gu,
+                                                      double* __restrict__ loss, int loss_stride,
+                                                      RegW rw, Geom g, double inv_v, uint32_t nbx,
+                                                      uint32_t total) {
+  __shared__ double red[kBlock / 64];
+  const VoxelBlock vb = voxel_block(nbx, total);
+  double acc = 0.0;
+  if (vb.lin < g.V) {
+    const int lin = vb.lin;
+    const float* I = img + static_cast<size_t>(vb.s) * g.V;
+    const size_t off = static_cast<size_t>(vb.s) * 3 * g.V;
+    const float* f = u + off;
+    int x0, x1, x2;
+    voxel_coords(g, lin, x0, x1, x2);
+    const Tri t = sample_zero(I, g, x0, x1, x2, f[lin], f[g.V + lin], f[2 * g.V + lin]);
+    const double diff = static_cast<double>(t.v) - static_cast<double>(atlas[lin]);
+    acc = diff * diff * inv_v;
+    float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f;
+    if (rw.on) {
+      double racc = 0.0;
+      r0 = reg_at(f, g, lin, x0, x1, x2, rw, racc);
+      r1 = reg_at(f + g.V, g, lin, x0, x1, x2, rw, racc);
+      r2 = reg_at(f + 2 * g.V, g, lin, x0, x1, x2, rw, racc);
+      acc += rw.lam * racc;
+    }
+    if (GRAD) {
+      const float gw = static_cast<float>(2.0 * inv_v * diff);
+      float* o = gu + off;
+      o[lin] = gw * t.d0 + r0;
+      o[g.V + lin] = gw * t.d1 + r1;
+      o[2 * g.V + lin] = gw * t.d2 + r2;
+    }
+  }
+  const double tot = block_sum<kBlock>(acc, red);
+  if (threadIdx.x == 0) atomicAdd(loss + static_cast<size_t>(vb.s) * loss_stride, tot);
+}
+
+// Diffusion regulariser of an ncomp-component field (one launch covers the
+// ncomp components of each subject, blocks over voxels).
+__global__ __launch_bounds__(kBlock) void k_diffusion(const float* __restrict__ in,
+                                                      float* __restrict__ out,
+                                                      double* __restrict__ loss, int loss_stride,
+                                                      RegW rw, Geom g, int ncomp, uint32_t nbx,
+                                                      uint32_t total) {
+  __shared__ double red[kBlock / 64];
+  const VoxelBlock vb = voxel_block(nbx, total);
+  double racc = 0.0;
+  if (vb.lin < g.V) {
+    const int lin = vb.lin;
+    int x0, x1, x2;
+    voxel_coords(g, lin, x0, x1, x2);
+    const size_t off = static_cast<size_t>(vb.s) * ncomp * g.V;
+    for (int c = 0; c < ncomp; ++c) {
+      const float gr = reg_at(in + off + static_cast<size_t>(c) * g.V, g, lin, x0, x1, x2, rw, racc);
+      if (out) out[off + static_cast<size_t>(c) * g.V + lin] += gr;
+    }
+  }
+  if (loss) {
+    const double tot = block_sum<kBlock>(racc, red);
+    if (threadIdx.x == 0) atomicAdd(loss + static_cast<size_t>(vb.s) * loss_stride, rw.lam * tot);
+  }
+}
+
+// ------------------------------------------------------------------- Adam
+
+__global__ __launch_bounds__(kBlock) void k_adam(const float* __restrict__ v_in,
+                                                 float* __restrict__ v_out, float* __restrict__ m,
+                                                 float* __restrict__ s,
+                                                 const float* __restrict__ g, long long count,
+                                                 float lr, float b1, float omb1, float b2,
+                                                 float omb2, float bc1, float bc2, float eps) {
+  const long long stride = static_cast<long long>(gridDim.x) * kBlock;
+  for (long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x; i < count;
+       i += stride) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float si = b2 * s[i] + omb2 * gi * gi;
+    m[i] = mi;
+    s[i] = si;
+    v_out[i] = v_in[i] - lr * (mi / bc1) / (sqrtf(si / bc2) + eps);
+  }
+}
+
+// ---------------------------------------------------------------- centring
+
+// mean(e) = (1/n) sum_i u_i(e) over the 3V entries e; u_i <- u_i - mean.
+__global__ __launch_bounds__(kBlock) void k_center(float* __restrict__ u,
+                                                   float* __restrict__ mean_out, int n,
+                                                   long long fs) {
+  const long long e = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (e >= fs) return;
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) acc += static_cast<double>(u[i * fs + e]);
+  const double mean = acc / n;
+  if (mean_out) mean_out[e] = static_cast<float>(mean);
+  for (int i = 0; i < n; ++i) u[i * fs + e] = static_cast<float>(static_cast<double>(u[i * fs + e]) - mean);
+}
+
+// ------------------------------------------------------------------- atlas
+
+__global__ __launch_bounds__(kBlock) void k_atlas(const float* __restrict__ images,
+                                                  const float* __restrict__ u,
+                                                  const float* __restrict__ mean,
+                                                  float* __restrict__ atlas, Geom g, int n,
+                                                  uint32_t nbx, uint32_t total) {
+  const VoxelBlock vb = voxel_block(nbx, total);
+  if (vb.lin >= g.V) return;
+  const int lin = vb.lin;
+  int x0, x1, x2;
+  voxel_coords(g, lin, x0, x1, x2);
+  float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f;
+  if (mean) {
+    m0 = mean[lin];
+    m1 = mean[g.V + lin];
+    m2 = mean[2 * g.V + lin];
+  }
+  double acc = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const float* f = u + static_cast<size_t>(i) * 3 * g.V;
+    const float* I = images + static_cast<size_t>(i) * g.V;
+    acc += static_cast<double>(sample_zero_value(I, g, x0, x1, x2, f[lin] - m0, f[g.V + lin] - m1,
+                                                 f[2 * g.V + lin] - m2));
+  }
+  atlas[lin] = static_cast<float>(acc / n);
+}
+
+// ---------------------------------------------------------------- helpers
+
+__global__ __launch_bounds__(kBlock) void k_fill_f32(float* __restrict__ p, long long count,
+                                                     float value) {
+  const long long stride = static_cast<long long>(gridDim.x) * kBlock;
+  for (long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x; i < count;
+       i += stride)
+    p[i] = value;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill_f64(double* __restrict__ p, long long count,
+                                                     double value) {
+  const long long stride = static_cast<long long>(gridDim.x) * kBlock;
+  for (long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x; i < count;
+       i += stride)
+    p[i] = value;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sum_f64(const double* __restrict__ in, int n,
+                                                    double scale, double* __restrict__ out) {
+  __shared__ double red[kBlock / 64];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += kBlock) acc += in[i];
+  const double tot = block_sum<kBlock>(acc, red);
+  if (threadIdx.x == 0) out[0] = scale * tot;
+}
+
+inline uint32_t grid_stride_blocks(long long count) {
+  const long long b = (count + kBlock - 1) / kBlock;
+  return static_cast<uint32_t>(b < 65536 ? (b < 1 ? 1 : b) : 65536);
+}
+
+}  // namespace
+
+// ==========================================================================
+// launchers
+
+RegW make_regw(const Geom& g, int ncomp, float lam) {
+  RegW r;
+  const int ds[3] = {g.d0, g.d1, g.d2};
+  for (int d = 0; d < 3; ++d) {
+    const double cnt = static_cast<double>(ncomp) * (ds[d] - 1) * (static_cast<double>(g.V) / ds[d]);
+    r.w[d] = 1.0 / (3.0 * cnt);
+    r.g[d] = static_cast<float>(static_cast<double>(lam) * 2.0 * r.w[d]);
+  }
+  r.lam = lam;
+  r.on = lam != 0.0f;
+  return r;
+}
+
+void launch_exp_step(const float* src, float* dst, const Geom& g, int n, bool first, float scale,
+                     hipStream_t st) {
+  const uint32_t nbx = blocks_for(g.V, kBlock), total = nbx * n;
+  prof_begin(st, KC_EXP_FWD);
+  if (first)
+    hipLaunchKernelGGL((k_exp_step<true>), dim3(total), dim3(kBlock), 0, st, src, dst, g, scale,
+                       nbx, total);
+  else
+    hipLaunchKernelGGL((k_exp_step<false>), dim3(total), dim3(kBlock), 0, st, src, dst, g, scale,
+                       nbx, total);
+  prof_end(st, KC_EXP_FWD);
+}
+
+void launch_exp_step_bwd(const float* ut, const float* gin, float* gout, const Geom& g, int n,
+                         bool first, float scale, float oscale, hipStream_t st) {
+  const uint32_t nbx = blocks_for(g.V, kBlock), total = nbx * n;
+  prof_begin(st, KC_EXP_BWD);
+  if (first)
+    hipLaunchKernelGGL((k_exp_step_bwd<true>), dim3(total), dim3(kBlock), 0, st, ut, gin, gout, g,
+                       scale, oscale, nbx, total);
+  else
+    hipLaunchKernelGGL((k_exp_step_bwd<false>), dim3(total), dim3(kBlock), 0, st, ut, gin, gout,
+                       g, scale, oscale, nbx, total);
+  prof_end(st, KC_EXP_BWD);
+}
+
+void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, const Geom& g, int n, int n_sq,
+                 hipStream_t st) {
+  const size_t fs = static_cast<size_t>(n) * 3 * g.V;
+  if (n_sq == 0) {
+    prof_begin(st, KC_MISC);
+    hipMemcpyAsync(u, v, fs * sizeof(float), hipMemcpyDeviceToDevice, st);
+    prof_end(st, KC_MISC);
+    return;
+  }
+  const float scale = ldexpf(1.0f, -n_sq);
+  const float* src = v;
+  for (int t = 0; t < n_sq; ++t) {
+    float* dst;
+    if (t == n_sq - 1)
+      dst = u;
+    else if (ckpt)
+      dst = ckpt + static_cast<size_t>(t) * fs;  // slot t holds u_{t+1}
+    else
+      dst = ((n_sq - 1 - t) % 2 == 0) ? u : tmp;  // ping-pong ending in u
+    launch_exp_step(src, dst, g, n, t == 0, scale, st);
+    src = dst;
+  }
+}
+
+void run_exp_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, float* tmp_a,
+                 float* tmp_b, const Geom& g, int n, int n_sq, hipStream_t st) {
+  const size_t fs = static_cast<size_t>(n) * 3 * g.V;
+  if (n_sq == 0) {
+    prof_begin(st, KC_MISC);
+    hipMemcpyAsync(g_v, g_u, fs * sizeof(float), hipMemcpyDeviceToDevice, st);
+    prof_end(st, KC_MISC);
+    return;
+  }
+  const float scale = ldexpf(1.0f, -n_sq);
+  const float* gin = g_u;
+  for (int t = n_sq - 1; t >= 0; --t) {
+    float* gout = (t == 0) ? g_v : (((n_sq - 1 - t) % 2 == 0) ? tmp_a : tmp_b);
+    const float* ut = (t == 0) ? v : ckpt + static_cast<size_t>(t - 1) * fs;
+    launch_fill_f32(gout, static_cast<long long>(fs), 0.0f, st);
+    launch_exp_step_bwd(ut, gin, gout, g, n, t == 0, scale, t == 0 ? scale : 1.0f, st);
+    gin = gout;
+  }
+}
+
+void launch_warp(const float* img, const float* u, float* out, const Geom& g, int n,
+                 hipStream_t st) {
+  const uint32_t nbx = blocks_for(g.V, kBlock), total = nbx * n;
+  prof_begin(st, KC_WARP);
+  hipLaunchKernelGGL(k_warp, dim3(total), dim3(kBlock), 0, st, img, u, out, g, nbx, total);
+  prof_end(st, KC_WARP);
+}
+
+void launch_warp_bwd(const float* img, const float* u, const float* gout, float* gu, const Geom& g,
+                     int n, hipStream_t st) {
+  const uint32_t nbx = blocks_for(g.V, kBlock), total = nbx * n;
+  prof_begin(st, KC_WARP_BWD);
+  hipLaunchKernelGGL(k_warp_bwd, dim3(total), dim3(kBlock), 0, st, img, u, gout, gu, g, nbx,
+                     total);
+  prof_end(st, KC_WARP_BWD);
+}
+
+void launch_mse(const float* w, const float* atlas, double* loss, int loss_stride, float* gw,
+                const Geom& g, int n, hipStream_t st) {
+  const uint32_t nbx = blocks_for(g.V, kBlock), total = nbx * n;
+  prof_begin(st, KC_MSE);
+  hipLaunchKernelGGL(k_mse, dim3(total), dim3(kBlock), 0, st, w, atlas, loss, loss_stride, gw, g,
+                     1.0 / g.V, nbx, total);
+  prof_end(st, KC_MSE);
+}
+
+void launch_mse_fused(const float* img, const float* atlas, const float* u, float* gu,
+                      double* loss, int loss_stride, const RegW& rw, const Geom& g, int n,
+                      hipStream_t st) {
+  const uint32_t nbx = blocks_for(g.V, kBlock), total = nbx * n;
+  prof_begin(st, KC_MSE);
+  if (gu)
+    hipLaunchKernelGGL((k_mse_fused<true>), dim3(total), dim3(kBlock), 0, st, img, atlas, u, gu,
+                       loss, loss_stride, rw, g, 1.0 / g.V, nbx, total);
+  else
+    hipLaunchKernelGGL((k_mse_fused<false>), dim3(total), dim3(kBlock), 0, st, img, atlas, u, gu,
+                       loss, loss_stride, rw, g, 1.0 / g.V, nbx, total);
+  prof_end(st, KC_MSE);
+}
+
+void launch_diffusion(const float* in, float* out, double* loss, int loss_stride, const RegW& rw,
+                      const Geom& g, int n, int ncomp, hipStream_t st) {
+  const uint32_t nbx = blocks_for(g.V, kBlock), total = nbx * n;
+  prof_begin(st, KC_DIFFUSION);
+  hipLaunchKernelGGL(k_diffusion, dim3(total), dim3(kBlock), 0, st, in, out, loss, loss_stride, rw,
+                     g, ncomp, nbx, total);
+  prof_end(st, KC_DIFFUSION);
+}
+
+void launch_adam(const float* v_in, float* v_out, float* m, float* s, const float* g,
+                 long long count, long long t, float lr, double b1, double b2, float eps,
+                 hipStream_t st) {
+  // coefficients formed in FP64 and rounded once
+  const double bc1 = 1.0 - std::pow(b1, static_cast<double>(t));
+  const double bc2 = 1.0 - std::pow(b2, static_cast<double>(t));
+  prof_begin(st, KC_ADAM);
+  hipLaunchKernelGGL(k_adam, dim3(grid_stride_blocks(count)), dim3(kBlock), 0, st, v_in, v_out, m,
+                     s, g, count, lr, static_cast<float>(b1), static_cast<float>(1.0 - b1),
+                     static_cast<float>(b2), static_cast<float>(1.0 - b2), static_cast<float>(bc1),
+                     static_cast<float>(bc2), eps);
+  prof_end(st, KC_ADAM);
+}
+
+void launch_center(float* u, float* mean_out, const Geom& g, int n, hipStream_t st) {
+  const long long fs = 3ll * g.V;
+  prof_begin(st, KC_CENTER);
+  hipLaunchKernelGGL(k_center, dim3(blocks_for(fs, kBlock)), dim3(kBlock), 0, st, u, mean_out, n,
+                     fs);
+  prof_end(st, KC_CENTER);
+}
+
+void launch_atlas(const float* images, const float* u, const float* mean, float* atlas,
+                  const Geom& g, int n, hipStream_t st) {
+  const uint32_t nbx = blocks_for(g.V, kBlock);
+  prof_begin(st, KC_ATLAS);
+  hipLaunchKernelGGL(k_atlas, dim3(nbx), dim3(kBlock), 0, st, images, u, mean, atlas, g, n, nbx,
+                     nbx);
+  prof_end(st, KC_ATLAS);
+}
+
+void launch_fill_f32(float* p, long long count, float value, hipStream_t st) {
+  if (count <= 0) return;
+  prof_begin(st, KC_FILL);
+  hipLaunchKernelGGL(k_fill_f32, dim3(grid_stride_blocks(count)), dim3(kBlock), 0, st, p, count,
+                     value);
+  prof_end(st, KC_FILL);
+}
+
+void launch_fill_f64(double* p, long long count, double value, hipStream_t st) {
+  if (count <= 0) return;
+  prof_begin(st, KC_FILL);
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_stride_blocks(count)), dim3(kBlock), 0, st, p, count,
+                     value);
+  prof_end(st, KC_FILL);
+}
+
+void launch_sum_f64(const double* in, int n, double scale, double* out, hipStream_t st) {
+  prof_begin(st, KC_MISC);
+  hipLaunchKernelGGL(k_sum_f64, dim3(1), dim3(kBlock), 0, st, in, n, scale, out);
+  prof_end(st, KC_MISC);
+}
+
+}  // namespace darc

@@ -1,0 +1,464 @@
+// Window kernels of libdarc: the local NCC statistics and their adjoint
+// (win^3 box sums, FP64) and the separable Gaussian smoother.
+//
+// Each block owns a TX x TY tile of a (d1, d2) plane and marches along d0 over
+// a chunk of TZ planes.  For every plane it stages the tile plus its halo in
+// LDS, sums along d2 and then d1 in LDS, and keeps the last W plane sums in a
+// register ring from which the d0-direction window sum follows (running sum
+// for the box, weighted sum for the Gaussian).  The plane loop is unrolled by
+// W so that every ring slot is a compile-time register.
+#include "darc_kernels.hpp"
+
+namespace darc {
+
+namespace {
+
+constexpr int kTX = 32;  // tile width along d2
+constexpr int kTY = 8;   // tile height along d1
+constexpr int kNT = kTX * kTY;
+
+struct MarchGeom {
+  Geom g;
+  int ntx, nty, nz, tz;
+  uint32_t total;  // ntx * nty * nz * nchan blocks
+};
+
+struct Tile {
+  int xb, yb, z0, z1, chan;
+};
+
+__device__ __forceinline__ Tile march_tile(const MarchGeom& mg) {
+  uint32_t b = xcd_remap(blockIdx.x, mg.total);
+  Tile t;
+  const int tx = static_cast<int>(b % mg.ntx);
+  b /= mg.ntx;
+  const int ty = static_cast<int>(b % mg.nty);
+  b /= mg.nty;
+  const int zc = static_cast<int>(b % mg.nz);
+  t.chan = static_cast<int>(b / mg.nz);
+  t.xb = tx * kTX;
+  t.yb = ty * kTY;
+  t.z0 = zc * mg.tz;
+  t.z1 = min(t.z0 + mg.tz, mg.g.d0);
+  return t;
+}
+
+MarchGeom make_march(const Geom& g, int nchan, int halo) {
+  MarchGeom mg;
+  mg.g = g;
+  mg.ntx = (g.d2 + kTX - 1) / kTX;
+  mg.nty = (g.d1 + kTY - 1) / kTY;
+  // long chunks amortise the 2*halo planes of ramp-up; shorter ones give
+  // enough blocks for small cohorts
+  int tz = 64;
+  while (tz > 8 && tz > 2 * halo &&
+         static_cast<long long>(mg.ntx) * mg.nty * ((g.d0 + tz - 1) / tz) * nchan < 2048)
+    tz /= 2;
+  mg.tz = tz;
+  mg.nz = (g.d0 + tz - 1) / tz;
+  mg.total = static_cast<uint32_t>(mg.ntx) * mg.nty * mg.nz * nchan;
+  return mg;
+}
+
+// -------------------------------------------------------------- LNCC forward
+//
+// Window sums S_I, S_J, S_II, S_JJ, S_IJ over the W^3 cube centred at each
+// voxel (zero outside the volume, N = W^3), then
+//   cross = S_IJ - S_I S_J / N, Ivar = S_II - S_I^2 / N, Jvar = S_JJ - S_J^2 / N,
+//   den = Ivar Jvar + eps, cc = cross^2 / den,
+// loss += -(1/V) sum cc and, when FIELDS, the four per-voxel factors of the
+// adjoint: alpha = 2 cross / den, alpha * Jbar, beta = 2 cross^2 Jvar / den^2,
+// beta * Ibar.
+template <int W, bool FIELDS>
+__global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg,
+                                                  const float* __restrict__ atlas,
+                                                  float* __restrict__ fields,
+                                                  double* __restrict__ loss, int loss_stride,
+                                                  MarchGeom mg, double eps, double neg_inv_v) {
+  constexpr int R = W / 2, HX = kTX + 2 * R, HY = kTY + 2 * R;
+  constexpr double kInvN = 1.0 / (W * W * W);
+  __shared__ double sI[HY * HX];
+  __shared__ double sJ[HY * HX];
+  __shared__ double sr[5][HY * kTX];
+  __shared__ double red[kNT / 64];
+  const Geom& g = mg.g;
+  const Tile tl = march_tile(mg);
+  const int tid = threadIdx.x, lx = tid % kTX, ly = tid / kTX;
+  const float* I = wimg + static_cast<size_t>(tl.chan) * g.V;
+  double ring[W][5];
+  double S[5];
+#pragma unroll
+  for (int c = 0; c < 5; ++c) {
+    S[c] = 0.0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) ring[j][c] = 0.0;
+  }
+  double acc = 0.0;
+  const int nplanes = (tl.z1 - tl.z0) + 2 * R;
+  for (int base = 0; base < nplanes; base += W) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int p = base + j;
+      if (p < nplanes) {
+        const int zz = tl.z0 - R + p;
+        const bool zin = (zz >= 0) && (zz < g.d0);
+        for (int e = tid; e < HY * HX; e += kNT) {
+          const int hy = e / HX, hx = e - hy * HX;
+          const int y = tl.yb - R + hy, x = tl.xb - R + hx;
+          double vi = 0.0, vj = 0.0;
+          if (zin && y >= 0 && y < g.d1 && x >= 0 && x < g.d2) {
+            const int idx = (zz * g.d1 + y) * g.d2 + x;
+            vi = I[idx];
+            vj = atlas[idx];
+          }
+          sI[e] = vi;
+          sJ[e] = vj;
+        }
+        __syncthreads();
+        for (int e = tid; e < HY * kTX; e += kNT) {
+          const int hy = e / kTX, cx = e - hy * kTX;
+          double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
+#pragma unroll
+          for (int k = 0; k < W; ++k) {
+            const double vi = sI[hy * HX + cx + k], vj = sJ[hy * HX + cx + k];
+            a0 += vi;
+            a1 += vj;
+            a2 += vi * vi;
+            a3 += vj * vj;
+            a4 += vi * vj;
+          }
+          sr[0][e] = a0;
+          sr[1][e] = a1;
+          sr[2][e] = a2;
+          sr[3][e] = a3;
+          sr[4][e] = a4;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 5; ++c) {
+          double P = 0.0;
+#pragma unroll
+          for (int k = 0; k < W; ++k) P += sr[c][(ly + k) * kTX + lx];
+          S[c] += P - ring[j][c];
+          ring[j][c] = P;
+        }
+        const int zo = zz - R;
+        const int y = tl.yb + ly, x = tl.xb + lx;
+        if (zo >= tl.z0 && y < g.d1 && x < g.d2) {
+          const double cross = S[4] - S[0] * S[1] * kInvN;
+          const double ivar = S[2] - S[0] * S[0] * kInvN;
+          const double jvar = S[3] - S[1] * S[1] * kInvN;
+          const double den = ivar * jvar + eps;
+          const double cc = cross * cross / den;
+          acc += cc;
+          if (FIELDS) {
+            const double alpha = 2.0 * cross / den;
+            const double beta = 2.0 * cross * cross * jvar / (den * den);
+            const int idx = (zo * g.d1 + y) * g.d2 + x;
+            float* F = fields + static_cast<size_t>(tl.chan) * 4 * g.V;
+            F[idx] = static_cast<float>(alpha);
+            F[g.V + idx] = static_cast<float>(alpha * S[1] * kInvN);
+            F[2 * g.V + idx] = static_cast<float>(beta);
+            F[3 * g.V + idx] = static_cast<float>(beta * S[0] * kInvN);
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  const double tot = block_sum<kNT>(acc, red);
+  if (tid == 0) atomicAdd(loss + static_cast<size_t>(tl.chan) * loss_stride, tot * neg_inv_v);
+}
+
+// -------------------------------------------------------------- LNCC adjoint
+//
+// Box sums (same zero-padded W^3 window) of the four factor fields, then
+//   dD/dI(y) = -(1/V) [J(y) Box(alpha) - Box(alpha Jbar) - I(y) Box(beta) + Box(beta Ibar)].
+// FUSED: continues through the warp adjoint, gu = dD/dI * grad I_orig(x + u)
+// + lam dR/du, and adds lam R(u) to the loss; otherwise writes dD/dI.
+template <int W, bool FUSED>
+__global__ __launch_bounds__(kNT) void k_lncc_bwd(
+    const float* __restrict__ fields, const float* __restrict__ wimg,
+    const float* __restrict__ atlas, float* __restrict__ gw, const float* __restrict__ img,
+    const float* __restrict__ u, float* __restrict__ gu, double* __restrict__ loss,
+    int loss_stride, RegW rw, MarchGeom mg, double neg_inv_v) {
+  constexpr int R = W / 2, HX = kTX + 2 * R, HY = kTY + 2 * R;
+  __shared__ double sIn[4][HY * HX];
+  __shared__ double sr[4][HY * kTX];
+  __shared__ double red[kNT / 64];
+  const Geom& g = mg.g;
+  const Tile tl = march_tile(mg);
+  const int tid = threadIdx.x, lx = tid % kTX, ly = tid / kTX;
+  const float* F = fields + static_cast<size_t>(tl.chan) * 4 * g.V;
+  double ring[W][4];
+  double S[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    S[c] = 0.0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) ring[j][c] = 0.0;
+  }
+  double racc = 0.0;
+  const int nplanes = (tl.z1 - tl.z0) + 2 * R;
+  for (int base = 0; base < nplanes; base += W) {
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int p = base + j;
+      if (p < nplanes) {
+        const int zz = tl.z0 - R + p;
+        const bool zin = (zz >= 0) && (zz < g.d0);
+        for (int e = tid; e < HY * HX; e += kNT) {
+          const int hy = e / HX, hx = e - hy * HX;
+          const int y = tl.yb - R + hy, x = tl.xb - R + hx;
+          double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+          if (zin && y >= 0 && y < g.d1 && x >= 0 && x < g.d2) {
+            const int idx = (zz * g.d1 + y) * g.d2 + x;
+            v0 = F[idx];
+            v1 = F[g.V + idx];
+            v2 = F[2 * g.V + idx];
+            v3 = F[3 * g.V + idx];
+          }
+          sIn[0][e] = v0;
+          sIn[1][e] = v1;
+          sIn[2][e] = v2;
+          sIn[3][e] = v3;
+        }
+        __syncthreads();
+        for (int e = tid; e < HY * kTX; e += kNT) {
+          const int hy = e / kTX, cx = e - hy * kTX;
+#pragma unroll
+          for (int c = 0; c < 4; ++c) {
+            double a = 0.0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) a += sIn[c][hy * HX + cx + k];
+            sr[c][e] = a;
+          }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          double P = 0.0;
+#pragma unroll
+          for (int k = 0; k < W; ++k) P += sr[c][(ly + k) * kTX + lx];
+          S[c] += P - ring[j][c];
+          ring[j][c] = P;
+        }
+        const int zo = zz - R;
+        const int y = tl.yb + ly, x = tl.xb + lx;
+        if (zo >= tl.z0 && y < g.d1 && x < g.d2) {
+          const int idx = (zo * g.d1 + y) * g.d2 + x;
+          const size_t vidx = static_cast<size_t>(tl.chan) * g.V + idx;
+          const double Jc = atlas[idx];
+          const double Ic = wimg[vidx];
+          const double gI = neg_inv_v * (Jc * S[0] - S[1] - Ic * S[2] + S[3]);
+          if (!FUSED) {
+            gw[vidx] = static_cast<float>(gI);
+          } else {
+            const size_t off = static_cast<size_t>(tl.chan) * 3 * g.V;
+            const float* f = u + off;
+            const float* Io = img + static_cast<size_t>(tl.chan) * g.V;
+            const Tri t = sample_zero(Io, g, zo, y, x, f[idx], f[g.V + idx], f[2 * g.V + idx]);
+            float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f;
+            if (rw.on) {
+              r0 = reg_at(f, g, idx, zo, y, x, rw, racc);
+              r1 = reg_at(f + g.V, g, idx, zo, y, x, rw, racc);
+              r2 = reg_at(f + 2 * g.V, g, idx, zo, y, x, rw, racc);
+            }
+            const float gf = static_cast<float>(gI);
+            float* o = gu + off;
+            o[idx] = gf * t.d0 + r0;
+            o[g.V + idx] = gf * t.d1 + r1;
+            o[2 * g.V + idx] = gf * t.d2 + r2;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+  if (FUSED && rw.on) {
+    const double tot = block_sum<kNT>(racc, red);
+    if (tid == 0) atomicAdd(loss + static_cast<size_t>(tl.chan) * loss_stride, rw.lam * tot);
+  }
+}
+
+// ------------------------------------------------------------ Gaussian smoother
+//
+// out = G_sigma * in, separable, weights w[0..2R], replicated border.
+struct GaussW {
+  float w[17];
+};
+
+template <int R>
+__global__ __launch_bounds__(kNT) void k_gauss(const float* __restrict__ in,
+                                               float* __restrict__ out, MarchGeom mg, GaussW gw) {
+  constexpr int W2 = 2 * R + 1, HX = kTX + 2 * R, HY = kTY + 2 * R;
+  __shared__ float sIn[HY * HX];
+  __shared__ float sr[HY * kTX];
+  const Geom& g = mg.g;
+  const Tile tl = march_tile(mg);
+  const int tid = threadIdx.x, lx = tid % kTX, ly = tid / kTX;
+  const float* src = in + static_cast<size_t>(tl.chan) * g.V;
+  float* dst = out + static_cast<size_t>(tl.chan) * g.V;
+  float ring[W2];
+#pragma unroll
+  for (int j = 0; j < W2; ++j) ring[j] = 0.0f;
+  const int nplanes = (tl.z1 - tl.z0) + 2 * R;
+  for (int base = 0; base < nplanes; base += W2) {
+#pragma unroll
+    for (int j = 0; j < W2; ++j) {
+      const int p = base + j;
+      if (p < nplanes) {
+        const int zz = tl.z0 - R + p;
+        const int zc = min(max(zz, 0), g.d0 - 1);
+        for (int e = tid; e < HY * HX; e += kNT) {
+          const int hy = e / HX, hx = e - hy * HX;
+          const int y = min(max(tl.yb - R + hy, 0), g.d1 - 1);
+          const int x = min(max(tl.xb - R + hx, 0), g.d2 - 1);
+          sIn[e] = src[(zc * g.d1 + y) * g.d2 + x];
+        }
+        __syncthreads();
+        for (int e = tid; e < HY * kTX; e += kNT) {
+          const int hy = e / kTX, cx = e - hy * kTX;
+          float a = 0.0f;
+#pragma unroll
+          for (int k = 0; k < W2; ++k) a += gw.w[k] * sIn[hy * HX + cx + k];
+          sr[e] = a;
+        }
+        __syncthreads();
+        float P = 0.0f;
+#pragma unroll
+        for (int k = 0; k < W2; ++k) P += gw.w[k] * sr[(ly + k) * kTX + lx];
+        ring[j] = P;
+        if (p >= 2 * R) {
+          const int zo = zz - R;
+          const int y = tl.yb + ly, x = tl.xb + lx;
+          if (y < g.d1 && x < g.d2) {
+            float o = 0.0f;
+#pragma unroll
+            for (int k = 0; k < W2; ++k) o += gw.w[k] * ring[(j + 1 + k) % W2];
+            dst[(zo * g.d1 + y) * g.d2 + x] = o;
+          }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+template <int W>
+void lncc_fwd_w(const float* w, const float* atlas, float* fields, double* loss, int loss_stride,
+                double eps, const Geom& g, int n, hipStream_t st) {
+  const MarchGeom mg = make_march(g, n, W / 2);
+  const double neg_inv_v = -1.0 / g.V;
+  if (fields)
+    hipLaunchKernelGGL((k_lncc_fwd<W, true>), dim3(mg.total), dim3(kNT), 0, st, w, atlas, fields,
+                       loss, loss_stride, mg, eps, neg_inv_v);
+  else
+    hipLaunchKernelGGL((k_lncc_fwd<W, false>), dim3(mg.total), dim3(kNT), 0, st, w, atlas, fields,
+                       loss, loss_stride, mg, eps, neg_inv_v);
+}
+
+template <int W, bool FUSED>
+void lncc_bwd_w(const float* fields, const float* w, const float* atlas, float* gw,
+                const float* img, const float* u, float* gu, double* loss, int loss_stride,
+                const RegW& rw, const Geom& g, int n, hipStream_t st) {
+  const MarchGeom mg = make_march(g, n, W / 2);
+  hipLaunchKernelGGL((k_lncc_bwd<W, FUSED>), dim3(mg.total), dim3(kNT), 0, st, fields, w, atlas,
+                     gw, img, u, gu, loss, loss_stride, rw, mg, -1.0 / g.V);
+}
+
+template <bool FUSED>
+bool lncc_bwd_dispatch(const float* fields, const float* w, const float* atlas, float* gw,
+                       const float* img, const float* u, float* gu, double* loss, int loss_stride,
+                       const RegW& rw, int win, const Geom& g, int n, hipStream_t st) {
+  switch (win) {
+    case 3: lncc_bwd_w<3, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, st); return true;
+    case 5: lncc_bwd_w<5, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, st); return true;
+    case 7: lncc_bwd_w<7, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, st); return true;
+    case 9: lncc_bwd_w<9, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, st); return true;
+    case 11: lncc_bwd_w<11, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, st); return true;
+    default: return false;
+  }
+}
+
+template <int R>
+void gauss_r(const float* in, float* out, const GaussW& gw, const Geom& g, int nchan,
+             hipStream_t st) {
+  const MarchGeom mg = make_march(g, nchan, R);
+  hipLaunchKernelGGL((k_gauss<R>), dim3(mg.total), dim3(kNT), 0, st, in, out, mg, gw);
+}
+
+}  // namespace
+
+bool lncc_window_supported(int win) {
+  return win == 3 || win == 5 || win == 7 || win == 9 || win == 11;
+}
+
+bool launch_lncc_fwd(const float* w, const float* atlas, float* fields, double* loss,
+                     int loss_stride, int win, double eps, const Geom& g, int n, hipStream_t st) {
+  if (!lncc_window_supported(win)) return false;
+  prof_begin(st, KC_LNCC_FWD);
+  switch (win) {
+    case 3: lncc_fwd_w<3>(w, atlas, fields, loss, loss_stride, eps, g, n, st); break;
+    case 5: lncc_fwd_w<5>(w, atlas, fields, loss, loss_stride, eps, g, n, st); break;
+    case 7: lncc_fwd_w<7>(w, atlas, fields, loss, loss_stride, eps, g, n, st); break;
+    case 9: lncc_fwd_w<9>(w, atlas, fields, loss, loss_stride, eps, g, n, st); break;
+    default: lncc_fwd_w<11>(w, atlas, fields, loss, loss_stride, eps, g, n, st); break;
+  }
+  prof_end(st, KC_LNCC_FWD);
+  return true;
+}
+
+bool launch_lncc_bwd(const float* fields, const float* w, const float* atlas, float* gw, int win,
+                     const Geom& g, int n, hipStream_t st) {
+  if (!lncc_window_supported(win)) return false;
+  RegW none{};
+  prof_begin(st, KC_LNCC_BWD);
+  lncc_bwd_dispatch<false>(fields, w, atlas, gw, nullptr, nullptr, nullptr, nullptr, 0, none, win,
+                           g, n, st);
+  prof_end(st, KC_LNCC_BWD);
+  return true;
+}
+
+bool launch_lncc_bwd_fused(const float* fields, const float* w, const float* atlas,
+                           const float* img, const float* u, float* gu, double* loss,
+                           int loss_stride, const RegW& rw, int win, const Geom& g, int n,
+                           hipStream_t st) {
+  if (!lncc_window_supported(win)) return false;
+  prof_begin(st, KC_LNCC_BWD);
+  lncc_bwd_dispatch<true>(fields, w, atlas, nullptr, img, u, gu, loss, loss_stride, rw, win, g, n,
+                          st);
+  prof_end(st, KC_LNCC_BWD);
+  return true;
+}
+
+int gauss_radius(float sigma) { return static_cast<int>(3.0f * sigma + 0.5f); }
+
+bool launch_gauss(const float* in, float* out, float sigma, const Geom& g, int nchan,
+                  hipStream_t st) {
+  const int r = gauss_radius(sigma);
+  if (r < 1 || r > 8) return false;
+  GaussW gw{};
+  double w[17];
+  double sum = 0.0;
+  for (int k = -r; k <= r; ++k) {
+    w[k + r] = std::exp(-0.5 * k * k / (static_cast<double>(sigma) * sigma));
+    sum += w[k + r];
+  }
+  for (int k = 0; k < 2 * r + 1; ++k) gw.w[k] = static_cast<float>(w[k] / sum);
+  prof_begin(st, KC_GAUSS);
+  switch (r) {
+    case 1: gauss_r<1>(in, out, gw, g, nchan, st); break;
+    case 2: gauss_r<2>(in, out, gw, g, nchan, st); break;
+    case 3: gauss_r<3>(in, out, gw, g, nchan, st); break;
+    case 4: gauss_r<4>(in, out, gw, g, nchan, st); break;
+    case 5: gauss_r<5>(in, out, gw, g, nchan, st); break;
+    case 6: gauss_r<6>(in, out, gw, g, nchan, st); break;
+    case 7: gauss_r<7>(in, out, gw, g, nchan, st); break;
+    default: gauss_r<8>(in, out, gw, g, nchan, st); break;
+  }
+  prof_end(st, KC_GAUSS);
+  return true;
+}
+
+}  // namespace darc

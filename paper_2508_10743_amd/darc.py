@@ -1,0 +1,335 @@
+"""Python binding of libdarc: torch tensors in, C ABI calls out.
+
+torch supplies device memory and the current HIP stream; every step of the
+DARC hot path runs in libdarc's HIP kernels.  Each function checks shapes,
+dtypes and devices, passes raw pointers and sizes to the matching ``darc_*``
+entry point on ``torch.cuda.current_stream()``, and raises
+:class:`DarcError` on a non-zero status.  Nothing here computes.
+
+Shapes: images ``[n, D0, D1, D2]`` FP32, fields ``[n, 3, D0, D1, D2]`` FP32
+(component c displaces axis c, voxel units), all contiguous on one device.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional, Tuple
+
+import torch
+
+from . import _lib as L
+from ._lib import DarcError  # noqa: F401
+
+METRICS = {"mse": L.DARC_MSE, "lncc": L.DARC_LNCC}
+CENTER_MODES = {"displacement": L.DARC_CENTER_DISPLACEMENT, "velocity": L.DARC_CENTER_VELOCITY}
+
+
+def lib() -> ctypes.CDLL:
+    return L.load()
+
+
+def _stream() -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _p(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(name: str, t: torch.Tensor, dtype=torch.float32, ndim: Optional[int] = None) -> None:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must live in GPU memory (got device {t.device})")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dims (got shape {tuple(t.shape)})")
+
+
+def _field(name: str, t: torch.Tensor) -> Tuple[int, int, int, int]:
+    _dev(name, t, ndim=5)
+    if t.shape[1] != 3:
+        raise ValueError(f"{name} must be [n, 3, D0, D1, D2] (got {tuple(t.shape)})")
+    n, _, d0, d1, d2 = t.shape
+    return n, d0, d1, d2
+
+
+def _images(name: str, t: torch.Tensor) -> Tuple[int, int, int, int]:
+    _dev(name, t, ndim=4)
+    n, d0, d1, d2 = t.shape
+    return n, d0, d1, d2
+
+
+def _same(a_name, a, b_name, b):
+    if tuple(a) != tuple(b):
+        raise ValueError(f"{a_name} {tuple(a)} and {b_name} {tuple(b)} do not match")
+
+
+def _call(fn: str, *args) -> None:
+    lb = lib()
+    L.check(lb, fn, getattr(lb, fn)(*args))
+
+
+def _workspace(nbytes: int, device) -> Optional[torch.Tensor]:
+    if nbytes == 0:
+        return None
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+# --------------------------------------------------------------------- Exp(v)
+
+
+def exp_svf(v: torch.Tensor, n_sq: int = 7, checkpoints: bool = True):
+    """u = Exp(v) - id by scaling and squaring; returns ``(u, ckpt)``.
+
+    ``ckpt`` is ``[n_sq-1, n, 3, D0, D1, D2]`` (u_1 .. u_{n_sq-1}) when
+    ``checkpoints`` and ``n_sq >= 2``, else None.
+    """
+    n, d0, d1, d2 = _field("v", v)
+    u = torch.empty_like(v)
+    ckpt = None
+    if checkpoints and n_sq >= 2:
+        ckpt = torch.empty((n_sq - 1,) + tuple(v.shape), dtype=v.dtype, device=v.device)
+    ws = _workspace(lib().darc_exp_svf_ws_bytes(n, d0, d1, d2, n_sq, int(ckpt is not None)),
+                    v.device)
+    _call("darc_exp_svf", _p(v), _p(u), _p(ckpt), n, d0, d1, d2, n_sq, _p(ws),
+          0 if ws is None else ws.numel(), _stream())
+    return u, ckpt
+
+
+def exp_svf_bwd(v: torch.Tensor, ckpt: Optional[torch.Tensor], g_u: torch.Tensor,
+                n_sq: int = 7) -> torch.Tensor:
+    """dL/dv given dL/du, through the n_sq squaring steps."""
+    n, d0, d1, d2 = _field("v", v)
+    _same("g_u", g_u.shape, "v", v.shape)
+    _field("g_u", g_u)
+    if ckpt is not None:
+        _dev("ckpt", ckpt, ndim=6)
+        _same("ckpt", ckpt.shape, "expected", (n_sq - 1,) + tuple(v.shape))
+    g_v = torch.empty_like(v)
+    ws = _workspace(lib().darc_exp_svf_bwd_ws_bytes(n, d0, d1, d2, n_sq), v.device)
+    _call("darc_exp_svf_bwd", _p(v), _p(ckpt), _p(g_u), _p(g_v), n, d0, d1, d2, n_sq, _p(ws),
+          0 if ws is None else ws.numel(), _stream())
+    return g_v
+
+
+# ----------------------------------------------------------------------- warp
+
+
+def warp3d(img: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+    """out_i(x) = I_i(x + u_i(x)), trilinear, zero padding."""
+    n, d0, d1, d2 = _images("img", img)
+    _same("u", u.shape, "expected", (n, 3, d0, d1, d2))
+    _field("u", u)
+    out = torch.empty_like(img)
+    _call("darc_warp3d", _p(img), _p(u), _p(out), n, d0, d1, d2, _stream())
+    return out
+
+
+def warp3d_bwd(img: torch.Tensor, u: torch.Tensor, g_out: torch.Tensor,
+               g_u: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """g_u += g_out * grad I(x + u); a zero g_u is created when None."""
+    n, d0, d1, d2 = _images("img", img)
+    _same("u", u.shape, "expected", (n, 3, d0, d1, d2))
+    _field("u", u)
+    _same("g_out", g_out.shape, "img", img.shape)
+    _images("g_out", g_out)
+    if g_u is None:
+        g_u = torch.zeros_like(u)
+    else:
+        _same("g_u", g_u.shape, "u", u.shape)
+        _field("g_u", g_u)
+    _call("darc_warp3d_bwd", _p(img), _p(u), _p(g_out), _p(g_u), n, d0, d1, d2, _stream())
+    return g_u
+
+
+# ------------------------------------------------------------ dissimilarity
+
+
+def sim_grad(warped: torch.Tensor, atlas: torch.Tensor, metric: str = "mse", win: int = 9,
+             eps: float = 1e-5, grad: bool = True):
+    """Per-subject dissimilarity (FP64 ``[n]``) and, if ``grad``, dD/dwarped."""
+    n, d0, d1, d2 = _images("warped", warped)
+    _dev("atlas", atlas, ndim=3)
+    _same("atlas", atlas.shape, "volume", (d0, d1, d2))
+    m = METRICS[metric]
+    loss = torch.zeros(n, dtype=torch.float64, device=warped.device)
+    g = torch.empty_like(warped) if grad else None
+    ws = _workspace(lib().darc_sim_grad_ws_bytes(m, n, d0, d1, d2) if grad else 0, warped.device)
+    _call("darc_sim_grad", _p(warped), _p(atlas), m, win, eps, _p(loss), _p(g), n, d0, d1, d2,
+          _p(ws), 0 if ws is None else ws.numel(), _stream())
+    return loss, g
+
+
+# ----------------------------------------------------------------- smoothing
+
+
+def gauss_smooth(x: torch.Tensor, sigma: float) -> torch.Tensor:
+    """Separable Gaussian of every component of ``[n, ncomp, D0, D1, D2]``."""
+    _dev("x", x, ndim=5)
+    n, nc, d0, d1, d2 = x.shape
+    out = torch.empty_like(x)
+    _call("darc_smooth3d", _p(x), _p(out), n, nc, d0, d1, d2, L.DARC_GAUSS, sigma, None, None, 0,
+          _stream())
+    return out
+
+
+def diffusion(u: torch.Tensor, lam: float, out: Optional[torch.Tensor] = None,
+              with_loss: bool = True):
+    """(out += lam dR/du, lam R(u_i) per subject as FP64 ``[n]``)."""
+    _dev("u", u, ndim=5)
+    n, nc, d0, d1, d2 = u.shape
+    if out is None:
+        out = torch.zeros_like(u)
+    else:
+        _same("out", out.shape, "u", u.shape)
+        _dev("out", out, ndim=5)
+    loss = torch.zeros(n, dtype=torch.float64, device=u.device) if with_loss else None
+    _call("darc_smooth3d", _p(u), _p(out), n, nc, d0, d1, d2, L.DARC_DIFFUSION, lam, _p(loss),
+          None, 0, _stream())
+    return out, loss
+
+
+# ------------------------------------------------- optimiser, centring, atlas
+
+
+def adam_step(v, m, s, g, t: int, lr=1e-2, beta1=0.9, beta2=0.999, eps=1e-8) -> None:
+    """One in-place Adam step on v (m, s updated); t is the new step count."""
+    for name, x in (("v", v), ("m", m), ("s", s), ("g", g)):
+        _dev(name, x)
+        _same(name, x.shape, "v", v.shape)
+    _call("darc_adam_step", _p(v), _p(m), _p(s), _p(g), v.numel(), t, lr, beta1, beta2, eps,
+          _stream())
+
+
+def center(u: torch.Tensor) -> torch.Tensor:
+    """In place u_i <- u_i - mean_j u_j; returns the mean ``[3, D0, D1, D2]``."""
+    n, d0, d1, d2 = _field("u", u)
+    mean = torch.empty((3, d0, d1, d2), dtype=u.dtype, device=u.device)
+    _call("darc_center", _p(u), _p(mean), n, d0, d1, d2, _stream())
+    return mean
+
+
+def atlas_update(images: torch.Tensor, u: torch.Tensor,
+                 mean: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """A(x) = (1/n) sum_i I_i(x + u_i(x) - mean(x))."""
+    n, d0, d1, d2 = _images("images", images)
+    _same("u", u.shape, "expected", (n, 3, d0, d1, d2))
+    _field("u", u)
+    if mean is not None:
+        _dev("mean", mean, ndim=4)
+        _same("mean", mean.shape, "expected", (3, d0, d1, d2))
+    atlas = torch.empty((d0, d1, d2), dtype=images.dtype, device=images.device)
+    _call("darc_atlas_update", _p(images), _p(u), _p(mean), _p(atlas), n, d0, d1, d2, _stream())
+    return atlas
+
+
+# ---------------------------------------------------------------------- sweep
+
+
+@dataclasses.dataclass
+class SweepParams:
+    """Settings of one coordinate-descent sweep (mirrors ``darc_params``)."""
+
+    metric: str = "mse"
+    win: int = 9
+    ncc_eps: float = 1e-5
+    lam: float = 0.01
+    smooth_sigma: float = 0.0
+    n_sq: int = 7
+    k2: int = 5
+    lr: float = 1e-2
+    beta1: float = 0.9
+    beta2: float = 0.999
+    adam_eps: float = 1e-8
+    center_mode: str = "displacement"
+    reinit_v: bool = False
+    batch: int = 0  # subjects per launch; 0 = all
+
+    def to_c(self) -> L.DarcParams:
+        return L.DarcParams(METRICS[self.metric], self.win, self.ncc_eps, self.lam,
+                            self.smooth_sigma, self.n_sq, self.k2, self.lr, self.beta1,
+                            self.beta2, self.adam_eps, CENTER_MODES[self.center_mode],
+                            int(self.reinit_v), self.batch)
+
+
+class Cohort:
+    """Device state of one DARC run: images, velocities, Adam moments, atlas.
+
+    ``images`` is ``[n, D0, D1, D2]`` FP32 on the GPU.  Velocities and moments
+    start at zero and the atlas at the mean of the unwarped subjects
+    (computed by ``darc_atlas_update`` with zero displacements).
+    """
+
+    def __init__(self, images: torch.Tensor, params: SweepParams, keep_u_hat: bool = True):
+        n, d0, d1, d2 = _images("images", images)
+        self.images = images
+        self.params = params
+        dev = images.device
+        shape = (n, 3, d0, d1, d2)
+        self.v = torch.zeros(shape, dtype=torch.float32, device=dev)
+        self.m = torch.zeros_like(self.v)
+        self.s = torch.zeros_like(self.v)
+        self.u_hat = torch.zeros_like(self.v) if keep_u_hat else None
+        self.atlas = atlas_update(images, self.v)
+        self.step = 0
+        self.sweeps = 0
+        self._state = L.DarcState()
+        self._cparams = params.to_c()
+        self._refresh_state()
+        nbytes = lib().darc_sweep_ws_bytes(ctypes.byref(self._state), ctypes.byref(self._cparams))
+        if nbytes == 0:
+            raise DarcError("darc_sweep_ws_bytes", L.DARC_EINVAL,
+                            lib().darc_last_error().decode(errors="replace"))
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.losses = torch.zeros(n * params.k2 + 1, dtype=torch.float64, device=dev)
+
+    def _refresh_state(self) -> None:
+        n, d0, d1, d2 = self.images.shape
+        st = self._state
+        st.images = self.images.data_ptr()
+        st.v = self.v.data_ptr()
+        st.m = self.m.data_ptr()
+        st.s = self.s.data_ptr()
+        st.atlas = self.atlas.data_ptr()
+        st.u_hat = None if self.u_hat is None else self.u_hat.data_ptr()
+        st.step = self.step
+        st.n, st.d0, st.d1, st.d2 = n, d0, d1, d2
+
+    def sweep(self) -> torch.Tensor:
+        """Enqueue one sweep; returns the device losses ``[n*k2 + 1]`` (FP64):
+        per-subject inner losses, then the group loss."""
+        self._refresh_state()
+        _call("darc_sweep", ctypes.byref(self._state), ctypes.byref(self._cparams),
+              _p(self.losses), _p(self.ws), self.ws.numel(), _stream())
+        self.step = int(self._state.step)
+        self.sweeps += 1
+        return self.losses
+
+    def group_loss(self) -> float:
+        return float(self.losses[-1].item())
+
+
+# -------------------------------------------------------------- kernel timing
+
+
+def profile_enable(on: bool = True) -> None:
+    _call("darc_profile_enable", int(on))
+
+
+def profile_reset() -> None:
+    _call("darc_profile_reset")
+
+
+def profile_collect() -> dict:
+    """{kernel class: (launches, total ms)} since the last reset."""
+    lb = lib()
+    k = lb.darc_profile_num_classes()
+    counts = (ctypes.c_longlong * k)()
+    ms = (ctypes.c_double * k)()
+    L.check(lb, "darc_profile_collect", lb.darc_profile_collect(counts, ms, k))
+    return {lb.darc_profile_name(i).decode(): (int(counts[i]), float(ms[i])) for i in range(k)}

@@ -117,8 +117,8 @@ int darc_exp_svf(const float* v, float* u, float* ckpt, int n, int d0, int d1, i
  *         Required when n_sq >= 2.
  *   g_u   [n][3][V] in.   g_v [n][3][V] out (overwritten, not accumulated).
  *   ws    scratch of darc_exp_svf_bwd_ws_bytes().
- * The scatter uses floating-point atomics: results are reproducible only up
- * to FP32 summation order.
+ * The scatter term is summed with LDS floating-point atomics: results are
+ * reproducible only up to FP32 summation order.
  * ---------------------------------------------------------------------- */
 size_t darc_exp_svf_bwd_ws_bytes(int n, int d0, int d1, int d2, int n_sq);
 int darc_exp_svf_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, int n,

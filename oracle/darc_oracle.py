@@ -226,6 +226,45 @@ def squaring_step_bwd(u_t: np.ndarray, g_next: np.ndarray) -> np.ndarray:
     return g_next + jtg + scatter_border(pos, g_next, dims)
 
 
+def squaring_step_bwd_at(u_t: np.ndarray, g_next: np.ndarray, points: np.ndarray) -> np.ndarray:
+    """``squaring_step_bwd(u_t, g_next)`` evaluated only at the voxels
+    ``points`` (``[3, P]`` integer coordinates); returns ``[3, P]``.
+
+    Same sum as the full adjoint, taken one output voxel y at a time: the
+    direct term g(y) + J_t(y)^T g(y), plus w_k(x) g(x) over every source x
+    whose cell has y as corner k.  Such an x satisfies |x_d + u_d(x) - y_d| < 1
+    (or is clamped onto y), so |x_d - y_d| <= max|u_d| + 1 and a window of that
+    radius around y contains all of them.
+    """
+    u_t = np.asarray(u_t, dtype=np.float64)
+    g_next = np.asarray(g_next, dtype=np.float64)
+    dims = u_t.shape[1:]
+    pts = np.asarray(points, dtype=np.int64)
+    y = pts.astype(np.float64)
+    uy = u_t[:, pts[0], pts[1], pts[2]]
+    gy = g_next[:, pts[0], pts[1], pts[2]]
+    _, jac = sample_border(u_t, y + uy)
+    out = gy + np.einsum("cdp,cp->dp", jac, gy)
+    R = [int(np.ceil(np.abs(u_t[d]).max())) + 1 for d in range(3)]
+    offs = np.stack(np.meshgrid(*[np.arange(-r, r + 1) for r in R], indexing="ij")).reshape(3, -1)
+    for p in range(pts.shape[1]):
+        xs = pts[:, p:p + 1] + offs
+        keep = np.all((xs >= 0) & (xs < np.array(dims)[:, None]), axis=0)
+        xs = xs[:, keep]
+        ux = u_t[:, xs[0], xs[1], xs[2]]
+        idx, t, _ = _cells_border(xs.astype(np.float64) + ux, dims)
+        gx = g_next[:, xs[0], xs[1], xs[2]]
+        for a in (0, 1):
+            for b in (0, 1):
+                for c in (0, 1):
+                    hit = ((idx[0] + a == pts[0, p]) & (idx[1] + b == pts[1, p])
+                           & (idx[2] + c == pts[2, p]))
+                    w = ((t[0] if a else 1.0 - t[0]) * (t[1] if b else 1.0 - t[1])
+                         * (t[2] if c else 1.0 - t[2]))
+                    out[:, p] += (gx * (w * hit)).sum(axis=1)
+    return out
+
+
 def exp_svf_bwd(steps: List[np.ndarray], g_u: np.ndarray) -> np.ndarray:
     """Gradient with respect to v of a loss whose gradient w.r.t. u_N is ``g_u``."""
     n_sq = len(steps)

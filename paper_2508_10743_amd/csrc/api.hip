@@ -147,15 +147,16 @@ int darc_exp_svf(const float* v, float* u, float* ckpt, int n, int d0, int d1, i
   const size_t need = darc_exp_svf_ws_bytes(n, d0, d1, d2, n_sq, ckpt != nullptr);
   DARC_TRY(check_ws("darc_exp_svf", ws, ws_bytes, need));
   const Geom g = make_geom(d0, d1, d2);
-  run_exp_fwd(v, u, n_sq >= 2 ? ckpt : nullptr, static_cast<float*>(ws), g, n, n_sq,
+  run_exp_fwd(v, u, n_sq >= 2 ? ckpt : nullptr, static_cast<float*>(ws), nullptr, g, n, n_sq,
               as_stream(stream));
   return check_launch("darc_exp_svf");
 }
 
 size_t darc_exp_svf_bwd_ws_bytes(int n, int d0, int d1, int d2, int n_sq) {
-  if (n <= 0 || n_sq < 2) return 0;
+  if (n <= 0 || n_sq < 1 || d0 < 2 || d1 < 2 || d2 < 2) return 0;
   const size_t f = align256(field_bytes(n, d0, d1, d2));
-  return n_sq == 2 ? f : 2 * f;
+  const size_t nf = n_sq >= 3 ? 2 : (n_sq == 2 ? 1 : 0);
+  return nf * f + align256(exp_aux_bytes(make_geom(d0, d1, d2), n, n_sq));
 }
 
 int darc_exp_svf_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, int n, int d0,
@@ -171,11 +172,13 @@ int darc_exp_svf_bwd(const float* v, const float* ckpt, const float* g_u, float*
   const size_t need = darc_exp_svf_bwd_ws_bytes(n, d0, d1, d2, n_sq);
   DARC_TRY(check_ws("darc_exp_svf_bwd", ws, ws_bytes, need));
   const Geom g = make_geom(d0, d1, d2);
-  float* tmp_a = static_cast<float*>(ws);
-  float* tmp_b = n_sq >= 3 ? reinterpret_cast<float*>(static_cast<char*>(ws) +
-                                                      align256(field_bytes(n, d0, d1, d2)))
-                           : nullptr;
-  run_exp_bwd(v, ckpt, g_u, g_v, tmp_a, tmp_b, g, n, n_sq, as_stream(stream));
+  char* w = static_cast<char*>(ws);
+  const size_t f = align256(field_bytes(n, d0, d1, d2));
+  const size_t nf = n_sq >= 3 ? 2 : (n_sq == 2 ? 1 : 0);
+  float* tmp_a = nf >= 1 ? reinterpret_cast<float*>(w) : nullptr;
+  float* tmp_b = nf >= 2 ? reinterpret_cast<float*>(w + f) : nullptr;
+  int* aux = n_sq >= 1 ? reinterpret_cast<int*>(w + nf * f) : nullptr;
+  run_exp_bwd(v, ckpt, g_u, g_v, tmp_a, tmp_b, aux, false, g, n, n_sq, as_stream(stream));
   return check_launch("darc_exp_svf_bwd");
 }
 
@@ -307,7 +310,7 @@ namespace {
 
 struct SweepLayout {
   int B;
-  size_t ckpt, uN, gU, gA, gB, gV, iw, fields, vtmp, uhat, sloss, total;
+  size_t ckpt, aux, uN, gU, gA, gB, gV, iw, fields, vtmp, uhat, sloss, total;
 };
 
 SweepLayout sweep_layout(const darc_state* st, const darc_params* p) {
@@ -323,6 +326,7 @@ SweepLayout sweep_layout(const darc_state* st, const darc_params* p) {
     return o;
   };
   L.ckpt = take(p->n_sq >= 2 ? static_cast<size_t>(p->n_sq - 1) * fb : 0);
+  L.aux = take(exp_aux_bytes(make_geom(st->d0, st->d1, st->d2), L.B, p->n_sq));
   L.uN = take(fb);
   L.gU = take(fb);
   L.gA = take(fb);
@@ -395,6 +399,7 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
   const size_t fsv = 3 * static_cast<size_t>(g.V);
   char* w = static_cast<char*>(ws);
   float* ckpt = N >= 2 ? reinterpret_cast<float*>(w + L.ckpt) : nullptr;
+  int* aux = reinterpret_cast<int*>(w + L.aux);
   float* uN = reinterpret_cast<float*>(w + L.uN);
   float* gU = reinterpret_cast<float*>(w + L.gU);
   float* gA = reinterpret_cast<float*>(w + L.gA);
@@ -429,7 +434,7 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
     const float* ib = st->images + static_cast<size_t>(b0) * g.V;
     for (int k = 0; k < k2; ++k) {
       double* lslot = losses + static_cast<size_t>(b0) * k2 + k;
-      run_exp_fwd(vb, uN, ckpt, nullptr, g, nb, N, s);
+      run_exp_fwd(vb, uN, ckpt, nullptr, aux, g, nb, N, s);
       if (!lncc) {
         launch_mse_fused(ib, st->atlas, uN, gU, lslot, k2, rw, g, nb, s);
       } else {
@@ -437,7 +442,7 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
         launch_lncc_fwd(iw, st->atlas, fields, lslot, k2, p->win, p->ncc_eps, g, nb, s);
         launch_lncc_bwd_fused(fields, iw, st->atlas, ib, uN, gU, lslot, k2, rw, p->win, g, nb, s);
       }
-      run_exp_bwd(vb, ckpt, gU, gV, gA, gB, g, nb, N, s);
+      run_exp_bwd(vb, ckpt, gU, gV, gA, gB, aux, true, g, nb, N, s);
       const long long cnt = static_cast<long long>(nb) * fsv;
       if (smooth) {
         launch_adam(vb, vtmp, mb, sb, gV, cnt, step + k + 1, p->lr, p->beta1, p->beta2,
@@ -454,7 +459,7 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
   if (p->center_mode == DARC_CENTER_VELOCITY) launch_center(st->v, nullptr, g, n, s);
   for (int b0 = 0; b0 < n; b0 += B) {
     const int nb = n - b0 < B ? n - b0 : B;
-    run_exp_fwd(st->v + b0 * fsv, uh + b0 * fsv, nullptr, gA, g, nb, N, s);
+    run_exp_fwd(st->v + b0 * fsv, uh + b0 * fsv, nullptr, gA, nullptr, g, nb, N, s);
   }
   if (p->center_mode == DARC_CENTER_DISPLACEMENT) launch_center(uh, nullptr, g, n, s);
 

@@ -212,18 +212,18 @@ __device__ __forceinline__ float sample_zero_value(const float* __restrict__ img
 // Border cell of the position x + u in all three axes.
 struct BorderCell {
   int base;        // linear index of corner (0, 0, 0)
+  int i0, i1, i2;  // cell index (corner (0, 0, 0)) per axis, i_d in [0, D_d - 2]
   float t0, t1, t2;
   bool k0, k1, k2; // clamped along axis d
 };
 
 __device__ __forceinline__ BorderCell border_cell(const Geom& g, int x0, int x1, int x2, float u0,
                                                   float u1, float u2) {
-  int i0, i1, i2;
   BorderCell b;
-  cell_border(x0, sane(u0), g.d0, i0, b.t0, b.k0);
-  cell_border(x1, sane(u1), g.d1, i1, b.t1, b.k1);
-  cell_border(x2, sane(u2), g.d2, i2, b.t2, b.k2);
-  b.base = (i0 * g.d1 + i1) * g.d2 + i2;
+  cell_border(x0, sane(u0), g.d0, b.i0, b.t0, b.k0);
+  cell_border(x1, sane(u1), g.d1, b.i1, b.t1, b.k1);
+  cell_border(x2, sane(u2), g.d2, b.i2, b.t2, b.k2);
+  b.base = (b.i0 * g.d1 + b.i1) * g.d2 + b.i2;
   return b;
 }
 

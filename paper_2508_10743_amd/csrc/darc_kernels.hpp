@@ -11,16 +11,22 @@ namespace darc {
 RegW make_regw(const Geom& g, int ncomp, float lam);
 
 // --- scaling and squaring -------------------------------------------------
-void launch_exp_step(const float* src, float* dst, const Geom& g, int n, bool first, float scale,
-                     hipStream_t st);
-void launch_exp_step_bwd(const float* ut, const float* gin, float* gout, const Geom& g, int n,
-                         bool first, float scale, float oscale, hipStream_t st);
-// Full Exp(v): ckpt ([n_sq-1][n][3][V]) or tmp ([n][3][V]) must be given when n_sq >= 2.
-void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, const Geom& g, int n, int n_sq,
-                 hipStream_t st);
-// Full adjoint; tmp_a, tmp_b are [n][3][V]; g_v must not alias g_u.
+// The squaring kernels work on 32 x 8 x 8 tiles (d2 x d1 x d0).  The forward
+// step can record, per tile, the box of trilinear cells its sample positions
+// fall in, and per subject how far those boxes reach past their own tile;
+// the adjoint uses them to gather every contribution to an output tile
+// without global atomics.  `aux` holds [n_sq][n][ntiles][8] boxes followed by
+// [n_sq][n][8] reaches (ints).
+size_t exp_aux_bytes(const Geom& g, int n, int n_sq);
+// Full Exp(v): ckpt ([n_sq-1][n][3][V]) or tmp ([n][3][V]) must be given when
+// n_sq >= 2; aux (nullable) receives the boxes the adjoint needs.
+void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, int* aux, const Geom& g, int n,
+                 int n_sq, hipStream_t st);
+// Full adjoint; tmp_a, tmp_b are [n][3][V]; g_v must not alias g_u.  When
+// aux_ready is false the boxes in aux are recomputed from v and ckpt first.
 void run_exp_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, float* tmp_a,
-                 float* tmp_b, const Geom& g, int n, int n_sq, hipStream_t st);
+                 float* tmp_b, int* aux, bool aux_ready, const Geom& g, int n, int n_sq,
+                 hipStream_t st);
 
 // --- warp -----------------------------------------------------------------
 void launch_warp(const float* img, const float* u, float* out, const Geom& g, int n,

@@ -1,6 +1,5 @@
-// Voxel-parallel kernels of libdarc: scaling and squaring and its adjoint,
-// warping and its adjoint, MSE, the diffusion regulariser, Adam, the
-// centrality activation and the mean atlas.  One thread per voxel, 256-thread
+// Voxel-parallel kernels of libdarc: warping and its adjoint, MSE, the
+// diffusion regulariser, Adam, the centrality activation and the mean atlas.  One thread per voxel, 256-thread
 // blocks, blocks remapped so that each XCD walks a contiguous range of voxels
 // (the gathers of neighbouring voxels then share that XCD's L2).
 #include "darc_kernels.hpp"
@@ -21,111 +20,6 @@ __device__ __forceinline__ VoxelBlock voxel_block(uint32_t nbx, uint32_t total) 
   r.s = s;
   r.lin = static_cast<int>((b - s * nbx) * kBlock + threadIdx.x);
   return r;
-}
-
-// ------------------------------------------------------------------ Exp(v)
-
-// One squaring step u_{t+1}(x) = u_t(x) + u_t(x + u_t(x)), border sampling.
-// FIRST: src is v and u_0 = scale * v (scale = 2^-N, exact).
-template <bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_exp_step(const float* __restrict__ src,
-                                                     float* __restrict__ dst, Geom g, float scale,
-                                                     uint32_t nbx, uint32_t total) {
-  const VoxelBlock vb = voxel_block(nbx, total);
-  if (vb.lin >= g.V) return;
-  const size_t off = static_cast<size_t>(vb.s) * 3 * g.V;
-  const float* f = src + off;
-  float* o = dst + off;
-  const int lin = vb.lin;
-  int x0, x1, x2;
-  voxel_coords(g, lin, x0, x1, x2);
-  float u0 = f[lin], u1 = f[g.V + lin], u2 = f[2 * g.V + lin];
-  if (FIRST) {
-    u0 *= scale;
-    u1 *= scale;
-    u2 *= scale;
-  }
-  const BorderCell bc = border_cell(g, x0, x1, x2, u0, u1, u2);
-  float c[8];
-  corners_border(f, g, bc.base, c);
-  float s0 = tri_value(c, bc.t0, bc.t1, bc.t2);
-  corners_border(f + g.V, g, bc.base, c);
-  float s1 = tri_value(c, bc.t0, bc.t1, bc.t2);
-  corners_border(f + 2 * g.V, g, bc.base, c);
-  float s2 = tri_value(c, bc.t0, bc.t1, bc.t2);
-  if (FIRST) {
-    s0 *= scale;
-    s1 *= scale;
-    s2 *= scale;
-  }
-  o[lin] = u0 + s0;
-  o[g.V + lin] = u1 + s1;
-  o[2 * g.V + lin] = u2 + s2;
-}
-
-// Adjoint of one squaring step, accumulated into gout (zeroed beforehand):
-//   gout(y) += oscale * [g(y) + J_t(y)^T g(y)]           at y = x
-//   gout(corner_k(x)) += oscale * w_k(x) g(x)             (trilinear scatter)
-template <bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_exp_step_bwd(const float* __restrict__ ut,
-                                                         const float* __restrict__ gin,
-                                                         float* __restrict__ gout, Geom g,
-                                                         float scale, float oscale, uint32_t nbx,
-                                                         uint32_t total) {
-  const VoxelBlock vb = voxel_block(nbx, total);
-  if (vb.lin >= g.V) return;
-  const size_t off = static_cast<size_t>(vb.s) * 3 * g.V;
-  const float* f = ut + off;
-  const float* gi = gin + off;
-  float* go = gout + off;
-  const int lin = vb.lin;
-  int x0, x1, x2;
-  voxel_coords(g, lin, x0, x1, x2);
-  float u0 = f[lin], u1 = f[g.V + lin], u2 = f[2 * g.V + lin];
-  if (FIRST) {
-    u0 *= scale;
-    u1 *= scale;
-    u2 *= scale;
-  }
-  const BorderCell bc = border_cell(g, x0, x1, x2, u0, u1, u2);
-  const float g0 = gi[lin], g1 = gi[g.V + lin], g2 = gi[2 * g.V + lin];
-  const float gc[3] = {g0, g1, g2};
-  // J^T g: sum_c dS_c/dp_d * g_c
-  float jt0 = 0.0f, jt1 = 0.0f, jt2 = 0.0f;
-#pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    float cv[8];
-    corners_border(f + c * g.V, g, bc.base, cv);
-    const Tri t = tri_eval(cv, bc.t0, bc.t1, bc.t2);
-    jt0 += t.d0 * gc[c];
-    jt1 += t.d1 * gc[c];
-    jt2 += t.d2 * gc[c];
-  }
-  const float js = FIRST ? scale : 1.0f;
-  jt0 = bc.k0 ? 0.0f : jt0 * js;
-  jt1 = bc.k1 ? 0.0f : jt1 * js;
-  jt2 = bc.k2 ? 0.0f : jt2 * js;
-  unsafeAtomicAdd(go + lin, (g0 + jt0) * oscale);
-  unsafeAtomicAdd(go + g.V + lin, (g1 + jt1) * oscale);
-  unsafeAtomicAdd(go + 2 * g.V + lin, (g2 + jt2) * oscale);
-  // scatter of g through the trilinear weights
-  const float w0[2] = {1.0f - bc.t0, bc.t0};
-  const float w1[2] = {1.0f - bc.t1, bc.t1};
-  const float w2[2] = {1.0f - bc.t2, bc.t2};
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const float w = w0[a] * w1[b] * w2[e] * oscale;
-        const int idx = bc.base + a * g.plane + b * g.d2 + e;
-        unsafeAtomicAdd(go + idx, w * g0);
-        unsafeAtomicAdd(go + g.V + idx, w * g1);
-        unsafeAtomicAdd(go + 2 * g.V + idx, w * g2);
-      }
-    }
-  }
 }
 
 // -------------------------------------------------------------------- warp
@@ -365,76 +259,6 @@ RegW make_regw(const Geom& g, int ncomp, float lam) {
   r.lam = lam;
   r.on = lam != 0.0f;
   return r;
-}
-
-void launch_exp_step(const float* src, float* dst, const Geom& g, int n, bool first, float scale,
-                     hipStream_t st) {
-  const uint32_t nbx = blocks_for(g.V, kBlock), total = nbx * n;
-  prof_begin(st, KC_EXP_FWD);
-  if (first)
-    hipLaunchKernelGGL((k_exp_step<true>), dim3(total), dim3(kBlock), 0, st, src, dst, g, scale,
-                       nbx, total);
-  else
-    hipLaunchKernelGGL((k_exp_step<false>), dim3(total), dim3(kBlock), 0, st, src, dst, g, scale,
-                       nbx, total);
-  prof_end(st, KC_EXP_FWD);
-}
-
-void launch_exp_step_bwd(const float* ut, const float* gin, float* gout, const Geom& g, int n,
-                         bool first, float scale, float oscale, hipStream_t st) {
-  const uint32_t nbx = blocks_for(g.V, kBlock), total = nbx * n;
-  prof_begin(st, KC_EXP_BWD);
-  if (first)
-    hipLaunchKernelGGL((k_exp_step_bwd<true>), dim3(total), dim3(kBlock), 0, st, ut, gin, gout, g,
-                       scale, oscale, nbx, total);
-  else
-    hipLaunchKernelGGL((k_exp_step_bwd<false>), dim3(total), dim3(kBlock), 0, st, ut, gin, gout,
-                       g, scale, oscale, nbx, total);
-  prof_end(st, KC_EXP_BWD);
-}
-
-void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, const Geom& g, int n, int n_sq,
-                 hipStream_t st) {
-  const size_t fs = static_cast<size_t>(n) * 3 * g.V;
-  if (n_sq == 0) {
-    prof_begin(st, KC_MISC);
-    hipMemcpyAsync(u, v, fs * sizeof(float), hipMemcpyDeviceToDevice, st);
-    prof_end(st, KC_MISC);
-    return;
-  }
-  const float scale = ldexpf(1.0f, -n_sq);
-  const float* src = v;
-  for (int t = 0; t < n_sq; ++t) {
-    float* dst;
-    if (t == n_sq - 1)
-      dst = u;
-    else if (ckpt)
-      dst = ckpt + static_cast<size_t>(t) * fs;  // slot t holds u_{t+1}
-    else
-      dst = ((n_sq - 1 - t) % 2 == 0) ? u : tmp;  // ping-pong ending in u
-    launch_exp_step(src, dst, g, n, t == 0, scale, st);
-    src = dst;
-  }
-}
-
-void run_exp_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, float* tmp_a,
-                 float* tmp_b, const Geom& g, int n, int n_sq, hipStream_t st) {
-  const size_t fs = static_cast<size_t>(n) * 3 * g.V;
-  if (n_sq == 0) {
-    prof_begin(st, KC_MISC);
-    hipMemcpyAsync(g_v, g_u, fs * sizeof(float), hipMemcpyDeviceToDevice, st);
-    prof_end(st, KC_MISC);
-    return;
-  }
-  const float scale = ldexpf(1.0f, -n_sq);
-  const float* gin = g_u;
-  for (int t = n_sq - 1; t >= 0; --t) {
-    float* gout = (t == 0) ? g_v : (((n_sq - 1 - t) % 2 == 0) ? tmp_a : tmp_b);
-    const float* ut = (t == 0) ? v : ckpt + static_cast<size_t>(t - 1) * fs;
-    launch_fill_f32(gout, static_cast<long long>(fs), 0.0f, st);
-    launch_exp_step_bwd(ut, gin, gout, g, n, t == 0, scale, t == 0 ? scale : 1.0f, st);
-    gin = gout;
-  }
 }
 
 void launch_warp(const float* img, const float* u, float* out, const Geom& g, int n,

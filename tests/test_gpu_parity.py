@@ -109,6 +109,34 @@ def test_exp_svf_bwd(dev, n_sq):
         assert rel_l2(gv[i], O.exp_svf_bwd(steps, gu[i].astype(np.float64))) <= TOL_GRAD
 
 
+@pytest.mark.parametrize("dims,amp,corr", [((20, 30, 70), 12.0, 6.0), ((11, 9, 40), 40.0, 2.0),
+                                            ((40, 26, 33), 6.0, 3.0)])
+def test_exp_large_displacements(dev, dims, amp, corr):
+    """Displacements reaching across several 32 x 8 x 8 tiles, and (amp 40 on
+    a small volume) positions clamped at the border.
+
+    The adjoint is always compared with the oracle's adjoint of the squaring
+    steps the GPU computed (its checkpoints).  Where Exp(v) is a
+    diffeomorphism it is also compared end to end; the amp-40 field folds
+    (det J down to about -700, |grad u| about 26), and there the FP32 rounding
+    of the forward steps moves sample points across cell faces, which the
+    gradient of a piecewise-linear interpolant cannot be stable against.
+    """
+    v = random_velocity(130, 2, dims, amp, corr_len=corr)
+    gu = random_volume(131, v.shape, -1.0, 1.0)
+    vd = g(v, dev)
+    u, ck = D.exp_svf(vd, 7)
+    gv = h(D.exp_svf_bwd(vd, ck, g(gu, dev), 7))
+    u, ck = h(u), h(ck)
+    for i in range(2):
+        ref, steps = O.exp_svf(v[i].astype(np.float64))
+        assert rel_linf(u[i], ref) <= TOL_WARP
+        own = [v[i].astype(np.float64) / 2 ** 7] + [ck[t, i].astype(np.float64) for t in range(6)]
+        assert rel_l2(gv[i], O.exp_svf_bwd(own, gu[i].astype(np.float64))) <= TOL_GRAD
+        if O.jacobian_det(ref).min() > 0:
+            assert rel_l2(gv[i], O.exp_svf_bwd(steps, gu[i].astype(np.float64))) <= TOL_GRAD
+
+
 # ------------------------------------------------------------------- warp
 
 

@@ -113,14 +113,15 @@ int darc_exp_svf(const float* v, float* u, float* ckpt, int n, int d0, int d1, i
  * (zero along an axis whose coordinate was clamped) and w_k the trilinear
  * weights; dL/dv = g_0 / 2^n_sq.
  *   v     [n][3][V] in (u_0 is recomputed from it).
- *   ckpt  [n_sq-1][n][3][V] in: the checkpoints written by darc_exp_svf.
- *         Required when n_sq >= 2.
+ *   ckpt  [n_sq-1][n][3][V] in: the checkpoints written by darc_exp_svf, or
+ *         NULL: each u_t is then recomputed from v (n_sq (n_sq-1)/2 extra
+ *         squaring steps, two fields of scratch instead of n_sq-1 stored).
  *   g_u   [n][3][V] in.   g_v [n][3][V] out (overwritten, not accumulated).
- *   ws    scratch of darc_exp_svf_bwd_ws_bytes().
+ *   ws    scratch of darc_exp_svf_bwd_ws_bytes(..., has_ckpt = ckpt != NULL).
  * The scatter term is summed with LDS floating-point atomics: results are
  * reproducible only up to FP32 summation order.
  * ---------------------------------------------------------------------- */
-size_t darc_exp_svf_bwd_ws_bytes(int n, int d0, int d1, int d2, int n_sq);
+size_t darc_exp_svf_bwd_ws_bytes(int n, int d0, int d1, int d2, int n_sq, int has_ckpt);
 int darc_exp_svf_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, int n,
                      int d0, int d1, int d2, int n_sq, void* ws, size_t ws_bytes, void* stream);
 
@@ -232,6 +233,11 @@ typedef struct darc_state {
   float* atlas;        /* [V] atlas: A^k in, A^{k+1} out */
   float* u_hat;        /* [n][3][V] centred displacements out, or NULL */
   long long step;      /* Adam step count shared by all subjects, in/out (host) */
+  long long* step_dev; /* the same count in device memory (int64), or NULL.  When
+                          given, the bias corrections are formed on the device
+                          from it (and it is advanced by k2), so that a sweep
+                          captured in a graph can be replayed; `step` is then
+                          only advanced on the host for information */
   int n, d0, d1, d2;
 } darc_state;
 
@@ -265,6 +271,21 @@ size_t darc_sweep_ws_bytes(const darc_state* st, const darc_params* p);
  * after the sweep.  st->step is advanced by k2 on the host. */
 int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, size_t ws_bytes,
                void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_autotune -- picks the chunk length (planes per block along d0) of the
+ * marching kernels for this state's volume shape and batch size by timing
+ * the candidates 8, 16, 32, 64 on the sweep's workspace (the squaring steps
+ * and their adjoint; the window kernels when the metric is LNCC or v is
+ * smoothed).  v, m, s and the atlas are only read.  The choice is kept for
+ * every later call with the same shape and batch in this process.  Blocks
+ * until `stream` is idle; must not run while a stream is being captured.
+ * chosen (nullable) receives {squaring tz, window tz} (0 = not tuned).
+ * darc_autotune_clear forgets all choices.
+ * ---------------------------------------------------------------------- */
+int darc_autotune(darc_state* st, const darc_params* p, void* ws, size_t ws_bytes, void* stream,
+                  int* chosen);
+int darc_autotune_clear(void);
 
 /* ------------------------------------------------------------------------
  * Kernel timing for measurement.  When enabled, every kernel launched by the

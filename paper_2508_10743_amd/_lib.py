@@ -48,6 +48,7 @@ class DarcState(ctypes.Structure):
         ("atlas", c_void_p),
         ("u_hat", c_void_p),
         ("step", c_longlong),
+        ("step_dev", c_void_p),
         ("n", c_int),
         ("d0", c_int),
         ("d1", c_int),
@@ -85,7 +86,7 @@ PROTOTYPES = {
     "darc_last_error": (c_char_p, []),
     "darc_exp_svf_ws_bytes": (c_size_t, [_I, _I, _I, _I, _I, _I]),
     "darc_exp_svf": (c_int, [_P, _P, _P, _I, _I, _I, _I, _I, _P, _Z, _P]),
-    "darc_exp_svf_bwd_ws_bytes": (c_size_t, [_I, _I, _I, _I, _I]),
+    "darc_exp_svf_bwd_ws_bytes": (c_size_t, [_I, _I, _I, _I, _I, _I]),
     "darc_exp_svf_bwd": (c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _I, _P, _Z, _P]),
     "darc_warp3d": (c_int, [_P, _P, _P, _I, _I, _I, _I, _P]),
     "darc_warp3d_bwd": (c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _P]),
@@ -100,6 +101,9 @@ PROTOTYPES = {
     "darc_sizeof_params": (c_size_t, []),
     "darc_sweep_ws_bytes": (c_size_t, [POINTER(DarcState), POINTER(DarcParams)]),
     "darc_sweep": (c_int, [POINTER(DarcState), POINTER(DarcParams), _P, _P, _Z, _P]),
+    "darc_autotune": (c_int, [POINTER(DarcState), POINTER(DarcParams), _P, _Z, _P,
+                              POINTER(c_int)]),
+    "darc_autotune_clear": (c_int, []),
     "darc_profile_enable": (c_int, [_I]),
     "darc_profile_reset": (c_int, []),
     "darc_profile_num_classes": (c_int, []),

@@ -2,6 +2,7 @@
 // descent sweep (Eq. (3), Algorithm 1 of the paper) and kernel timing.
 #include <cstdarg>
 #include <cstdio>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -108,7 +109,7 @@ void prof_begin(hipStream_t s, int cls) {
   if (!g_prof_on) return;
   hipEvent_t a = take_event();
   if (!a) return;
-  hipEventRecord(a, s);
+  (void)hipEventRecord(a, s);
   g_prof_recs.push_back(ProfRec{cls, a, nullptr});
 }
 
@@ -118,8 +119,60 @@ void prof_end(hipStream_t s, int cls) {
   if (r.cls != cls || r.b != nullptr) return;
   hipEvent_t b = take_event();
   if (!b) return;
-  hipEventRecord(b, s);
+  (void)hipEventRecord(b, s);
   r.b = b;
+}
+
+// ------------------------------------------------------------ tuning table
+
+namespace {
+struct TuneEntry {
+  int kind, d0, d1, d2, n, tz;
+};
+std::mutex g_tune_mu;
+std::vector<TuneEntry> g_tune;
+}  // namespace
+
+int tuned_tz(int kind, const Geom& g, int n) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const TuneEntry& e : g_tune)
+    if (e.kind == kind && e.d0 == g.d0 && e.d1 == g.d1 && e.d2 == g.d2 && e.n == n) return e.tz;
+  return 0;
+}
+
+void set_tuned_tz(int kind, const Geom& g, int n, int tz) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (TuneEntry& e : g_tune)
+    if (e.kind == kind && e.d0 == g.d0 && e.d1 == g.d1 && e.d2 == g.d2 && e.n == n) {
+      e.tz = tz;
+      return;
+    }
+  g_tune.push_back(TuneEntry{kind, g.d0, g.d1, g.d2, n, tz});
+}
+
+void clear_tuned() {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune.clear();
+}
+
+// Runs `body` twice on `s` and returns the faster time in ms (or -1).
+template <class F>
+float time_on(hipStream_t s, F body) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return -1.0f;
+  float best = -1.0f;
+  body();  // warm-up
+  for (int r = 0; r < 2; ++r) {
+    (void)hipEventRecord(a, s);
+    body();
+    (void)hipEventRecord(b, s);
+    if (hipEventSynchronize(b) != hipSuccess) break;
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, a, b) == hipSuccess && (best < 0.0f || ms < best)) best = ms;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return best;
 }
 
 }  // namespace darc
@@ -152,11 +205,18 @@ int darc_exp_svf(const float* v, float* u, float* ckpt, int n, int d0, int d1, i
   return check_launch("darc_exp_svf");
 }
 
-size_t darc_exp_svf_bwd_ws_bytes(int n, int d0, int d1, int d2, int n_sq) {
+// gradient ping-pong buffers (plus two recompute buffers without
+// checkpoints), then the adjoint's tile records
+static size_t exp_bwd_fields(int n_sq, int has_ckpt) {
+  const size_t nf = n_sq >= 3 ? 2 : (n_sq == 2 ? 1 : 0);
+  return nf + ((!has_ckpt && n_sq >= 2) ? 2 : 0);
+}
+
+size_t darc_exp_svf_bwd_ws_bytes(int n, int d0, int d1, int d2, int n_sq, int has_ckpt) {
   if (n <= 0 || n_sq < 1 || d0 < 2 || d1 < 2 || d2 < 2) return 0;
   const size_t f = align256(field_bytes(n, d0, d1, d2));
-  const size_t nf = n_sq >= 3 ? 2 : (n_sq == 2 ? 1 : 0);
-  return nf * f + align256(exp_aux_bytes(make_geom(d0, d1, d2), n, n_sq));
+  return exp_bwd_fields(n_sq, has_ckpt) * f +
+         align256(exp_aux_bytes(make_geom(d0, d1, d2), n, n_sq));
 }
 
 int darc_exp_svf_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, int n, int d0,
@@ -167,18 +227,21 @@ int darc_exp_svf_bwd(const float* v, const float* ckpt, const float* g_u, float*
   if (g_v == g_u) return fail(DARC_EINVAL, "darc_exp_svf_bwd: g_v must not alias g_u");
   if (n_sq < 0 || n_sq > 16)
     return fail(DARC_EINVAL, "darc_exp_svf_bwd: n_sq = %d not in 0..16", n_sq);
-  if (n_sq >= 2 && !ckpt)
-    return fail(DARC_EINVAL, "darc_exp_svf_bwd: ckpt is required when n_sq >= 2");
-  const size_t need = darc_exp_svf_bwd_ws_bytes(n, d0, d1, d2, n_sq);
+  const int has_ckpt = ckpt != nullptr;
+  const size_t need = darc_exp_svf_bwd_ws_bytes(n, d0, d1, d2, n_sq, has_ckpt);
   DARC_TRY(check_ws("darc_exp_svf_bwd", ws, ws_bytes, need));
   const Geom g = make_geom(d0, d1, d2);
   char* w = static_cast<char*>(ws);
   const size_t f = align256(field_bytes(n, d0, d1, d2));
-  const size_t nf = n_sq >= 3 ? 2 : (n_sq == 2 ? 1 : 0);
-  float* tmp_a = nf >= 1 ? reinterpret_cast<float*>(w) : nullptr;
-  float* tmp_b = nf >= 2 ? reinterpret_cast<float*>(w + f) : nullptr;
-  int* aux = n_sq >= 1 ? reinterpret_cast<int*>(w + nf * f) : nullptr;
-  run_exp_bwd(v, ckpt, g_u, g_v, tmp_a, tmp_b, aux, false, g, n, n_sq, as_stream(stream));
+  const size_t nf = exp_bwd_fields(n_sq, has_ckpt);
+  float* buf[4] = {nullptr, nullptr, nullptr, nullptr};
+  for (size_t i = 0; i < nf; ++i) buf[i] = reinterpret_cast<float*>(w + i * f);
+  int* aux = reinterpret_cast<int*>(w + nf * f);
+  if (has_ckpt || n_sq < 2)
+    run_exp_bwd(v, ckpt, g_u, g_v, buf[0], buf[1], aux, false, g, n, n_sq, as_stream(stream));
+  else
+    run_exp_bwd_recompute(v, g_u, g_v, buf[0], buf[1], buf[2], buf[3], aux, g, n, n_sq,
+                          as_stream(stream));
   return check_launch("darc_exp_svf_bwd");
 }
 
@@ -310,7 +373,7 @@ namespace {
 
 struct SweepLayout {
   int B;
-  size_t ckpt, aux, uN, gU, gA, gB, gV, iw, fields, vtmp, uhat, sloss, total;
+  size_t ckpt, aux, uN, gU, gA, gB, gV, iw, fields, vtmp, uhat, sloss, bc, total;
 };
 
 SweepLayout sweep_layout(const darc_state* st, const darc_params* p) {
@@ -338,6 +401,7 @@ SweepLayout sweep_layout(const darc_state* st, const darc_params* p) {
   L.vtmp = take(p->smooth_sigma > 0.0f ? fb : 0);
   L.uhat = take(st->u_hat ? 0 : static_cast<size_t>(n) * 3 * V * sizeof(float));
   L.sloss = take(static_cast<size_t>(n) * sizeof(double));
+  L.bc = take(static_cast<size_t>(p->k2) * 2 * sizeof(float));
   L.total = off;
   return L;
 }
@@ -410,6 +474,7 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
   float* vtmp = reinterpret_cast<float*>(w + L.vtmp);
   float* uh = st->u_hat ? st->u_hat : reinterpret_cast<float*>(w + L.uhat);
   double* sloss = reinterpret_cast<double*>(w + L.sloss);
+  float* bc = reinterpret_cast<float*>(w + L.bc);
   const RegW rw = make_regw(g, 3, p->lam);
   const bool lncc = p->metric == DARC_LNCC;
   const bool smooth = p->smooth_sigma > 0.0f;
@@ -421,6 +486,7 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
     launch_fill_f32(st->v, cnt, 0.0f, s);
     launch_fill_f32(st->m, cnt, 0.0f, s);
     launch_fill_f32(st->s, cnt, 0.0f, s);
+    if (st->step_dev) launch_fill_f64(reinterpret_cast<double*>(st->step_dev), 1, 0.0, s);
     step = 0;
   }
 
@@ -444,16 +510,18 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
       }
       run_exp_bwd(vb, ckpt, gU, gV, gA, gB, aux, true, g, nb, N, s);
       const long long cnt = static_cast<long long>(nb) * fsv;
-      if (smooth) {
-        launch_adam(vb, vtmp, mb, sb, gV, cnt, step + k + 1, p->lr, p->beta1, p->beta2,
+      float* vdst = smooth ? vtmp : vb;
+      if (st->step_dev)
+        launch_adam_dev(vb, vdst, mb, sb, gV, cnt, st->step_dev, k, bc + 2 * k, p->lr, p->beta1,
+                        p->beta2, p->adam_eps, s);
+      else
+        launch_adam(vb, vdst, mb, sb, gV, cnt, step + k + 1, p->lr, p->beta1, p->beta2,
                     p->adam_eps, s);
-        launch_gauss(vtmp, vb, p->smooth_sigma, g, nb * 3, s);
-      } else {
-        launch_adam(vb, vb, mb, sb, gV, cnt, step + k + 1, p->lr, p->beta1, p->beta2, p->adam_eps,
-                    s);
-      }
+      if (smooth) launch_gauss(vtmp, vb, p->smooth_sigma, g, nb * 3, s);
     }
   }
+
+  if (st->step_dev) launch_step_add(st->step_dev, k2, s);
 
   // step 2: u_i = Exp(v_i), centrality activation
   if (p->center_mode == DARC_CENTER_VELOCITY) launch_center(st->v, nullptr, g, n, s);
@@ -482,6 +550,85 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
   launch_sum_f64(sloss, n, 1.0 / n, losses + static_cast<size_t>(n) * k2, s);
   st->step = step + k2;
   return check_launch("darc_sweep");
+}
+
+// -------------------------------------------------------------- autotuning
+
+
+int darc_autotune(darc_state* st, const darc_params* p, void* ws, size_t ws_bytes, void* stream,
+                  int* chosen) {
+  DARC_TRY(check_sweep(st, p));
+  const SweepLayout L = sweep_layout(st, p);
+  DARC_TRY(check_ws("darc_autotune", ws, ws_bytes, L.total));
+  hipStream_t s = as_stream(stream);
+  const Geom g = make_geom(st->d0, st->d1, st->d2);
+  const int B = L.B, N = p->n_sq;
+  char* w = static_cast<char*>(ws);
+  float* ckpt = N >= 2 ? reinterpret_cast<float*>(w + L.ckpt) : nullptr;
+  int* aux = reinterpret_cast<int*>(w + L.aux);
+  float* uN = reinterpret_cast<float*>(w + L.uN);
+  float* gU = reinterpret_cast<float*>(w + L.gU);
+  float* gA = reinterpret_cast<float*>(w + L.gA);
+  float* gB = reinterpret_cast<float*>(w + L.gB);
+  float* gV = reinterpret_cast<float*>(w + L.gV);
+  const int cands[4] = {8, 16, 32, 64};
+  int pick[2] = {0, 0};
+  // squaring steps and their adjoint on the first batch (u_N stands in for dL/du)
+  {
+    float best = -1.0f;
+    for (int tz : cands) {
+      set_tuned_tz(TUNE_EXP, g, B, tz);
+      const float ms = time_on(s, [&] {
+        run_exp_fwd(st->v, uN, ckpt, nullptr, aux, g, B, N, s);
+        (void)hipMemcpyAsync(gU, uN, static_cast<size_t>(B) * 3 * g.V * sizeof(float),
+                             hipMemcpyDeviceToDevice, s);
+        run_exp_bwd(st->v, ckpt, gU, gV, gA, gB, aux, true, g, B, N, s);
+      });
+      if (ms >= 0.0f && (best < 0.0f || ms < best)) {
+        best = ms;
+        pick[0] = tz;
+      }
+    }
+    set_tuned_tz(TUNE_EXP, g, B, pick[0]);
+  }
+  // window kernels: LNCC statistics and adjoint, or the Gaussian on v
+  const bool lncc = p->metric == DARC_LNCC, smooth = p->smooth_sigma > 0.0f;
+  if (lncc || smooth) {
+    float* iw = reinterpret_cast<float*>(w + L.iw);
+    float* fields = reinterpret_cast<float*>(w + L.fields);
+    double* sloss = reinterpret_cast<double*>(w + L.sloss);
+    const RegW rw = make_regw(g, 3, p->lam);
+    float best = -1.0f;
+    for (int tz : cands) {
+      set_tuned_tz(TUNE_WINDOW, g, B, tz);
+      set_tuned_tz(TUNE_WINDOW, g, 3 * B, tz);
+      const float ms = time_on(s, [&] {
+        if (lncc) {
+          launch_warp(st->images, uN, iw, g, B, s);
+          launch_lncc_fwd(iw, st->atlas, fields, sloss, 1, p->win, p->ncc_eps, g, B, s);
+          launch_lncc_bwd_fused(fields, iw, st->atlas, st->images, uN, gU, sloss, 1, rw, p->win, g,
+                                B, s);
+        }
+        if (smooth) launch_gauss(st->v, gA, p->smooth_sigma, g, 3 * B, s);
+      });
+      if (ms >= 0.0f && (best < 0.0f || ms < best)) {
+        best = ms;
+        pick[1] = tz;
+      }
+    }
+    set_tuned_tz(TUNE_WINDOW, g, B, pick[1]);
+    set_tuned_tz(TUNE_WINDOW, g, 3 * B, pick[1]);
+  }
+  if (chosen) {
+    chosen[0] = pick[0];
+    chosen[1] = pick[1];
+  }
+  return check_launch("darc_autotune");
+}
+
+int darc_autotune_clear(void) {
+  clear_tuned();
+  return ok();
 }
 
 // ------------------------------------------------------------- timing API

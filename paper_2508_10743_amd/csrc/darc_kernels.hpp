@@ -27,6 +27,11 @@ void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, int* aux, co
 void run_exp_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, float* tmp_a,
                  float* tmp_b, int* aux, bool aux_ready, const Geom& g, int n, int n_sq,
                  hipStream_t st);
+// The same adjoint without checkpoints: each u_t is recomputed from v into
+// rec_a / rec_b ([n][3][V] each); n_sq >= 2.
+void run_exp_bwd_recompute(const float* v, const float* g_u, float* g_v, float* tmp_a,
+                           float* tmp_b, float* rec_a, float* rec_b, int* aux, const Geom& g,
+                           int n, int n_sq, hipStream_t st);
 
 // --- warp -----------------------------------------------------------------
 void launch_warp(const float* img, const float* u, float* out, const Geom& g, int n,
@@ -78,6 +83,23 @@ void launch_adam(const float* v_in, float* v_out, float* m, float* s, const floa
 void launch_center(float* u, float* mean_out, const Geom& g, int n, hipStream_t st);
 void launch_atlas(const float* images, const float* u, const float* mean, float* atlas,
                   const Geom& g, int n, hipStream_t st);
+
+// --- chunk lengths of the marching kernels ---------------------------------
+// Planes per block along d0.  0 = not tuned (the launchers then use their own
+// heuristic); set by darc_autotune for one volume shape and batch size.
+enum TuneKind : int { TUNE_EXP = 0, TUNE_WINDOW = 1, TUNE_NUM };
+int tuned_tz(int kind, const Geom& g, int n);
+void set_tuned_tz(int kind, const Geom& g, int n, int tz);
+void clear_tuned();
+
+// --- Adam with a device-side step count (graph-capturable) ------------------
+// The update of inner iteration k uses t = *step_dev + k + 1: bc[0] = 1 - b1^t
+// and bc[1] = 1 - b2^t are formed on the device first.  launch_step_add then
+// advances *step_dev once all subjects have taken their steps.
+void launch_adam_dev(const float* v_in, float* v_out, float* m, float* s, const float* g,
+                     long long count, const long long* step_dev, int k, float* bc, float lr,
+                     double b1, double b2, float eps, hipStream_t st);
+void launch_step_add(long long* step_dev, long long k, hipStream_t st);
 
 // --- small helpers --------------------------------------------------------
 void launch_fill_f32(float* p, long long count, float value, hipStream_t st);

@@ -74,27 +74,69 @@ __device__ __forceinline__ int wave_max(int x) {
   return x;
 }
 
-// MODE 0: squaring step only; 1: step and cell offsets; 2: cell offsets only.
-// boxes[(s * ntiles + tile) * 8 + {0,1,2}] = min over the tile's voxels x of
-// i_d(x) - x_d along d0, d1, d2 (i = cell index of x + u(x)), [.. + {3,4,5}] =
-// the max; so the corners a voxel x touches lie in x + [min, max + 1].
-// reach[s * 8 + d] = max(0, -min over tiles of the min offset) and
-// reach[s * 8 + 3 + d] = max(0, max over tiles of the max offset + 1): how far
-// below / above itself any voxel of the subject can scatter (zeroed before).
-template <bool FIRST, int MODE>
-__global__ __launch_bounds__(ENT) void k_exp_fwd(const float* __restrict__ src,
-                                                 float* __restrict__ dst, TileGeom tg, float scale,
-                                                 int* __restrict__ boxes, int* __restrict__ reach) {
+// Per-tile records used by the adjoint: boxes[(s * ntiles + tile) * 8 + {0,1,2}]
+// = min over the tile's voxels x of i_d(x) - x_d along d0, d1, d2 (i = cell
+// index of x + u(x)), [.. + {3,4,5}] = the max; so the corners a voxel x
+// touches lie in x + [min, max + 1].  reach[s * 8 + d] = max(0, -min over tiles
+// of the min offset) and reach[s * 8 + 3 + d] = max(0, max over tiles of the
+// max offset + 1): how far below / above itself any voxel of the subject can
+// scatter (zeroed before).  Tiles are 32 (d2) x 8 (d1) x 8 (d0).
+__device__ __forceinline__ void write_record(int mn0, int mn1, int mn2, int mx0, int mx1, int mx2,
+                                             int (*red)[ENT / 64], int* __restrict__ boxes,
+                                             int* __restrict__ reach, int s, int tile,
+                                             int ntiles) {
+  mn0 = wave_min(mn0);
+  mn1 = wave_min(mn1);
+  mn2 = wave_min(mn2);
+  mx0 = wave_max(mx0);
+  mx1 = wave_max(mx1);
+  mx2 = wave_max(mx2);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    red[0][w] = mn0;
+    red[1][w] = mn1;
+    red[2][w] = mn2;
+    red[3][w] = mx0;
+    red[4][w] = mx1;
+    red[5][w] = mx2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int r[6];
+    for (int k = 0; k < 6; ++k) r[k] = red[k][0];
+    for (int i = 1; i < ENT / 64; ++i) {
+      for (int k = 0; k < 3; ++k) r[k] = min(r[k], red[k][i]);
+      for (int k = 3; k < 6; ++k) r[k] = max(r[k], red[k][i]);
+    }
+    int* bx = boxes + (static_cast<size_t>(s) * ntiles + tile) * 8;
+    int* rc = reach + s * 8;
+    for (int d = 0; d < 3; ++d) {
+      bx[d] = r[d];
+      bx[3 + d] = r[3 + d];
+      // the reaches only grow and saturate early: skip the atomic (which
+      // every block of the subject would aim at the same word) unless this
+      // record can raise it; a stale read only costs a redundant atomic
+      const int lo = max(0, -r[d]), hi = max(0, r[3 + d] + 1);
+      if (lo > *reinterpret_cast<volatile int*>(rc + d)) atomicMax(rc + d, lo);
+      if (hi > *reinterpret_cast<volatile int*>(rc + 3 + d)) atomicMax(rc + 3 + d, hi);
+    }
+  }
+  __syncthreads();
+}
+
+// Records only (for an adjoint whose forward pass did not record them).
+template <bool FIRST>
+__global__ __launch_bounds__(ENT) void k_exp_rec(const float* __restrict__ src, TileGeom tg,
+                                                 float scale, int* __restrict__ boxes,
+                                                 int* __restrict__ reach) {
   __shared__ int red[6][ENT / 64];
   const Geom& g = tg.g;
   const TileId id = tile_id(tg);
   const int lx = threadIdx.x % ETX, ly = threadIdx.x / ETX;
   const int x2 = id.ox + lx, x1 = id.oy + ly;
   const bool colv = (x2 < g.d2) && (x1 < g.d1);
-  const size_t off = static_cast<size_t>(id.s) * 3 * g.V;
-  const float* f = src + off;
+  const float* f = src + static_cast<size_t>(id.s) * 3 * g.V;
   int mn0 = INT_MAX, mn1 = INT_MAX, mn2 = INT_MAX, mx0 = INT_MIN, mx1 = INT_MIN, mx2 = INT_MIN;
-#pragma unroll 2
   for (int k = 0; k < ETZ; ++k) {
     const int x0 = id.oz + k;
     if (colv && x0 < g.d0) {
@@ -106,69 +148,198 @@ __global__ __launch_bounds__(ENT) void k_exp_fwd(const float* __restrict__ src,
         u2 *= scale;
       }
       const BorderCell bc = border_cell(g, x0, x1, x2, u0, u1, u2);
-      if (MODE != 2) {
-        float c[8];
-        corners_border(f, g, bc.base, c);
-        float s0 = tri_value(c, bc.t0, bc.t1, bc.t2);
-        corners_border(f + g.V, g, bc.base, c);
-        float s1 = tri_value(c, bc.t0, bc.t1, bc.t2);
-        corners_border(f + 2 * g.V, g, bc.base, c);
-        float s2 = tri_value(c, bc.t0, bc.t1, bc.t2);
-        if (FIRST) {
-          s0 *= scale;
-          s1 *= scale;
-          s2 *= scale;
-        }
-        float* o = dst + off;
-        o[lin] = u0 + s0;
-        o[g.V + lin] = u1 + s1;
-        o[2 * g.V + lin] = u2 + s2;
+      mn0 = min(mn0, bc.i0 - x0);
+      mn1 = min(mn1, bc.i1 - x1);
+      mn2 = min(mn2, bc.i2 - x2);
+      mx0 = max(mx0, bc.i0 - x0);
+      mx1 = max(mx1, bc.i1 - x1);
+      mx2 = max(mx2, bc.i2 - x2);
+    }
+  }
+  write_record(mn0, mn1, mn2, mx0, mx1, mx2, red, boxes, reach, id.s, id.tile, tg.ntiles);
+}
+
+// ---------------------------------------------------------------------------
+// Marching kernels: a block owns a 32 x 8 column of the (d1, d2) plane and
+// walks a chunk of planes along d0.  A ring of the last planes of u (and g)
+// with a one-voxel halo in d1 and d2 lives in LDS; the next plane is loaded
+// into registers while the current one is computed, so every value is read
+// from memory once and loads overlap compute.
+constexpr int MHX = ETX + 2, MHY = ETY + 2;  // staged plane with halo
+constexpr int MHP = MHX * MHY;               // 340 positions
+constexpr int MNJ = (MHP + ENT - 1) / ENT;   // positions per thread (2)
+
+struct MarchGeom {
+  TileGeom rec;  // record tiling (same 32 x 8 columns, 8 planes per record)
+  int nzc, tz;   // chunks along d0 and their length (a multiple of ETZ)
+  uint32_t total;
+};
+
+MarchGeom make_march(const TileGeom& tg, int n, int tz) {
+  MarchGeom m;
+  m.rec = tg;
+  m.tz = tz;
+  m.nzc = (tg.g.d0 + tz - 1) / tz;
+  m.total = static_cast<uint32_t>(tg.ntx) * tg.nty * m.nzc * n;
+  return m;
+}
+
+struct MarchId {
+  int s, tx, ty, ox, oy, z0, z1;
+};
+
+__device__ __forceinline__ MarchId march_id(const MarchGeom& m) {
+  uint32_t b = xcd_remap(blockIdx.x, m.total);
+  MarchId id;
+  id.tx = static_cast<int>(b % m.rec.ntx);
+  b /= m.rec.ntx;
+  id.ty = static_cast<int>(b % m.rec.nty);
+  b /= m.rec.nty;
+  const int zc = static_cast<int>(b % m.nzc);
+  id.s = static_cast<int>(b / m.nzc);
+  id.ox = id.tx * ETX;
+  id.oy = id.ty * ETY;
+  id.z0 = zc * m.tz;
+  id.z1 = min(id.z0 + m.tz, m.rec.g.d0);
+  return id;
+}
+
+// Halo positions of one plane handled by this thread: in-plane offset of the
+// (clamped) voxel, and whether the unclamped voxel exists.
+struct HaloPos {
+  int off[MNJ];
+  bool use[MNJ];     // position index < MHP
+  bool inside[MNJ];  // the voxel is inside the volume (d1, d2)
+  int y[MNJ], x[MNJ];
+};
+
+__device__ __forceinline__ HaloPos halo_pos(const Geom& g, int oy, int ox) {
+  HaloPos h;
+#pragma unroll
+  for (int j = 0; j < MNJ; ++j) {
+    const int e = threadIdx.x + j * ENT;
+    h.use[j] = e < MHP;
+    const int hy = e / MHX, hx = e - hy * MHX;
+    const int y = oy - 1 + hy, x = ox - 1 + hx;
+    h.y[j] = y;
+    h.x[j] = x;
+    h.inside[j] = y >= 0 && y < g.d1 && x >= 0 && x < g.d2;
+    h.off[j] = min(max(y, 0), g.d1 - 1) * g.d2 + min(max(x, 0), g.d2 - 1);
+  }
+  return h;
+}
+
+// Forward squaring step, marching.  REC: also write the per-tile records.
+template <bool FIRST, bool REC>
+__global__ __launch_bounds__(ENT) void k_exp_fwd(const float* __restrict__ src,
+                                                 float* __restrict__ dst, MarchGeom m,
+                                                 float scale, int* __restrict__ boxes,
+                                                 int* __restrict__ reach) {
+  __shared__ float ring[3][3][MHP];  // [plane slot][component][position]
+  __shared__ int red[6][ENT / 64];
+  const Geom& g = m.rec.g;
+  const MarchId id = march_id(m);
+  const size_t off = static_cast<size_t>(id.s) * 3 * g.V;
+  const float* f = src + off;
+  float* o = dst + off;
+  const int lx = threadIdx.x % ETX, ly = threadIdx.x / ETX;
+  const HaloPos hp = halo_pos(g, id.oy, id.ox);
+  float pre[MNJ][3];
+  auto load_plane = [&](int z) {
+    const int zc = min(max(z, 0), g.d0 - 1);
+#pragma unroll
+    for (int j = 0; j < MNJ; ++j)
+      if (hp.use[j]) {
+        const int lin = zc * g.plane + hp.off[j];
+        pre[j][0] = f[lin];
+        pre[j][1] = f[g.V + lin];
+        pre[j][2] = f[2 * g.V + lin];
       }
-      if (MODE != 0) {
-        mn0 = min(mn0, bc.i0 - x0);
+  };
+  auto store_plane = [&](int z) {
+    const int sl = (z + 3) % 3;
+#pragma unroll
+    for (int j = 0; j < MNJ; ++j)
+      if (hp.use[j]) {
+        const int e = threadIdx.x + j * ENT;
+        ring[sl][0][e] = pre[j][0];
+        ring[sl][1][e] = pre[j][1];
+        ring[sl][2][e] = pre[j][2];
+      }
+  };
+  load_plane(id.z0 - 1);
+  store_plane(id.z0 - 1);
+  load_plane(id.z0);
+  store_plane(id.z0);
+  load_plane(id.z0 + 1);
+  const int x2 = id.ox + lx, x1 = id.oy + ly;
+  const bool colv = (x2 < g.d2) && (x1 < g.d1);
+  const int own = (ly + 1) * MHX + lx + 1;
+  int mn0 = INT_MAX, mn1 = INT_MAX, mn2 = INT_MAX, mx0 = INT_MIN, mx1 = INT_MIN, mx2 = INT_MIN;
+  for (int z = id.z0; z < id.z1; ++z) {
+    store_plane(z + 1);
+    __syncthreads();
+    if (z + 2 <= id.z1) load_plane(z + 2);
+    if (colv) {
+      const int sz = z % 3;
+      float u0 = ring[sz][0][own], u1 = ring[sz][1][own], u2 = ring[sz][2][own];
+      if (FIRST) {
+        u0 *= scale;
+        u1 *= scale;
+        u2 *= scale;
+      }
+      const BorderCell bc = border_cell(g, z, x1, x2, u0, u1, u2);
+      const int c0 = bc.i0 - z + 1, c1 = bc.i1 - id.oy + 1, c2 = bc.i2 - id.ox + 1;
+      float r[3];
+      if (c0 >= 0 && c0 <= 1 && c1 >= 0 && c1 + 1 < MHY && c2 >= 0 && c2 + 1 < MHX) {
+        const int sa = (bc.i0 + 3) % 3, sb = (bc.i0 + 4) % 3;
+        const int pb = c1 * MHX + c2;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          float cv[8];
+          cv[0] = ring[sa][c][pb];
+          cv[1] = ring[sa][c][pb + 1];
+          cv[2] = ring[sa][c][pb + MHX];
+          cv[3] = ring[sa][c][pb + MHX + 1];
+          cv[4] = ring[sb][c][pb];
+          cv[5] = ring[sb][c][pb + 1];
+          cv[6] = ring[sb][c][pb + MHX];
+          cv[7] = ring[sb][c][pb + MHX + 1];
+          r[c] = tri_value(cv, bc.t0, bc.t1, bc.t2);
+        }
+      } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          float cv[8];
+          corners_border(f + c * g.V, g, bc.base, cv);
+          r[c] = tri_value(cv, bc.t0, bc.t1, bc.t2);
+        }
+      }
+      if (FIRST) {
+        r[0] *= scale;
+        r[1] *= scale;
+        r[2] *= scale;
+      }
+      const int lin = z * g.plane + x1 * g.d2 + x2;
+      o[lin] = u0 + r[0];
+      o[g.V + lin] = u1 + r[1];
+      o[2 * g.V + lin] = u2 + r[2];
+      if (REC) {
+        mn0 = min(mn0, bc.i0 - z);
         mn1 = min(mn1, bc.i1 - x1);
         mn2 = min(mn2, bc.i2 - x2);
-        mx0 = max(mx0, bc.i0 - x0);
+        mx0 = max(mx0, bc.i0 - z);
         mx1 = max(mx1, bc.i1 - x1);
         mx2 = max(mx2, bc.i2 - x2);
       }
     }
-  }
-  if (MODE != 0) {
-    mn0 = wave_min(mn0);
-    mn1 = wave_min(mn1);
-    mn2 = wave_min(mn2);
-    mx0 = wave_max(mx0);
-    mx1 = wave_max(mx1);
-    mx2 = wave_max(mx2);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) {
-      red[0][w] = mn0;
-      red[1][w] = mn1;
-      red[2][w] = mn2;
-      red[3][w] = mx0;
-      red[4][w] = mx1;
-      red[5][w] = mx2;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int i = 1; i < ENT / 64; ++i) {
-        red[0][0] = min(red[0][0], red[0][i]);
-        red[1][0] = min(red[1][0], red[1][i]);
-        red[2][0] = min(red[2][0], red[2][i]);
-        red[3][0] = max(red[3][0], red[3][i]);
-        red[4][0] = max(red[4][0], red[4][i]);
-        red[5][0] = max(red[5][0], red[5][i]);
-      }
-      int* bx = boxes + (static_cast<size_t>(id.s) * tg.ntiles + id.tile) * 8;
-      int* rc = reach + id.s * 8;
-#pragma unroll
-      for (int d = 0; d < 3; ++d) {
-        bx[d] = red[d][0];
-        bx[3 + d] = red[3 + d][0];
-        atomicMax(rc + d, max(0, -red[d][0]));
-        atomicMax(rc + 3 + d, max(0, red[3 + d][0] + 1));
-      }
+    if (REC && ((z + 1) % ETZ == 0 || z + 1 == id.z1)) {
+      const int tile = ((z / ETZ) * m.rec.nty + id.ty) * m.rec.ntx + id.tx;
+      write_record(mn0, mn1, mn2, mx0, mx1, mx2, red, boxes, reach, id.s, tile, m.rec.ntiles);
+      mn0 = mn1 = mn2 = INT_MAX;
+      mx0 = mx1 = mx2 = INT_MIN;
+    } else {
+      __syncthreads();
     }
   }
 }
@@ -206,11 +377,17 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
                                                  const int* __restrict__ boxes,
                                                  const int* __restrict__ reach) {
   __shared__ int cnt[NCELL];
-  __shared__ float sdat[KSLOT][6][NCELL];
+  __shared__ float4 sdat4[KSLOT][NCELL];  // t0, t1, t2, g0 of a binned source
+  __shared__ float2 sdat2[KSLOT][NCELL];  // g1, g2
   __shared__ float ovf[3][BTILE];
+  __shared__ int ubox[6];  // union of the candidate source sub-boxes
   const TileGeom& tg = bg.src;
   const Geom& g = tg.g;
-  const uint32_t bid = xcd_remap(blockIdx.x, bg.total);
+  // persistent: each block walks a contiguous run of tiles (runs of
+  // neighbouring blocks sit on the same XCD)
+  const uint32_t run = (bg.total + gridDim.x - 1) / gridDim.x;
+  const uint32_t first = xcd_remap(blockIdx.x, gridDim.x) * run;
+  for (uint32_t bid = first; bid < min(first + run, bg.total); ++bid) {
   const int s = static_cast<int>(bid / bg.ntiles);
   const int tile = static_cast<int>(bid - static_cast<uint32_t>(s) * bg.ntiles);
   const int ox = (tile % bg.ntx) * BTX;
@@ -220,6 +397,15 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
   const int L1 = min(oy + BTY, g.d1) - 1;
   const int L2 = min(ox + BTX, g.d2) - 1;
   const int lx = threadIdx.x % BTX, ly = (threadIdx.x / BTX) % BTY, lz = threadIdx.x / (BTX * BTY);
+  {
+    // subjects with reach 1 everywhere are handled by the marching kernel:
+    // skip the rest of this subject's tiles
+    const int* rc = reach + s * 8;
+    if (rc[0] <= 1 && rc[1] <= 1 && rc[2] <= 1 && rc[3] <= 1 && rc[4] <= 1 && rc[5] <= 1) {
+      bid = static_cast<uint32_t>(s + 1) * bg.ntiles - 1;
+      continue;
+    }
+  }
   const size_t off = static_cast<size_t>(s) * 3 * g.V;
   const float* f = ut + off;
   const float* gi = gin + off;
@@ -227,6 +413,7 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
 
   for (int i = threadIdx.x; i < NCELL; i += BNT) cnt[i] = 0;
   for (int i = threadIdx.x; i < 3 * BTILE; i += BNT) (&ovf[0][0])[i] = 0.0f;
+  if (threadIdx.x < 6) ubox[threadIdx.x] = threadIdx.x < 3 ? INT_MAX : INT_MIN;
 
   // 1. direct term of the two voxels (z = 2 lz, 2 lz + 1) this thread owns
   float acc[2][3];
@@ -262,74 +449,121 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
   }
   __syncthreads();
 
-  // 2. bin the source voxels whose cell base lies in [O - 1, L]: a source x of
-  //    forward tile s has cell base in x + [min, max] (recorded offsets), so
-  //    only x_d in [O_d - 1 - max_d, L_d - min_d] qualify.  Candidate forward
-  //    tiles come from the subject-wide reach.
+  // 2. bin the source voxels whose cell base lies in [O - 1, L].  A source x
+  //    of forward tile s has its cell base in x + [min, max] (the recorded
+  //    offsets), so only x_d in [O_d - 1 - max_d, L_d - min_d] can qualify;
+  //    candidate forward tiles come from the subject-wide reach.  The union
+  //    box of those sub-boxes is swept as one flattened range, four sources
+  //    per thread at a time with all their loads issued before any is used.
   const int* rc = reach + s * 8;
   const int lo0 = max(0, oz - rc[3]) / ETZ, hi0 = min(tg.ntz - 1, (L0 + rc[0]) / ETZ);
   const int lo1 = max(0, oy - rc[4]) / ETY, hi1 = min(tg.nty - 1, (L1 + rc[1]) / ETY);
   const int lo2 = max(0, ox - rc[5]) / ETX, hi2 = min(tg.ntx - 1, (L2 + rc[2]) / ETX);
   const int* sbox = boxes + static_cast<size_t>(s) * tg.ntiles * 8;
-  for (int sz = lo0; sz <= hi0; ++sz) {
-    for (int sy = lo1; sy <= hi1; ++sy) {
-      for (int sx = lo2; sx <= hi2; ++sx) {
-        const int* bx = sbox + ((sz * tg.nty + sy) * tg.ntx + sx) * 8;
-        const int a0 = max(sz * ETZ, oz - 1 - bx[3]);
-        const int b0 = min(min(sz * ETZ + ETZ, g.d0) - 1, L0 - bx[0]);
-        const int a1 = max(sy * ETY, oy - 1 - bx[4]);
-        const int b1 = min(min(sy * ETY + ETY, g.d1) - 1, L1 - bx[1]);
-        const int a2 = max(sx * ETX, ox - 1 - bx[5]);
-        const int b2 = min(min(sx * ETX + ETX, g.d2) - 1, L2 - bx[2]);
-        if (a0 > b0 || a1 > b1 || a2 > b2) continue;
-        const int e2 = b2 - a2 + 1, e1 = b1 - a1 + 1;
-        const int nvox = (b0 - a0 + 1) * e1 * e2;
-        for (int q = threadIdx.x; q < nvox; q += BNT) {
-          const int r = q / e2;
-          const int x2 = a2 + (q - r * e2);
-          const int r1 = r / e1;
-          const int x1 = a1 + (r - r1 * e1);
-          const int x0 = a0 + r1;
-          const int lin = (x0 * g.d1 + x1) * g.d2 + x2;
-          float u0 = f[lin], u1 = f[g.V + lin], u2 = f[2 * g.V + lin];
-          if (FIRST) {
-            u0 *= scale;
-            u1 *= scale;
-            u2 *= scale;
-          }
-          const BorderCell bc = border_cell(g, x0, x1, x2, u0, u1, u2);
-          // local cell index: base - (O - 1), in [0, C)
-          const int c0 = bc.i0 - oz + 1, c1 = bc.i1 - oy + 1, c2 = bc.i2 - ox + 1;
-          if (c0 < 0 || c0 >= CZ || c1 < 0 || c1 >= CY || c2 < 0 || c2 >= CX) continue;
-          const int ci = (c0 * CY + c1) * CX + c2;
-          const float g0 = gi[lin], g1 = gi[g.V + lin], g2 = gi[2 * g.V + lin];
-          const int slot = atomicAdd(&cnt[ci], 1);
-          if (slot < KSLOT) {
-            sdat[slot][0][ci] = bc.t0;
-            sdat[slot][1][ci] = bc.t1;
-            sdat[slot][2][ci] = bc.t2;
-            sdat[slot][3][ci] = g0;
-            sdat[slot][4][ci] = g1;
-            sdat[slot][5][ci] = g2;
-          } else {
-            const float w0[2] = {1.0f - bc.t0, bc.t0};
-            const float w1[2] = {1.0f - bc.t1, bc.t1};
-            const float w2[2] = {1.0f - bc.t2, bc.t2};
+  {
+    const int nc2 = hi2 - lo2 + 1, nc1 = hi1 - lo1 + 1;
+    const int ncand = (hi0 - lo0 + 1) * nc1 * nc2;
+    for (int ic = threadIdx.x; ic < ncand; ic += BNT) {
+      const int sx = lo2 + ic % nc2;
+      const int rr = ic / nc2;
+      const int sy = lo1 + rr % nc1;
+      const int sz = lo0 + rr / nc1;
+      const int* bx = sbox + ((sz * tg.nty + sy) * tg.ntx + sx) * 8;
+      const int a0 = max(sz * ETZ, oz - 1 - bx[3]);
+      const int b0 = min(min(sz * ETZ + ETZ, g.d0) - 1, L0 - bx[0]);
+      const int a1 = max(sy * ETY, oy - 1 - bx[4]);
+      const int b1 = min(min(sy * ETY + ETY, g.d1) - 1, L1 - bx[1]);
+      const int a2 = max(sx * ETX, ox - 1 - bx[5]);
+      const int b2 = min(min(sx * ETX + ETX, g.d2) - 1, L2 - bx[2]);
+      if (a0 <= b0 && a1 <= b1 && a2 <= b2) {
+        atomicMin(&ubox[0], a0);
+        atomicMin(&ubox[1], a1);
+        atomicMin(&ubox[2], a2);
+        atomicMax(&ubox[3], b0);
+        atomicMax(&ubox[4], b1);
+        atomicMax(&ubox[5], b2);
+      }
+    }
+  }
+  __syncthreads();
+  const int ua0 = ubox[0], ua1 = ubox[1], ua2 = ubox[2];
+  const int ub0 = ubox[3], ub1 = ubox[4], ub2 = ubox[5];
+  if (ua0 <= ub0 && ua1 <= ub1 && ua2 <= ub2) {
+    const int e2 = ub2 - ua2 + 1, e1 = ub1 - ua1 + 1;
+    const int nvox = (ub0 - ua0 + 1) * e1 * e2;
+    // q -> (x0, x1, x2) by reciprocal multiplication: for q < 2^23 the FP32
+    // product is within one of the exact quotient and is corrected to it;
+    // larger boxes use integer division
+    const float inv2 = 1.0f / static_cast<float>(e2), inv1 = 1.0f / static_cast<float>(e1);
+    const bool small = nvox < (1 << 23);
+    for (int qb = 0; qb < nvox; qb += 4 * BNT) {
+      float uu[4][3], gg[4][3];
+      int xs[4][3];
+      bool ok[4];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) {
+      for (int j = 0; j < 4; ++j) {
+        const int q = qb + j * BNT + static_cast<int>(threadIdx.x);
+        ok[j] = q < nvox;
+        const int qq = ok[j] ? q : 0;
+        int r, r1;
+        if (small) {
+          r = static_cast<int>((static_cast<float>(qq) + 0.5f) * inv2);
+          r -= (r * e2 > qq);
+          r += ((r + 1) * e2 <= qq);
+          r1 = static_cast<int>((static_cast<float>(r) + 0.5f) * inv1);
+          r1 -= (r1 * e1 > r);
+          r1 += ((r1 + 1) * e1 <= r);
+        } else {
+          r = qq / e2;
+          r1 = r / e1;
+        }
+        xs[j][2] = ua2 + (qq - r * e2);
+        xs[j][1] = ua1 + (r - r1 * e1);
+        xs[j][0] = ua0 + r1;
+        const int lin = (xs[j][0] * g.d1 + xs[j][1]) * g.d2 + xs[j][2];
 #pragma unroll
-              for (int b = 0; b < 2; ++b) {
+        for (int c = 0; c < 3; ++c) {
+          uu[j][c] = f[c * g.V + lin];
+          gg[j][c] = gi[c * g.V + lin];
+        }
+      }
 #pragma unroll
-                for (int e = 0; e < 2; ++e) {
-                  // corner (c + k) - 1 in tile-local coordinates
-                  const int q0 = c0 + a - 1, q1 = c1 + b - 1, q2 = c2 + e - 1;
-                  if (q0 >= 0 && q0 < BTZ && q1 >= 0 && q1 < BTY && q2 >= 0 && q2 < BTX) {
-                    const float w = w0[a] * w1[b] * w2[e];
-                    const int li = (q0 * BTY + q1) * BTX + q2;
-                    atomicAdd(&ovf[0][li], w * g0);
-                    atomicAdd(&ovf[1][li], w * g1);
-                    atomicAdd(&ovf[2][li], w * g2);
-                  }
+      for (int j = 0; j < 4; ++j) {
+        if (!ok[j]) continue;
+        float u0 = uu[j][0], u1 = uu[j][1], u2 = uu[j][2];
+        if (FIRST) {
+          u0 *= scale;
+          u1 *= scale;
+          u2 *= scale;
+        }
+        const BorderCell bc = border_cell(g, xs[j][0], xs[j][1], xs[j][2], u0, u1, u2);
+        // local cell index: base - (O - 1), in [0, C)
+        const int c0 = bc.i0 - oz + 1, c1 = bc.i1 - oy + 1, c2 = bc.i2 - ox + 1;
+        if (c0 < 0 || c0 >= CZ || c1 < 0 || c1 >= CY || c2 < 0 || c2 >= CX) continue;
+        const int ci = (c0 * CY + c1) * CX + c2;
+        const float g0 = gg[j][0], g1 = gg[j][1], g2 = gg[j][2];
+        const int slot = atomicAdd(&cnt[ci], 1);
+        if (slot < KSLOT) {
+          sdat4[slot][ci] = make_float4(bc.t0, bc.t1, bc.t2, g0);
+          sdat2[slot][ci] = make_float2(g1, g2);
+        } else {
+          const float w0[2] = {1.0f - bc.t0, bc.t0};
+          const float w1[2] = {1.0f - bc.t1, bc.t1};
+          const float w2[2] = {1.0f - bc.t2, bc.t2};
+#pragma unroll
+          for (int a = 0; a < 2; ++a) {
+#pragma unroll
+            for (int b = 0; b < 2; ++b) {
+#pragma unroll
+              for (int e = 0; e < 2; ++e) {
+                // corner (c + k) - 1 in tile-local coordinates
+                const int q0 = c0 + a - 1, q1 = c1 + b - 1, q2 = c2 + e - 1;
+                if (q0 >= 0 && q0 < BTZ && q1 >= 0 && q1 < BTY && q2 >= 0 && q2 < BTX) {
+                  const float w = w0[a] * w1[b] * w2[e];
+                  const int li = (q0 * BTY + q1) * BTX + q2;
+                  atomicAdd(&ovf[0][li], w * g0);
+                  atomicAdd(&ovf[1][li], w * g1);
+                  atomicAdd(&ovf[2][li], w * g2);
                 }
               }
             }
@@ -360,11 +594,12 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
 #pragma unroll
           for (int j = 0; j < KSLOT; ++j) {
             if (j < nsrc) {
-              const float t0 = sdat[j][0][ci], t1 = sdat[j][1][ci], t2 = sdat[j][2][ci];
-              const float w = (a ? t0 : 1.0f - t0) * (b ? t1 : 1.0f - t1) * (e ? t2 : 1.0f - t2);
-              r0 += w * sdat[j][3][ci];
-              r1 += w * sdat[j][4][ci];
-              r2 += w * sdat[j][5][ci];
+              const float4 p = sdat4[j][ci];
+              const float2 q = sdat2[j][ci];
+              const float w = (a ? p.x : 1.0f - p.x) * (b ? p.y : 1.0f - p.y) * (e ? p.z : 1.0f - p.z);
+              r0 += w * p.w;
+              r1 += w * q.x;
+              r2 += w * q.y;
             }
           }
         }
@@ -379,7 +614,299 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
     go[g.V + lin] = r1 * oscale;
     go[2 * g.V + lin] = r2 * oscale;
   }
+  __syncthreads();  // the next tile reuses the LDS bins
+  }
 }
+
+// Adjoint of one squaring step, marching, for a subject whose every cell
+// offset lies in [-1, 0] (reach 1 in every direction: all |u_t| < 1, the
+// case of the early sweeps and of the first squaring steps).  Then the
+// sources whose cells touch the column's targets at plane z all lie in planes
+// z-1..z+1 of the column and its one-voxel halo, so every block finds them in
+// its ring.  Per plane z: (i) stage u_t of plane z+1; (ii) bin the sources of
+// plane z+1 into the ring of cell planes (one LDS integer atomic each, two
+// zero-initialised slots per cell, further sources into an overflow
+// accumulator); (iii) the direct term g + J^T g of the plane-z targets, whose
+// cells were found when they were binned one plane earlier; (iv) gather, for
+// each target, the sources binned in its 8 neighbouring cells (cell planes
+// z-1 and z).  Thread (ly, lx) stages and bins its own voxel, so a voxel's
+// cell and g stay in its registers from binning to its direct term.  Blocks
+// of subjects with a larger reach return at once: the tiled kernel handles
+// those.
+constexpr int MCX = ETX + 1, MCY = ETY + 1;  // cells per cell plane: 33 x 9
+constexpr int MCP = MCX * MCY;
+constexpr int MRING = MHP - ENT;             // halo ring positions (84)
+
+template <bool FIRST>
+__global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__ ut,
+                                                       const float* __restrict__ gin,
+                                                       float* __restrict__ gout, MarchGeom m,
+                                                       float scale, float oscale,
+                                                       const int* __restrict__ reach) {
+  __shared__ float uring[3][3][MHP];     // u_t planes z-1, z, z+1
+  __shared__ int bcnt[3][MCP];           // cell planes z-1, z, z+1
+  __shared__ float4 bd4[3][KSLOT][MCP];  // t0, t1, t2, g0 per binned source (0 if empty)
+  __shared__ float2 bd2[3][KSLOT][MCP];  // g1, g2
+  __shared__ float ovf[3][3][ENT];       // target planes z, z+1, z+2
+  const Geom& g = m.rec.g;
+  const MarchId id = march_id(m);
+  {
+    const int* rc = reach + id.s * 8;
+    if (rc[0] > 1 || rc[1] > 1 || rc[2] > 1 || rc[3] > 1 || rc[4] > 1 || rc[5] > 1) return;
+  }
+  const size_t off = static_cast<size_t>(id.s) * 3 * g.V;
+  const float* f = ut + off;
+  const float* gi = gin + off;
+  float* go = gout + off;
+  const int lx = threadIdx.x % ETX, ly = threadIdx.x / ETX;
+  const float js = FIRST ? scale : 1.0f;
+
+  // staged positions: j = 0 the thread's own voxel, j = 1 a halo-ring voxel
+  int pe[2], py[2], px[2], poff[2];
+  bool puse[2], pin[2];
+  pe[0] = (ly + 1) * MHX + lx + 1;
+  py[0] = id.oy + ly;
+  px[0] = id.ox + lx;
+  puse[0] = true;
+  {
+    const int r = threadIdx.x;
+    int hy, hx;
+    if (r < MHX) {
+      hy = 0;
+      hx = r;
+    } else if (r < 2 * MHX) {
+      hy = MHY - 1;
+      hx = r - MHX;
+    } else if (r < 2 * MHX + ETY) {
+      hy = 1 + r - 2 * MHX;
+      hx = 0;
+    } else {
+      hy = 1 + min(r - 2 * MHX - ETY, ETY - 1);
+      hx = MHX - 1;
+    }
+    puse[1] = r < MRING;
+    pe[1] = hy * MHX + hx;
+    py[1] = id.oy - 1 + hy;
+    px[1] = id.ox - 1 + hx;
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    pin[j] = py[j] >= 0 && py[j] < g.d1 && px[j] >= 0 && px[j] < g.d2;
+    poff[j] = min(max(py[j], 0), g.d1 - 1) * g.d2 + min(max(px[j], 0), g.d2 - 1);
+  }
+
+  float pu[2][3], pg[2][3];
+  auto load_plane = [&](int z) {
+    const int zc = min(max(z, 0), g.d0 - 1);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (puse[j]) {
+        const int lin = zc * g.plane + poff[j];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          pu[j][c] = f[c * g.V + lin];
+          pg[j][c] = gi[c * g.V + lin];
+        }
+      }
+  };
+  auto store_u = [&](int z) {
+    const int su = (z + 3) % 3;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (puse[j]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) uring[su][c][pe[j]] = pu[j][c];
+      }
+  };
+  auto clear_cells = [&](int cplane) {
+    const int cs = (cplane + 3) % 3;
+    const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float2 z2 = make_float2(0.0f, 0.0f);
+    for (int i = threadIdx.x; i < MCP; i += ENT) {
+      bcnt[cs][i] = 0;
+#pragma unroll
+      for (int k = 0; k < KSLOT; ++k) {
+        bd4[cs][k][i] = z4;
+        bd2[cs][k][i] = z2;
+      }
+    }
+  };
+  // bin the staged sources of plane p (values in vu, vg); returns the own
+  // voxel's cell in own_bc
+  auto bin_plane = [&](int p, const float (&vu)[2][3], const float (&vg)[2][3],
+                       BorderCell& own_bc) {
+    if (p < 0 || p >= g.d0) return;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (!(puse[j] && pin[j])) continue;
+      float u0 = vu[j][0], u1 = vu[j][1], u2 = vu[j][2];
+      if (FIRST) {
+        u0 *= scale;
+        u1 *= scale;
+        u2 *= scale;
+      }
+      const BorderCell bc = border_cell(g, p, py[j], px[j], u0, u1, u2);
+      if (j == 0) own_bc = bc;
+      if (bc.i0 < id.z0 - 1 || bc.i0 > id.z1 - 1) continue;  // cell plane not gathered here
+      const int c1 = bc.i1 - id.oy + 1, c2 = bc.i2 - id.ox + 1;
+      if (c1 < 0 || c1 >= MCY || c2 < 0 || c2 >= MCX) continue;
+      const int ci = c1 * MCX + c2;
+      const int cs = (bc.i0 + 3) % 3;
+      const float g0 = vg[j][0], g1 = vg[j][1], g2 = vg[j][2];
+      const int slot = atomicAdd(&bcnt[cs][ci], 1);
+      if (slot < KSLOT) {
+        bd4[cs][slot][ci] = make_float4(bc.t0, bc.t1, bc.t2, g0);
+        bd2[cs][slot][ci] = make_float2(g1, g2);
+      } else {
+        const float w0[2] = {1.0f - bc.t0, bc.t0};
+        const float w1[2] = {1.0f - bc.t1, bc.t1};
+        const float w2[2] = {1.0f - bc.t2, bc.t2};
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+          const int tz = bc.i0 + a;  // target plane
+          if (tz < id.z0 || tz >= id.z1) continue;
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+#pragma unroll
+            for (int ee = 0; ee < 2; ++ee) {
+              const int ty = c1 + b - 1, tx = c2 + ee - 1;
+              if (ty >= 0 && ty < ETY && tx >= 0 && tx < ETX) {
+                const float w = w0[a] * w1[b] * w2[ee];
+                float* ov = &ovf[(tz + 3) % 3][0][0] + ty * ETX + tx;
+                atomicAdd(ov, w * g0);
+                atomicAdd(ov + ENT, w * g1);
+                atomicAdd(ov + 2 * ENT, w * g2);
+              }
+            }
+          }
+        }
+      }
+    }
+  };
+
+  const bool colv = pin[0];
+  BorderCell cur_bc{}, nxt_bc{};
+  float cur_g[3] = {0.0f, 0.0f, 0.0f};
+
+  // prologue: planes z0-1 and z0 staged and binned, plane z0+1 in flight
+  for (int c = -1; c <= 1; ++c) clear_cells(id.z0 + c);
+  for (int i = threadIdx.x; i < 9 * ENT; i += ENT) (&ovf[0][0][0])[i] = 0.0f;
+  float qu[2][3], qg[2][3];
+  load_plane(id.z0 - 1);
+  store_u(id.z0 - 1);
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      qu[j][c] = pu[j][c];
+      qg[j][c] = pg[j][c];
+    }
+  load_plane(id.z0);
+  store_u(id.z0);
+  __syncthreads();
+  bin_plane(id.z0 - 1, qu, qg, nxt_bc);
+  bin_plane(id.z0, pu, pg, cur_bc);
+  cur_g[0] = pg[0][0];
+  cur_g[1] = pg[0][1];
+  cur_g[2] = pg[0][2];
+  load_plane(id.z0 + 1);
+  __syncthreads();
+
+  for (int z = id.z0; z < id.z1; ++z) {
+    // (i) stage u of plane z+1, clear cell plane z+1 and target plane z+2
+    store_u(z + 1);
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        qu[j][c] = pu[j][c];
+        qg[j][c] = pg[j][c];
+      }
+    clear_cells(z + 1);
+    for (int i = threadIdx.x; i < 3 * ENT; i += ENT) (&ovf[(z + 2) % 3][0][0])[i] = 0.0f;
+    __syncthreads();
+    if (z + 2 <= id.z1) load_plane(z + 2);
+    // (ii) bin the sources of plane z+1
+    bin_plane(z + 1, qu, qg, nxt_bc);
+    // (iii) direct term of the plane-z targets
+    float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f;
+    if (colv) {
+      const BorderCell& bc = cur_bc;
+      const int c0 = bc.i0 - z + 1, c1 = bc.i1 - id.oy + 1, c2 = bc.i2 - id.ox + 1;
+      const bool in_ring =
+          c0 >= 0 && c0 <= 1 && c1 >= 0 && c1 + 1 < MHY && c2 >= 0 && c2 + 1 < MHX;
+      float jt0 = 0.0f, jt1 = 0.0f, jt2 = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        float cv[8];
+        if (in_ring) {
+          const int sa = (bc.i0 + 3) % 3, sb = (bc.i0 + 4) % 3;
+          const int pb = c1 * MHX + c2;
+          cv[0] = uring[sa][c][pb];
+          cv[1] = uring[sa][c][pb + 1];
+          cv[2] = uring[sa][c][pb + MHX];
+          cv[3] = uring[sa][c][pb + MHX + 1];
+          cv[4] = uring[sb][c][pb];
+          cv[5] = uring[sb][c][pb + 1];
+          cv[6] = uring[sb][c][pb + MHX];
+          cv[7] = uring[sb][c][pb + MHX + 1];
+        } else {
+          corners_border(f + c * g.V, g, bc.base, cv);
+        }
+        const Tri t = tri_eval(cv, bc.t0, bc.t1, bc.t2);
+        jt0 += t.d0 * cur_g[c];
+        jt1 += t.d1 * cur_g[c];
+        jt2 += t.d2 * cur_g[c];
+      }
+      r0 = cur_g[0] + (bc.k0 ? 0.0f : jt0 * js);
+      r1 = cur_g[1] + (bc.k1 ? 0.0f : jt1 * js);
+      r2 = cur_g[2] + (bc.k2 ? 0.0f : jt2 * js);
+    }
+    __syncthreads();
+    // (iv) gather from cell planes z-1 (a = 1) and z (a = 0); empty slots hold zeros
+    if (colv) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int cs = (z - a + 3) % 3;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+          for (int e = 0; e < 2; ++e) {
+            const int ci = (ly + 1 - b) * MCX + (lx + 1 - e);
+#pragma unroll
+            for (int j = 0; j < KSLOT; ++j) {
+              const float4 p = bd4[cs][j][ci];
+              const float2 q = bd2[cs][j][ci];
+              const float w =
+                  (a ? p.x : 1.0f - p.x) * (b ? p.y : 1.0f - p.y) * (e ? p.z : 1.0f - p.z);
+              r0 += w * p.w;
+              r1 += w * q.x;
+              r2 += w * q.y;
+            }
+          }
+        }
+      }
+      const float* ov = &ovf[z % 3][0][0];
+      r0 += ov[threadIdx.x];
+      r1 += ov[ENT + threadIdx.x];
+      r2 += ov[2 * ENT + threadIdx.x];
+      const int lin = z * g.plane + py[0] * g.d2 + px[0];
+      go[lin] = r0 * oscale;
+      go[g.V + lin] = r1 * oscale;
+      go[2 * g.V + lin] = r2 * oscale;
+    }
+    // (v) the voxel binned at (ii) is the next plane's target
+    cur_bc = nxt_bc;
+    cur_g[0] = qg[0][0];
+    cur_g[1] = qg[0][1];
+    cur_g[2] = qg[0][2];
+    __syncthreads();
+  }
+}
+
+// Blocks of the persistent tiled adjoint: enough to fill the chip several
+// times over; each walks total / grid tiles.
+uint32_t bwd_grid(const BwdGeom& bg) { return bg.total < 4096u ? bg.total : 4096u; }
 
 BwdGeom make_bwd(const TileGeom& tg, int n) {
   BwdGeom b;
@@ -390,25 +917,6 @@ BwdGeom make_bwd(const TileGeom& tg, int n) {
   b.ntiles = b.ntx * b.nty * b.ntz;
   b.total = static_cast<uint32_t>(b.ntiles) * n;
   return b;
-}
-
-template <bool FIRST>
-void launch_fwd(int mode, const float* src, float* dst, const TileGeom& tg, float scale, int* boxes,
-                int* reach, hipStream_t st) {
-  switch (mode) {
-    case 0:
-      hipLaunchKernelGGL((k_exp_fwd<FIRST, 0>), dim3(tg.total), dim3(ENT), 0, st, src, dst, tg,
-                         scale, boxes, reach);
-      break;
-    case 1:
-      hipLaunchKernelGGL((k_exp_fwd<FIRST, 1>), dim3(tg.total), dim3(ENT), 0, st, src, dst, tg,
-                         scale, boxes, reach);
-      break;
-    default:
-      hipLaunchKernelGGL((k_exp_fwd<FIRST, 2>), dim3(tg.total), dim3(ENT), 0, st, src, dst, tg,
-                         scale, boxes, reach);
-      break;
-  }
 }
 
 struct AuxPtrs {
@@ -434,6 +942,17 @@ size_t exp_aux_bytes(const Geom& g, int n, int n_sq) {
          sizeof(int);
 }
 
+// Chunk length along d0 of the marching kernels: long chunks amortise the two
+// planes of ramp-up; shorter ones give small cohorts enough blocks.
+int march_tz(const TileGeom& tg, int n) {
+  const int tuned = tuned_tz(TUNE_EXP, tg.g, n);
+  if (tuned > 0) return tuned;
+  int tz = 32;
+  while (tz > ETZ && static_cast<long long>(tg.ntx) * tg.nty * ((tg.g.d0 + tz - 1) / tz) * n < 4096)
+    tz /= 2;
+  return tz;
+}
+
 void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, int* aux, const Geom& g, int n,
                  int n_sq, hipStream_t st) {
   const size_t fs = static_cast<size_t>(n) * 3 * g.V;
@@ -444,9 +963,12 @@ void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, int* aux, co
     return;
   }
   const TileGeom tg = make_tiles(g, n);
+  const MarchGeom m = make_march(tg, n, march_tz(tg, n));
   const AuxPtrs ap = aux_ptrs(aux, tg, n, n_sq);
   // the reaches are running maxima: start them at zero (all-zero bits)
-  if (aux) launch_fill_f32(reinterpret_cast<float*>(ap.reach), static_cast<long long>(ap.reach_stride) * n_sq, 0.0f, st);
+  if (aux)
+    launch_fill_f32(reinterpret_cast<float*>(ap.reach),
+                    static_cast<long long>(ap.reach_stride) * n_sq, 0.0f, st);
   const float scale = ldexpf(1.0f, -n_sq);
   const float* src = v;
   for (int t = 0; t < n_sq; ++t) {
@@ -460,14 +982,60 @@ void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, int* aux, co
     int* bx = aux ? ap.boxes + ap.box_stride * t : nullptr;
     int* rc = aux ? ap.reach + ap.reach_stride * t : nullptr;
     prof_begin(st, KC_EXP_FWD);
-    if (t == 0)
-      launch_fwd<true>(aux ? 1 : 0, src, dst, tg, scale, bx, rc, st);
-    else
-      launch_fwd<false>(aux ? 1 : 0, src, dst, tg, scale, bx, rc, st);
+    if (t == 0) {
+      if (aux)
+        hipLaunchKernelGGL((k_exp_fwd<true, true>), dim3(m.total), dim3(ENT), 0, st, src, dst, m,
+                           scale, bx, rc);
+      else
+        hipLaunchKernelGGL((k_exp_fwd<true, false>), dim3(m.total), dim3(ENT), 0, st, src, dst, m,
+                           scale, bx, rc);
+    } else {
+      if (aux)
+        hipLaunchKernelGGL((k_exp_fwd<false, true>), dim3(m.total), dim3(ENT), 0, st, src, dst, m,
+                           1.0f, bx, rc);
+      else
+        hipLaunchKernelGGL((k_exp_fwd<false, false>), dim3(m.total), dim3(ENT), 0, st, src, dst,
+                           m, 1.0f, bx, rc);
+    }
     prof_end(st, KC_EXP_FWD);
     src = dst;
   }
 }
+
+namespace {
+
+// Records of one step (positions x + u_t) and the adjoint of that step.
+void launch_rec(const float* ut, bool first, const TileGeom& tg, float scale, int* bx, int* rc,
+                hipStream_t st) {
+  prof_begin(st, KC_MISC);
+  if (first)
+    hipLaunchKernelGGL((k_exp_rec<true>), dim3(tg.total), dim3(ENT), 0, st, ut, tg, scale, bx, rc);
+  else
+    hipLaunchKernelGGL((k_exp_rec<false>), dim3(tg.total), dim3(ENT), 0, st, ut, tg, 1.0f, bx, rc);
+  prof_end(st, KC_MISC);
+}
+
+void launch_bwd_step(const float* ut, const float* gin, float* gout, bool first, const MarchGeom& m,
+                     const BwdGeom& bg, float scale, const int* bx, const int* rc,
+                     hipStream_t st) {
+  // each subject is handled by exactly one of the two kernels (decided on the
+  // device from its reach); the other one's blocks return at once
+  prof_begin(st, KC_EXP_BWD);
+  if (first) {
+    hipLaunchKernelGGL((k_exp_bwd_march<true>), dim3(m.total), dim3(ENT), 0, st, ut, gin, gout, m,
+                       scale, scale, rc);
+    hipLaunchKernelGGL((k_exp_bwd<true>), dim3(bwd_grid(bg)), dim3(BNT), 0, st, ut, gin, gout, bg,
+                       scale, scale, bx, rc);
+  } else {
+    hipLaunchKernelGGL((k_exp_bwd_march<false>), dim3(m.total), dim3(ENT), 0, st, ut, gin, gout, m,
+                       1.0f, 1.0f, rc);
+    hipLaunchKernelGGL((k_exp_bwd<false>), dim3(bwd_grid(bg)), dim3(BNT), 0, st, ut, gin, gout, bg,
+                       1.0f, 1.0f, bx, rc);
+  }
+  prof_end(st, KC_EXP_BWD);
+}
+
+}  // namespace
 
 void run_exp_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, float* tmp_a,
                  float* tmp_b, int* aux, bool aux_ready, const Geom& g, int n, int n_sq,
@@ -481,35 +1049,59 @@ void run_exp_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v
   }
   const TileGeom tg = make_tiles(g, n);
   const BwdGeom bg = make_bwd(tg, n);
+  const MarchGeom m = make_march(tg, n, march_tz(tg, n));
   const AuxPtrs ap = aux_ptrs(aux, tg, n, n_sq);
   const float scale = ldexpf(1.0f, -n_sq);
   if (!aux_ready) {
-    launch_fill_f32(reinterpret_cast<float*>(ap.reach), static_cast<long long>(ap.reach_stride) * n_sq, 0.0f, st);
+    launch_fill_f32(reinterpret_cast<float*>(ap.reach),
+                    static_cast<long long>(ap.reach_stride) * n_sq, 0.0f, st);
     for (int t = 0; t < n_sq; ++t) {
       const float* ut = (t == 0) ? v : ckpt + static_cast<size_t>(t - 1) * fs;
-      prof_begin(st, KC_MISC);
-      if (t == 0)
-        launch_fwd<true>(2, ut, nullptr, tg, scale, ap.boxes, ap.reach, st);
-      else
-        launch_fwd<false>(2, ut, nullptr, tg, scale, ap.boxes + ap.box_stride * t,
-                          ap.reach + ap.reach_stride * t, st);
-      prof_end(st, KC_MISC);
+      launch_rec(ut, t == 0, tg, scale, ap.boxes + ap.box_stride * t,
+                 ap.reach + ap.reach_stride * t, st);
     }
   }
   const float* gin = g_u;
   for (int t = n_sq - 1; t >= 0; --t) {
     float* gout = (t == 0) ? g_v : (((n_sq - 1 - t) % 2 == 0) ? tmp_a : tmp_b);
     const float* ut = (t == 0) ? v : ckpt + static_cast<size_t>(t - 1) * fs;
-    const int* bx = ap.boxes + ap.box_stride * t;
-    const int* rc = ap.reach + ap.reach_stride * t;
-    prof_begin(st, KC_EXP_BWD);
-    if (t == 0)
-      hipLaunchKernelGGL((k_exp_bwd<true>), dim3(bg.total), dim3(BNT), 0, st, ut, gin, gout, bg,
-                         scale, scale, bx, rc);
-    else
-      hipLaunchKernelGGL((k_exp_bwd<false>), dim3(bg.total), dim3(BNT), 0, st, ut, gin, gout, bg,
-                         1.0f, 1.0f, bx, rc);
-    prof_end(st, KC_EXP_BWD);
+    launch_bwd_step(ut, gin, gout, t == 0, m, bg, scale, ap.boxes + ap.box_stride * t,
+                    ap.reach + ap.reach_stride * t, st);
+    gin = gout;
+  }
+}
+
+void run_exp_bwd_recompute(const float* v, const float* g_u, float* g_v, float* tmp_a,
+                           float* tmp_b, float* rec_a, float* rec_b, int* aux, const Geom& g,
+                           int n, int n_sq, hipStream_t st) {
+  const TileGeom tg = make_tiles(g, n);
+  const BwdGeom bg = make_bwd(tg, n);
+  const MarchGeom m = make_march(tg, n, march_tz(tg, n));
+  const AuxPtrs ap = aux_ptrs(aux, tg, n, n_sq);
+  const float scale = ldexpf(1.0f, -n_sq);
+  launch_fill_f32(reinterpret_cast<float*>(ap.reach),
+                  static_cast<long long>(ap.reach_stride) * n_sq, 0.0f, st);
+  const float* gin = g_u;
+  for (int t = n_sq - 1; t >= 0; --t) {
+    // u_t = t squaring steps of v / 2^N, ping-ponging so that it ends in rec_a
+    const float* ut = v;
+    for (int k = 0; k < t; ++k) {
+      float* dst = ((t - 1 - k) % 2 == 0) ? rec_a : rec_b;
+      prof_begin(st, KC_EXP_FWD);
+      if (k == 0)
+        hipLaunchKernelGGL((k_exp_fwd<true, false>), dim3(m.total), dim3(ENT), 0, st, ut, dst, m,
+                           scale, nullptr, nullptr);
+      else
+        hipLaunchKernelGGL((k_exp_fwd<false, false>), dim3(m.total), dim3(ENT), 0, st, ut, dst, m,
+                           1.0f, nullptr, nullptr);
+      prof_end(st, KC_EXP_FWD);
+      ut = dst;
+    }
+    int* bx = ap.boxes + ap.box_stride * t;
+    int* rc = ap.reach + ap.reach_stride * t;
+    launch_rec(ut, t == 0, tg, scale, bx, rc, st);
+    float* gout = (t == 0) ? g_v : (((n_sq - 1 - t) % 2 == 0) ? tmp_a : tmp_b);
+    launch_bwd_step(ut, gin, gout, t == 0, m, bg, scale, bx, rc, st);
     gin = gout;
   }
 }

@@ -168,6 +168,41 @@ __global__ __launch_bounds__(kBlock) void k_adam(const float* __restrict__ v_in,
   }
 }
 
+// The step count lives on the device so that a captured sweep can be
+// replayed: one thread advances it and forms the bias corrections in FP64.
+__global__ void k_adam_prep(const long long* __restrict__ step, int k, float* __restrict__ bc,
+                            double b1, double b2) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double t = static_cast<double>(step[0] + k + 1);
+    bc[0] = static_cast<float>(1.0 - pow(b1, t));
+    bc[1] = static_cast<float>(1.0 - pow(b2, t));
+  }
+}
+
+__global__ void k_step_add(long long* __restrict__ step, long long k) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) step[0] += k;
+}
+
+__global__ __launch_bounds__(kBlock) void k_adam_dev(const float* __restrict__ v_in,
+                                                     float* __restrict__ v_out,
+                                                     float* __restrict__ m, float* __restrict__ s,
+                                                     const float* __restrict__ g, long long count,
+                                                     float lr, float b1, float omb1, float b2,
+                                                     float omb2, const float* __restrict__ bc,
+                                                     float eps) {
+  const float bc1 = bc[0], bc2 = bc[1];
+  const long long stride = static_cast<long long>(gridDim.x) * kBlock;
+  for (long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x; i < count;
+       i += stride) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + omb1 * gi;
+    const float si = b2 * s[i] + omb2 * gi * gi;
+    m[i] = mi;
+    s[i] = si;
+    v_out[i] = v_in[i] - lr * (mi / bc1) / (sqrtf(si / bc2) + eps);
+  }
+}
+
 // ---------------------------------------------------------------- centring
 
 // mean(e) = (1/n) sum_i u_i(e) over the 3V entries e; u_i <- u_i - mean.
@@ -322,6 +357,23 @@ void launch_adam(const float* v_in, float* v_out, float* m, float* s, const floa
                      static_cast<float>(b2), static_cast<float>(1.0 - b2), static_cast<float>(bc1),
                      static_cast<float>(bc2), eps);
   prof_end(st, KC_ADAM);
+}
+
+void launch_adam_dev(const float* v_in, float* v_out, float* m, float* s, const float* g,
+                     long long count, const long long* step_dev, int k, float* bc, float lr,
+                     double b1, double b2, float eps, hipStream_t st) {
+  prof_begin(st, KC_ADAM);
+  hipLaunchKernelGGL(k_adam_prep, dim3(1), dim3(64), 0, st, step_dev, k, bc, b1, b2);
+  hipLaunchKernelGGL(k_adam_dev, dim3(grid_stride_blocks(count)), dim3(kBlock), 0, st, v_in, v_out,
+                     m, s, g, count, lr, static_cast<float>(b1), static_cast<float>(1.0 - b1),
+                     static_cast<float>(b2), static_cast<float>(1.0 - b2), bc, eps);
+  prof_end(st, KC_ADAM);
+}
+
+void launch_step_add(long long* step_dev, long long k, hipStream_t st) {
+  prof_begin(st, KC_MISC);
+  hipLaunchKernelGGL(k_step_add, dim3(1), dim3(64), 0, st, step_dev, k);
+  prof_end(st, KC_MISC);
 }
 
 void launch_center(float* u, float* mean_out, const Geom& g, int n, hipStream_t st) {

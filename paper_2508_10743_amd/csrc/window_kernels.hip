@@ -50,10 +50,13 @@ MarchGeom make_march(const Geom& g, int nchan, int halo) {
   mg.nty = (g.d1 + kTY - 1) / kTY;
   // long chunks amortise the 2*halo planes of ramp-up; shorter ones give
   // enough blocks for small cohorts
-  int tz = 64;
-  while (tz > 8 && tz > 2 * halo &&
-         static_cast<long long>(mg.ntx) * mg.nty * ((g.d0 + tz - 1) / tz) * nchan < 2048)
-    tz /= 2;
+  int tz = tuned_tz(TUNE_WINDOW, g, nchan);
+  if (tz <= 0) {
+    tz = 64;
+    while (tz > 8 && tz > 2 * halo &&
+           static_cast<long long>(mg.ntx) * mg.nty * ((g.d0 + tz - 1) / tz) * nchan < 2048)
+      tz /= 2;
+  }
   mg.tz = tz;
   mg.nz = (g.d0 + tz - 1) / tz;
   mg.total = static_cast<uint32_t>(mg.ntx) * mg.nty * mg.nz * nchan;

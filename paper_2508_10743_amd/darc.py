@@ -103,7 +103,8 @@ def exp_svf(v: torch.Tensor, n_sq: int = 7, checkpoints: bool = True):
 
 def exp_svf_bwd(v: torch.Tensor, ckpt: Optional[torch.Tensor], g_u: torch.Tensor,
                 n_sq: int = 7) -> torch.Tensor:
-    """dL/dv given dL/du, through the n_sq squaring steps."""
+    """dL/dv given dL/du, through the n_sq squaring steps (recomputed from v
+    when ``ckpt`` is None)."""
     n, d0, d1, d2 = _field("v", v)
     _same("g_u", g_u.shape, "v", v.shape)
     _field("g_u", g_u)
@@ -111,7 +112,8 @@ def exp_svf_bwd(v: torch.Tensor, ckpt: Optional[torch.Tensor], g_u: torch.Tensor
         _dev("ckpt", ckpt, ndim=6)
         _same("ckpt", ckpt.shape, "expected", (n_sq - 1,) + tuple(v.shape))
     g_v = torch.empty_like(v)
-    ws = _workspace(lib().darc_exp_svf_bwd_ws_bytes(n, d0, d1, d2, n_sq), v.device)
+    ws = _workspace(lib().darc_exp_svf_bwd_ws_bytes(n, d0, d1, d2, n_sq, int(ckpt is not None)),
+                    v.device)
     _call("darc_exp_svf_bwd", _p(v), _p(ckpt), _p(g_u), _p(g_v), n, d0, d1, d2, n_sq, _p(ws),
           0 if ws is None else ws.numel(), _stream())
     return g_v
@@ -263,9 +265,14 @@ class Cohort:
     ``images`` is ``[n, D0, D1, D2]`` FP32 on the GPU.  Velocities and moments
     start at zero and the atlas at the mean of the unwarped subjects
     (computed by ``darc_atlas_update`` with zero displacements).
+
+    With ``device_step=True`` the Adam step counter lives in device memory and
+    the sweep reads and advances it there, so one captured sweep
+    (:meth:`capture`) can be replayed any number of times.
     """
 
-    def __init__(self, images: torch.Tensor, params: SweepParams, keep_u_hat: bool = True):
+    def __init__(self, images: torch.Tensor, params: SweepParams, keep_u_hat: bool = True,
+                 device_step: bool = False):
         n, d0, d1, d2 = _images("images", images)
         self.images = images
         self.params = params
@@ -278,6 +285,7 @@ class Cohort:
         self.atlas = atlas_update(images, self.v)
         self.step = 0
         self.sweeps = 0
+        self.step_dev = torch.zeros(1, dtype=torch.int64, device=dev) if device_step else None
         self._state = L.DarcState()
         self._cparams = params.to_c()
         self._refresh_state()
@@ -298,6 +306,7 @@ class Cohort:
         st.atlas = self.atlas.data_ptr()
         st.u_hat = None if self.u_hat is None else self.u_hat.data_ptr()
         st.step = self.step
+        st.step_dev = None if self.step_dev is None else self.step_dev.data_ptr()
         st.n, st.d0, st.d1, st.d2 = n, d0, d1, d2
 
     def sweep(self) -> torch.Tensor:
@@ -312,6 +321,58 @@ class Cohort:
 
     def group_loss(self) -> float:
         return float(self.losses[-1].item())
+
+    def autotune(self) -> tuple:
+        """Time the candidate plane-chunk lengths of the marching kernels on
+        this cohort's shapes and keep the fastest for later launches; returns
+        (squaring chunk, window-kernel chunk).  Only workspace memory is
+        written; the cohort state is left as it is."""
+        self._refresh_state()
+        chosen = (ctypes.c_int * 2)()
+        _call("darc_autotune", ctypes.byref(self._state), ctypes.byref(self._cparams),
+              _p(self.ws), self.ws.numel(), _stream(), chosen)
+        return int(chosen[0]), int(chosen[1])
+
+    def capture(self) -> "SweepGraph":
+        """Capture one sweep into a HIP graph (needs ``device_step=True``).
+        Capturing runs nothing; every replay performs one sweep."""
+        if self.step_dev is None:
+            raise ValueError("capture() needs a cohort built with device_step=True")
+        if self.params.reinit_v:
+            raise ValueError("a captured sweep with reinit_v would reset on every replay")
+        self._refresh_state()
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(device=self.images.device)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            graph.capture_begin()
+            try:
+                _call("darc_sweep", ctypes.byref(self._state), ctypes.byref(self._cparams),
+                      _p(self.losses), _p(self.ws), self.ws.numel(), _stream())
+            finally:
+                graph.capture_end()
+        torch.cuda.current_stream().wait_stream(side)
+        return SweepGraph(self, graph)
+
+
+class SweepGraph:
+    """A captured sweep of a :class:`Cohort`; :meth:`replay` runs one sweep."""
+
+    def __init__(self, cohort: Cohort, graph):
+        self.cohort = cohort
+        self.graph = graph
+
+    def replay(self) -> torch.Tensor:
+        self.graph.replay()
+        c = self.cohort
+        c.step += c.params.k2
+        c.sweeps += 1
+        return c.losses
+
+
+def autotune_clear() -> None:
+    """Forget every tuned launch shape (the built-in heuristic applies again)."""
+    _call("darc_autotune_clear")
 
 
 # -------------------------------------------------------------- kernel timing

@@ -64,8 +64,11 @@ def test_bad_dims_and_pointers_are_rejected_without_a_gpu(lib):
     # n_sq >= 2 without checkpoints needs a workspace
     _status(lib, lib.darc_exp_svf(dummy, ctypes.c_void_p(0x2000), None, 1, 4, 4, 4, 7, None, 0,
                                   None), L.DARC_EWORKSPACE)
+    # without checkpoints the squarings are recomputed: a workspace is required
     _status(lib, lib.darc_exp_svf_bwd(dummy, None, dummy, ctypes.c_void_p(0x2000), 1, 4, 4, 4, 7,
-                                      None, 0, None), L.DARC_EINVAL)  # no ckpt
+                                      None, 0, None), L.DARC_EWORKSPACE)
+    assert lib.darc_exp_svf_bwd_ws_bytes(1, 4, 4, 4, 7, 0) > lib.darc_exp_svf_bwd_ws_bytes(
+        1, 4, 4, 4, 7, 1)
     _status(lib, lib.darc_sim_grad(dummy, dummy, 1, 4, 1e-5, dummy, None, 1, 4, 4, 4, None, 0,
                                    None), L.DARC_EINVAL)  # even window
     _status(lib, lib.darc_sim_grad(dummy, dummy, 1, 13, 1e-5, dummy, None, 1, 4, 4, 4, None, 0,
@@ -101,7 +104,7 @@ def _params(**kw):
 
 def test_sweep_validation_and_workspace_sizes(lib):
     d = ctypes.c_void_p(0x1000)
-    st = L.DarcState(d.value, d.value, d.value, d.value, d.value, None, 0, 4, 8, 8, 8)
+    st = L.DarcState(d.value, d.value, d.value, d.value, d.value, None, 0, None, 4, 8, 8, 8)
     p = _params()
     V = 8 * 8 * 8
     nbytes = lib.darc_sweep_ws_bytes(ctypes.byref(st), ctypes.byref(p))

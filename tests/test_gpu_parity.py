@@ -137,6 +137,21 @@ def test_exp_large_displacements(dev, dims, amp, corr):
             assert rel_l2(gv[i], O.exp_svf_bwd(steps, gu[i].astype(np.float64))) <= TOL_GRAD
 
 
+@pytest.mark.parametrize("dims,amp", [((20, 21, 70), 0.3), ((9, 17, 33), 0.8)])
+def test_exp_small_displacements(dev, dims, amp):
+    """Every cell offset in [-1, 0] (the marching adjoint's case)."""
+    v = random_velocity(140, 2, dims, amp, corr_len=3.0)
+    gu = random_volume(141, v.shape, -1.0, 1.0)
+    vd = g(v, dev)
+    u, ck = D.exp_svf(vd, 7)
+    gv = h(D.exp_svf_bwd(vd, ck, g(gu, dev), 7))
+    u = h(u)
+    for i in range(2):
+        ref, steps = O.exp_svf(v[i].astype(np.float64))
+        assert rel_linf(u[i], ref) <= TOL_WARP
+        assert rel_l2(gv[i], O.exp_svf_bwd(steps, gu[i].astype(np.float64))) <= TOL_GRAD
+
+
 # ------------------------------------------------------------------- warp
 
 

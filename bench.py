@@ -36,10 +36,8 @@ def algorithmic_bytes(w, batch):
     b = {
         # per squaring step: read u_t (12 B), write u_{t+1} (12 B)
         "exp_fwd_step": N * (k2 + 1) * n * V * 24,
-        # per adjoint step: read u_t and g_{t+1}, accumulate g_t (12 B each)
+        # per adjoint step: read u_t and g_{t+1}, write g_t (12 B each)
         "exp_bwd_step": N * k2 * n * V * 36,
-        # zeroing the adjoint accumulator before each step
-        "fill": N * k2 * n * V * 12,
         # read g, v, m, s; write v, m, s
         "adam": k2 * n * V * 84,
         # read u of every subject, write centred u
@@ -58,6 +56,41 @@ def algorithmic_bytes(w, batch):
     if w.smooth_sigma > 0:
         b["gauss"] = k2 * n * V * 24
     return b
+
+
+def source_digest():
+    """SHA-256 over the HIP sources, to tell whether counters taken earlier
+    still describe the kernels that run now."""
+    import hashlib
+
+    h = hashlib.sha256()
+    src = os.path.join(ROOT, "paper_2508_10743_amd", "csrc")
+    for name in sorted(os.listdir(src)):
+        with open(os.path.join(src, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, kernel_class):
+    """HBM bytes per launch of `kernel_class` from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, each scaled by the same counter's
+    reading for a plain 1 GiB copy), in GB; None when there is no summary for
+    this workload and class or the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{workload}.md")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                fields[k.strip("` ")] = v.strip().strip("`")
+    if fields.get("source_sha256") != source_digest() or fields.get("class") != kernel_class:
+        return None
+    try:
+        return float(fields["hbm_GB_per_launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(w, seconds_hint=True):
@@ -110,6 +143,9 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="subjects per launch (0 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device-to-device copy first (a known-size kernel for "
+                         "calibrating HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -135,6 +171,13 @@ def main():
                            beta1=w.beta1, beta2=w.beta2, adam_eps=w.adam_eps, batch=args.batch)
     cohort = D.Cohort(images, params)
     torch.cuda.synchronize()
+    if args.calib_copy:
+        a = torch.full((1 << 28,), 1.0, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del a, b
     for i in range(args.warmup):
         cohort.sweep()
         torch.cuda.synchronize()
@@ -175,7 +218,8 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic(w.name, dom),
+            "traffic_unit": "GB per launch (HBM, from counters)",
         }
 
     ms_per_step = (t1 - t0) * 1e3 / args.steps

@@ -19,7 +19,14 @@ Model-Driven Groupwise Approach for Atlas Construction (DARC):
 * centrality activation: fourth line of Eq. (3) (Section 3, "Centrality
   activation function");
 * MSE atlas closed form: the first equation of Section 3, "Dissimilarity
-  metrics" (mean of the warped subjects).
+  metrics" (mean of the warped subjects); L1 atlas closed form: the second
+  equation there (voxelwise median); NCC atlas by minibatch stochastic
+  gradient descent: the last paragraph there and Algorithm 1
+  (``SGD_for_atlas``);
+* one-shot segmentation, Section 4, Eq. (oneshot): atlas labels carried to
+  subject i by Exp(-v_i), scored by Dice (Section 5);
+* factor-2 resampling between levels of a coarse-to-fine schedule (not in the
+  paper: a reading for large cohorts, see ``down2``/``up2``).
 
 Where the paper is silent this oracle reads it as follows: positions are in
 voxel units with voxel centres at integers; sampling is trilinear, with zero
@@ -299,6 +306,14 @@ def mse(warped: np.ndarray, atlas: np.ndarray):
     return float((diff ** 2).sum() / V), 2.0 * diff / V
 
 
+def l1(warped: np.ndarray, atlas: np.ndarray):
+    """L1 dissimilarity mean_x |Iw - A| (Section 3, "Dissimilarity metrics")
+    and its subgradient sign(Iw - A) / V, taking 0 where Iw = A."""
+    diff = np.asarray(warped, dtype=np.float64) - np.asarray(atlas, dtype=np.float64)
+    V = diff.size
+    return float(np.abs(diff).sum() / V), np.sign(diff) / V
+
+
 def box_sum(f: np.ndarray, win: int) -> np.ndarray:
     """Sum of f over the win^3 cube centred at each voxel, zero outside."""
     r = win // 2
@@ -418,13 +433,59 @@ def atlas_mean(images: np.ndarray, u_hat: np.ndarray) -> np.ndarray:
     return np.mean([warp3d(images[i], u_hat[i]) for i in range(len(images))], axis=0)
 
 
+def atlas_median(images: np.ndarray, u_hat: np.ndarray) -> np.ndarray:
+    """L1 atlas closed form: the voxelwise median of the warped subjects.
+    For even n every value between the two middle ones minimises the L1
+    sum; this takes their average."""
+    return np.median(np.stack([warp3d(images[i], u_hat[i]) for i in range(len(images))]), axis=0)
+
+
+def lncc_atlas_grad(warped: np.ndarray, atlas: np.ndarray, win: int = 9, eps: float = 1e-5):
+    """LNCC D(Iw, A) and dD/dA.  cc is symmetric in its two images, so the
+    gradient with respect to A is the one with respect to the first image
+    once the two are exchanged."""
+    return lncc(atlas, warped, win, eps)
+
+
+def atlas_sgd(warped: np.ndarray, atlas0: np.ndarray, epochs: int, batch: int, win: int = 9,
+              eps: float = 1e-5, lr: float = 1e-2, beta1: float = 0.9, beta2: float = 0.999,
+              adam_eps: float = 1e-8):
+    """Minibatch stochastic atlas update for NCC (Section 3, last paragraph
+    of "Dissimilarity metrics"; Algorithm 1, ``SGD_for_atlas``): ``epochs``
+    passes over the warped subjects in minibatches of ``batch`` (in subject
+    order); each minibatch takes one Adam step on A along the gradient of the
+    minibatch mean of D(Iw_i, A).  A starts from ``atlas0``; the Adam moments
+    start at zero.  Returns (A, per-minibatch losses taken before each step)."""
+    warped = np.asarray(warped, dtype=np.float64)
+    n = len(warped)
+    A = np.array(atlas0, dtype=np.float64)
+    m = np.zeros_like(A)
+    s = np.zeros_like(A)
+    t = 0
+    losses = []
+    for _ in range(epochs):
+        for b0 in range(0, n, batch):
+            idx = range(b0, min(n, b0 + batch))
+            loss, g = 0.0, np.zeros_like(A)
+            for i in idx:
+                li, gi = lncc_atlas_grad(warped[i], A, win, eps)
+                loss += li
+                g += gi
+            loss /= len(idx)
+            g /= len(idx)
+            t += 1
+            A, m, s = adam_step(A, m, s, g, t, lr, beta1, beta2, adam_eps)
+            losses.append(loss)
+    return A, losses
+
+
 # ---------------------------------------------------------------------------
 # per-subject registration and one coordinate-descent sweep
 
 
 @dataclasses.dataclass
 class SweepParams:
-    metric: str = "mse"          # "mse" | "lncc"
+    metric: str = "mse"          # "mse" | "lncc" | "l1"
     win: int = 9
     ncc_eps: float = 1e-5
     lam: float = 0.01
@@ -437,6 +498,15 @@ class SweepParams:
     adam_eps: float = 1e-8
     center_mode: str = "displacement"   # "displacement" | "velocity"
     reinit_v: bool = False
+    atlas_mode: str = "auto"     # "mean" | "median" | "sgd"; auto: median for L1, else mean
+    k3: int = 20                 # SGD atlas epochs
+    atlas_batch: int = 4         # SGD atlas minibatch
+    atlas_lr: float = 1e-2
+
+    def resolved_atlas_mode(self) -> str:
+        if self.atlas_mode != "auto":
+            return self.atlas_mode
+        return "median" if self.metric == "l1" else "mean"
 
 
 def dissimilarity(warped, atlas, p: SweepParams):
@@ -444,7 +514,24 @@ def dissimilarity(warped, atlas, p: SweepParams):
         return mse(warped, atlas)
     if p.metric == "lncc":
         return lncc(warped, atlas, p.win, p.ncc_eps)
+    if p.metric == "l1":
+        return l1(warped, atlas)
     raise ValueError(p.metric)
+
+
+def atlas_update(images, u_hat, atlas, p: SweepParams) -> np.ndarray:
+    """Step 3 of a sweep: the closed form of the metric (mean for MSE,
+    median for L1) or the minibatch stochastic update (NCC)."""
+    mode = p.resolved_atlas_mode()
+    if mode == "mean":
+        return atlas_mean(images, u_hat)
+    if mode == "median":
+        return atlas_median(images, u_hat)
+    if mode == "sgd":
+        warped = np.stack([warp3d(images[i], u_hat[i]) for i in range(len(images))])
+        return atlas_sgd(warped, atlas, p.k3, p.atlas_batch, p.win, p.ncc_eps, p.atlas_lr,
+                         p.beta1, p.beta2, p.adam_eps)[0]
+    raise ValueError(mode)
 
 
 def subject_loss_grad(img, v, atlas, p: SweepParams):
@@ -484,7 +571,7 @@ def sweep(images, v, m, s, step: int, atlas, p: SweepParams):
 
     Step 1: K2 Adam iterations per subject against the fixed atlas (subjects
     are independent, so their order does not matter).  Step 2: centring.
-    Step 3: atlas = mean of the warped subjects.  Returns a dict with the new
+    Step 3: the atlas update of ``atlas_update``.  Returns a dict with the new
     state, the inner losses ``[n, K2]`` (each taken before its step), the
     centred displacements and the group loss.
     """
@@ -513,7 +600,7 @@ def sweep(images, v, m, s, step: int, atlas, p: SweepParams):
     else:
         u = np.stack([exp_svf(v[i], p.n_sq)[0] for i in range(n)])
         u_hat, _ = center(u)
-    atlas = atlas_mean(images, u_hat)
+    atlas = atlas_update(images, u_hat, atlas, p)
     F = group_loss(images, u_hat, atlas, p)
     return dict(v=v, m=m, s=s, step=step, atlas=atlas, u_hat=u_hat,
                 inner_losses=inner, group_loss=F)
@@ -540,3 +627,110 @@ def centrality_error(u: np.ndarray) -> float:
     """mean_x |(1/n) sum_i u_i(x)|_2 in voxels."""
     mean = np.asarray(u, dtype=np.float64).mean(axis=0)
     return float(np.sqrt((mean ** 2).sum(axis=0)).mean())
+
+
+# ---------------------------------------------------------------------------
+# one-shot segmentation (Section 4, Eq. (oneshot)) and its score
+
+
+def warp_labels_nearest(labels: np.ndarray, u: np.ndarray) -> np.ndarray:
+    """Labels carried by a displacement: out(x) = L(round(x + u(x))), label 0
+    outside the volume.  Nearest-neighbour keeps labels integral.  The
+    position and its rounding, floor(p + 1/2), are taken in FP32 (the
+    precision of the fields), so the same FP32 displacement gives the same
+    labels on any IEEE FP32 machine."""
+    labels = np.asarray(labels)
+    u32 = np.asarray(u, dtype=np.float32)
+    dims = labels.shape
+    grid = np.meshgrid(*[np.arange(d, dtype=np.float32) for d in dims], indexing="ij")
+    idx, inside = [], np.ones(dims, dtype=bool)
+    for d in range(3):
+        p = grid[d] + u32[d]                               # FP32 add
+        k = np.floor(p + np.float32(0.5)).astype(np.int64)  # FP32 add, then floor
+        inside &= (k >= 0) & (k < dims[d])
+        idx.append(np.clip(k, 0, dims[d] - 1))
+    return np.where(inside, labels[idx[0], idx[1], idx[2]], 0).astype(labels.dtype)
+
+
+def segment_one_shot(atlas_labels: np.ndarray, v: np.ndarray, n_sq: int = 7) -> np.ndarray:
+    """I_i^(S) = A^(S) o Exp(-v_i): the atlas labels carried to a subject by
+    the inverse deformation, Exp(-v) (Section 4, Eq. (oneshot))."""
+    u_inv, _ = exp_svf(-np.asarray(v, dtype=np.float64), n_sq)
+    return warp_labels_nearest(atlas_labels, u_inv)
+
+
+def dice_counts(a: np.ndarray, b: np.ndarray, num_labels: int) -> np.ndarray:
+    """Per label l: (|a = l and b = l|, |a = l|, |b = l|) as int64 ``[L, 3]``.
+    Dice_l = 2 c0 / (c1 + c2)."""
+    a = np.asarray(a).ravel()
+    b = np.asarray(b).ravel()
+    out = np.zeros((num_labels, 3), dtype=np.int64)
+    for lab in range(num_labels):
+        ia, ib = a == lab, b == lab
+        out[lab] = (np.count_nonzero(ia & ib), np.count_nonzero(ia), np.count_nonzero(ib))
+    return out
+
+
+# ---------------------------------------------------------------------------
+# factor-2 resampling between the levels of a coarse-to-fine schedule.  The
+# paper runs one resolution; a pyramid is a reading for large cohorts.  Coarse
+# voxel k averages fine voxels 2k and 2k+1 per axis, so its centre sits at fine
+# coordinate 2k + 1/2 and fine voxel x sits at coarse coordinate (x - 1/2) / 2.
+
+
+def down2(f: np.ndarray) -> np.ndarray:
+    """Average of each 2x2x2 block over the last three axes (even sizes)."""
+    f = np.asarray(f, dtype=np.float64)
+    *lead, D0, D1, D2 = f.shape
+    assert D0 % 2 == 0 and D1 % 2 == 0 and D2 % 2 == 0
+    r = f.reshape(*lead, D0 // 2, 2, D1 // 2, 2, D2 // 2, 2)
+    return r.mean(axis=(-5, -3, -1))
+
+
+def up2(f: np.ndarray, scale: float = 1.0) -> np.ndarray:
+    """Trilinear upsampling of a ``[C, d0, d1, d2]`` field to twice the size:
+    out(x) = scale * S_B(f, (x - 1/2) / 2), border clamped.  ``scale = 2``
+    turns a coarse displacement (coarse voxels) into fine voxels."""
+    f = np.asarray(f, dtype=np.float64)
+    dims = tuple(2 * d for d in f.shape[1:])
+    pos = (identity_grid(dims) - 0.5) / 2.0
+    vals, _ = sample_border(f, pos)
+    return scale * vals
+
+
+def level_start(images, v, p: SweepParams):
+    """State at the start of a level: atlas from the centred Exp of the given
+    velocities (v = 0 gives the mean of the subjects), Adam moments at zero."""
+    n = len(images)
+    if p.center_mode == "velocity":
+        v, _ = center(v)
+        u_hat = np.stack([exp_svf(v[i], p.n_sq)[0] for i in range(n)])
+    else:
+        u_hat, _ = center(np.stack([exp_svf(v[i], p.n_sq)[0] for i in range(n)]))
+    atlas0 = np.asarray(images, dtype=np.float64).mean(axis=0)
+    atlas = atlas_update(images, u_hat, atlas0, p)
+    return np.array(v, dtype=np.float64), atlas
+
+
+def pyramid(images, levels: int, sweeps, p: SweepParams):
+    """Coarse-to-fine: the cohort at 1/2^(levels-1) ... 1 of its size (2x2x2
+    averaging), ``sweeps[l]`` sweeps at level l (0 = coarsest); velocities are
+    carried to the next level by ``up2(v, 2)``.  Returns the finest state."""
+    pyr = [np.asarray(images, dtype=np.float64)]
+    for _ in range(levels - 1):
+        pyr.append(down2(pyr[-1]))
+    pyr = pyr[::-1]
+    v = np.zeros((len(images), 3) + pyr[0].shape[1:])
+    out = None
+    for lev in range(levels):
+        imgs = pyr[lev]
+        if lev > 0:
+            v = np.stack([up2(v[i], 2.0) for i in range(len(imgs))])
+        v, atlas = level_start(imgs, v, p)
+        m = np.zeros_like(v)
+        s = np.zeros_like(v)
+        step = 0
+        for _ in range(sweeps[lev]):
+            out = sweep(imgs, v, m, s, step, atlas, p)
+            v, m, s, step, atlas = out["v"], out["m"], out["s"], out["step"], out["atlas"]
+    return out

@@ -15,7 +15,13 @@
  *     gradient steps against a fixed atlas, the centrality activation
  *     phi_i - (1/n) sum_j phi_j (fourth line of Eq. (3)), then the atlas
  *     update, which for MSE is the mean of the warped subjects (first equation
- *     of Section 3, "Dissimilarity metrics").
+ *     of Section 3, "Dissimilarity metrics"), for L1 their voxelwise median
+ *     (second equation there) and for NCC a minibatch stochastic descent
+ *     (last paragraph there; Algorithm 1 `SGD_for_atlas`);
+ *   - one-shot segmentation (Section 4, Eq. (oneshot)): atlas labels carried
+ *     to each subject by Exp(-v_i), with the Dice counts of Section 5;
+ *   - factor-2 resampling for a coarse-to-fine schedule of the sweeps (not in
+ *     the paper; provided for large cohorts).
  *
  * Conventions shared by every call
  *   - A volume has dims (d0, d1, d2) with d2 fastest: voxel (x0, x1, x2) sits
@@ -54,7 +60,7 @@
 extern "C" {
 #endif
 
-#define DARC_ABI_VERSION 1
+#define DARC_ABI_VERSION 2
 
 /* status codes */
 #define DARC_OK 0
@@ -66,6 +72,12 @@ extern "C" {
 /* dissimilarity metrics (Section 3, "Dissimilarity metrics") */
 #define DARC_MSE 0   /* (1/V) sum_x (Iw - A)^2 */
 #define DARC_LNCC 1  /* -(1/V) sum_x cc(x), squared local NCC over a win^3 window */
+#define DARC_L1 2    /* (1/V) sum_x |Iw - A| */
+
+/* atlas updates (step 3 of a sweep) */
+#define DARC_ATLAS_MEAN 0   /* MSE closed form: mean of the warped subjects */
+#define DARC_ATLAS_MEDIAN 1 /* L1 closed form: voxelwise median of the warped subjects */
+#define DARC_ATLAS_SGD 2    /* minibatch Adam on the LNCC of the warped subjects */
 
 /* smoothing modes */
 #define DARC_GAUSS 0     /* separable Gaussian, replicated border */
@@ -146,6 +158,8 @@ int darc_warp3d_bwd(const float* img, const float* u, const float* g_out, float*
  * (Section 3, "Dissimilarity metrics") and its gradient.
  *
  *   DARC_MSE : D_i = (1/V) sum_x (W_i - A)^2;   dD_i/dW_i = (2/V)(W_i - A).
+ *   DARC_L1  : D_i = (1/V) sum_x |W_i - A|;     dD_i/dW_i = sign(W_i - A) / V
+ *              (0 where W_i = A; the difference is formed in FP64).
  *   DARC_LNCC: window sums over the win^3 cube centred at x, zero outside the
  *              volume, with the fixed count N = win^3:
  *              cross = S_IJ - S_I S_J / N, Ivar = S_II - S_I^2 / N,
@@ -213,17 +227,95 @@ int darc_atlas_update(const float* images, const float* u, const float* mean, fl
                       int n, int d0, int d1, int d2, void* stream);
 
 /* ------------------------------------------------------------------------
+ * darc_atlas_median -- the L1 atlas closed form (Section 3, "Dissimilarity
+ * metrics", second equation): A(x) = median_i I_i(x + u_i(x) - mean(x)).
+ * For even n every value between the two middle samples minimises the L1
+ * sum; their average is returned.  Arguments as darc_atlas_update; n <= 512
+ * (DARC_EUNSUPPORTED above).  Each voxel's n samples are staged in LDS.
+ * ---------------------------------------------------------------------- */
+int darc_atlas_median(const float* images, const float* u, const float* mean, float* atlas,
+                      int n, int d0, int d1, int d2, void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_atlas_sgd -- the atlas update for NCC by minibatch stochastic descent
+ * (Section 3, last paragraph of "Dissimilarity metrics"; Algorithm 1
+ * `SGD_for_atlas`): `epochs` passes over the n warped subjects in minibatches
+ * of `batch` consecutive subjects (the last one may be smaller); each
+ * minibatch takes one Adam step on A along the gradient of
+ *   (1/|B|) sum_{i in B} D_LNCC(W_i, A)
+ * (cc is symmetric in its two images, so dD/dA is the LNCC adjoint with the
+ * roles exchanged).  The Adam moments start at zero and the step count at 1
+ * on every call; A starts from its value on entry.
+ *   warped [n][V] in; atlas [V] in/out.
+ *   losses [epochs * ceil(n / batch)] FP64 out (overwritten), or NULL: the
+ *          minibatch loss before each step.
+ *   ws     scratch of darc_atlas_sgd_ws_bytes().
+ * ---------------------------------------------------------------------- */
+size_t darc_atlas_sgd_ws_bytes(int n, int d0, int d1, int d2, int batch);
+int darc_atlas_sgd(const float* warped, float* atlas, int n, int d0, int d1, int d2, int batch,
+                   int epochs, int win, float eps, float lr, double beta1, double beta2,
+                   float adam_eps, double* losses, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_warp_labels -- a label map carried by displacements (nearest voxel,
+ * which keeps labels integral):
+ *   out_i(x) = labels(round(x + u_i(x))),  round(p) = floor(p + 1/2) per axis,
+ * with the addition and the rounding in FP32; label 0 outside the volume.
+ *   labels [V] uint8 in (shared); u [n][3][V] in; out [n][V] uint8 out.
+ *
+ * darc_segment -- one-shot segmentation (Section 4, Eq. (oneshot)):
+ *   out_i = labels o Exp(-v_i), the atlas labels carried to subject i by the
+ *   inverse deformation, Exp(-v_i) computed by scaling and squaring as in
+ *   darc_exp_svf (n_sq 1..16) into the workspace.
+ *   ws  scratch of darc_segment_ws_bytes().
+ * ---------------------------------------------------------------------- */
+int darc_warp_labels(const unsigned char* labels, const float* u, unsigned char* out, int n,
+                     int d0, int d1, int d2, void* stream);
+size_t darc_segment_ws_bytes(int n, int d0, int d1, int d2, int n_sq);
+int darc_segment(const unsigned char* labels, const float* v, unsigned char* out, int n, int d0,
+                 int d1, int d2, int n_sq, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_dice_counts -- overlap counts for the Dice score of Section 5: for
+ * each subject i and label l < num_labels (<= 256),
+ *   counts[i][l] += { |a_i = l and b_i = l|, |a_i = l|, |b_i = l| }
+ * (uint64); Dice = 2 c0 / (c1 + c2).  Labels >= num_labels are not counted.
+ *   a, b [n][V] uint8 in (V = voxels per subject, up to 2^40); counts
+ *   [n][num_labels][3] in/out, accumulated.
+ * ---------------------------------------------------------------------- */
+int darc_dice_counts(const unsigned char* a, const unsigned char* b, int n, long long V,
+                     int num_labels, unsigned long long* counts, void* stream);
+
+/* ------------------------------------------------------------------------
+ * darc_down2 / darc_up2 -- factor-2 resampling between the levels of a
+ * coarse-to-fine schedule.  Coarse voxel k averages the fine voxels 2k and
+ * 2k+1 of every axis, so fine voxel x sits at coarse coordinate (x - 1/2)/2.
+ *   darc_down2: out = 2x2x2 block means of `nchan` fine volumes
+ *               [nchan][d0][d1][d2] (even dims) into [nchan][d0/2][d1/2][d2/2].
+ *   darc_up2:   out(x) = scale * S_B(in, (x - 1/2) / 2), trilinear with border
+ *               clamping, from [nchan][d0/2][d1/2][d2/2] onto [nchan][d0][d1][d2]
+ *               (even dims); scale = 2 turns a coarse displacement or velocity
+ *               (coarse voxels) into fine voxels.
+ *   (d0, d1, d2) are the fine dims in both; in and out must not alias.
+ * ---------------------------------------------------------------------- */
+int darc_down2(const float* in, float* out, int nchan, int d0, int d1, int d2, void* stream);
+int darc_up2(const float* in, float* out, int nchan, int d0, int d1, int d2, float scale,
+             void* stream);
+
+/* ------------------------------------------------------------------------
  * darc_sweep -- one coordinate-descent sweep (Eq. (3), Algorithm 1 `main`).
  *
  *   step 1: for every subject i (independent given the atlas, Section 3 after
  *           Eq. (3)), k2 times: u = Exp(v_i); L = D(I_i o phi, A) + lam R(u);
  *           g = dL/dv_i; Adam step on v_i; if smooth_sigma > 0, v_i <- G * v_i.
  *   step 2: u_i = Exp(v_i); centrality activation (center_mode).
- *   step 3: A <- (1/n) sum_i I_i o phi_hat_i.
+ *   step 3: the atlas update of atlas_mode from the warped subjects
+ *           I_i o phi_hat_i: their mean, their median, or k3 epochs of the
+ *           minibatch update of darc_atlas_sgd starting from A^k.
  *   then the group loss F = (1/n) sum_i [D(I_i o phi_hat_i, A) + lam R(u_hat_i)].
  *
- * The atlas update is the MSE closed form for both metrics (with LNCC it is
- * the mean of the warped subjects, not an SGD atlas).
+ * k2 = 0 runs steps 2 and 3 only: the start of a level of a coarse-to-fine
+ * schedule, from velocities carried over from the coarser level.
  * ---------------------------------------------------------------------- */
 typedef struct darc_state {
   const float* images; /* [n][V] subject images I_i, in */
@@ -242,19 +334,23 @@ typedef struct darc_state {
 } darc_state;
 
 typedef struct darc_params {
-  int metric;         /* DARC_MSE or DARC_LNCC */
+  int metric;         /* DARC_MSE, DARC_LNCC or DARC_L1 */
   int win;            /* LNCC window (odd, 3..11) */
   float ncc_eps;      /* LNCC epsilon (> 0) */
   float lam;          /* diffusion regulariser weight (>= 0) */
   float smooth_sigma; /* Gaussian sigma applied to v after every step; 0 = off */
   int n_sq;           /* squaring steps, 1..16 (7 in the paper) */
-  int k2;             /* inner iterations per subject per sweep (>= 1) */
+  int k2;             /* inner iterations per subject per sweep (>= 0) */
   float lr;           /* Adam learning rate */
   double beta1, beta2; /* Adam moment decay rates, in [0, 1) */
   float adam_eps;     /* Adam epsilon (> 0) */
   int center_mode;    /* DARC_CENTER_DISPLACEMENT or DARC_CENTER_VELOCITY */
   int reinit_v;       /* 1: v, m, s and step reset to zero before step 1 */
   int batch;          /* subjects per launch in step 1: 1 = per subject, n = all */
+  int atlas_mode;     /* DARC_ATLAS_MEAN, DARC_ATLAS_MEDIAN or DARC_ATLAS_SGD */
+  int k3;             /* SGD atlas: epochs (>= 1) */
+  int atlas_batch;    /* SGD atlas: subjects per minibatch (>= 1) */
+  float atlas_lr;     /* SGD atlas: Adam learning rate (betas and eps as above) */
 } darc_params;
 
 /* sizeof(darc_state) and sizeof(darc_params) as compiled into the library,

@@ -643,12 +643,13 @@ def warp_labels_nearest(labels: np.ndarray, u: np.ndarray) -> np.ndarray:
     u32 = np.asarray(u, dtype=np.float32)
     dims = labels.shape
     grid = np.meshgrid(*[np.arange(d, dtype=np.float32) for d in dims], indexing="ij")
-    idx, inside = [], np.ones(dims, dtype=bool)
+    ks, inside = [], np.ones(dims, dtype=bool)
     for d in range(3):
-        p = grid[d] + u32[d]                               # FP32 add
-        k = np.floor(p + np.float32(0.5)).astype(np.int64)  # FP32 add, then floor
-        inside &= (k >= 0) & (k < dims[d])
-        idx.append(np.clip(k, 0, dims[d] - 1))
+        p = grid[d] + u32[d]                    # FP32 add
+        k = np.floor(p + np.float32(0.5))       # FP32 add, then floor
+        inside &= (k >= 0) & (k < dims[d])      # a NaN position is outside
+        ks.append(k)
+    idx = [np.where(inside, k, 0).astype(np.int64) for k in ks]
     return np.where(inside, labels[idx[0], idx[1], idx[2]], 0).astype(labels.dtype)
 
 
@@ -715,7 +716,9 @@ def level_start(images, v, p: SweepParams):
 def pyramid(images, levels: int, sweeps, p: SweepParams):
     """Coarse-to-fine: the cohort at 1/2^(levels-1) ... 1 of its size (2x2x2
     averaging), ``sweeps[l]`` sweeps at level l (0 = coarsest); velocities are
-    carried to the next level by ``up2(v, 2)``.  Returns the finest state."""
+    carried to the next level by ``up2(v, 2)``.  The coarsest level starts
+    like a plain run (v = 0, A^0 the mean of the subjects); every finer level
+    from ``level_start``.  Returns the finest state."""
     pyr = [np.asarray(images, dtype=np.float64)]
     for _ in range(levels - 1):
         pyr.append(down2(pyr[-1]))
@@ -726,7 +729,9 @@ def pyramid(images, levels: int, sweeps, p: SweepParams):
         imgs = pyr[lev]
         if lev > 0:
             v = np.stack([up2(v[i], 2.0) for i in range(len(imgs))])
-        v, atlas = level_start(imgs, v, p)
+            v, atlas = level_start(imgs, v, p)
+        else:
+            atlas = initial_atlas(imgs)
         m = np.zeros_like(v)
         s = np.zeros_like(v)
         step = 0

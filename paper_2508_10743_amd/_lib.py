@@ -14,7 +14,7 @@ from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_longlong, c_si
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdarc.so")
 
-DARC_ABI_VERSION = 1
+DARC_ABI_VERSION = 2
 
 DARC_OK = 0
 DARC_EINVAL = -1
@@ -24,6 +24,10 @@ DARC_EUNSUPPORTED = -4
 
 DARC_MSE = 0
 DARC_LNCC = 1
+DARC_L1 = 2
+DARC_ATLAS_MEAN = 0
+DARC_ATLAS_MEDIAN = 1
+DARC_ATLAS_SGD = 2
 DARC_GAUSS = 0
 DARC_DIFFUSION = 1
 DARC_CENTER_DISPLACEMENT = 0
@@ -74,6 +78,10 @@ class DarcParams(ctypes.Structure):
         ("center_mode", c_int),
         ("reinit_v", c_int),
         ("batch", c_int),
+        ("atlas_mode", c_int),
+        ("k3", c_int),
+        ("atlas_batch", c_int),
+        ("atlas_lr", c_float),
     ]
 
 
@@ -97,6 +105,16 @@ PROTOTYPES = {
                                c_double, c_float, _P]),
     "darc_center": (c_int, [_P, _P, _I, _I, _I, _I, _P]),
     "darc_atlas_update": (c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _P]),
+    "darc_atlas_median": (c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _P]),
+    "darc_atlas_sgd_ws_bytes": (c_size_t, [_I, _I, _I, _I, _I]),
+    "darc_atlas_sgd": (c_int, [_P, _P, _I, _I, _I, _I, _I, _I, _I, c_float, c_float, c_double,
+                               c_double, c_float, _P, _P, _Z, _P]),
+    "darc_warp_labels": (c_int, [_P, _P, _P, _I, _I, _I, _I, _P]),
+    "darc_segment_ws_bytes": (c_size_t, [_I, _I, _I, _I, _I]),
+    "darc_segment": (c_int, [_P, _P, _P, _I, _I, _I, _I, _I, _P, _Z, _P]),
+    "darc_dice_counts": (c_int, [_P, _P, _I, c_longlong, _I, _P, _P]),
+    "darc_down2": (c_int, [_P, _P, _I, _I, _I, _I, _P]),
+    "darc_up2": (c_int, [_P, _P, _I, _I, _I, _I, c_float, _P]),
     "darc_sizeof_state": (c_size_t, []),
     "darc_sizeof_params": (c_size_t, []),
     "darc_sweep_ws_bytes": (c_size_t, [POINTER(DarcState), POINTER(DarcParams)]),

@@ -277,7 +277,7 @@ int darc_sim_grad(const float* warped, const float* atlas, int metric, int win, 
                   double* loss, float* g_warped, int n, int d0, int d1, int d2, void* ws,
                   size_t ws_bytes, void* stream) {
   DARC_TRY(check_dims("darc_sim_grad", n, d0, d1, d2));
-  if (metric != DARC_MSE && metric != DARC_LNCC)
+  if (metric != DARC_MSE && metric != DARC_LNCC && metric != DARC_L1)
     return fail(DARC_EINVAL, "darc_sim_grad: unknown metric %d", metric);
   if (metric == DARC_LNCC) {
     if (win < 1 || win % 2 == 0)
@@ -290,8 +290,8 @@ int darc_sim_grad(const float* warped, const float* atlas, int metric, int win, 
   if (!warped || !atlas || !loss) return fail(DARC_EINVAL, "darc_sim_grad: NULL pointer");
   const Geom g = make_geom(d0, d1, d2);
   hipStream_t st = as_stream(stream);
-  if (metric == DARC_MSE) {
-    launch_mse(warped, atlas, loss, 1, g_warped, g, n, st);
+  if (metric != DARC_LNCC) {
+    launch_mse(warped, atlas, loss, 1, g_warped, g, n, metric == DARC_L1, st);
   } else {
     const size_t need = g_warped ? darc_sim_grad_ws_bytes(metric, n, d0, d1, d2) : 0;
     DARC_TRY(check_ws("darc_sim_grad", ws, ws_bytes, need));
@@ -365,6 +365,180 @@ int darc_atlas_update(const float* images, const float* u, const float* mean, fl
   return check_launch("darc_atlas_update");
 }
 
+int darc_atlas_median(const float* images, const float* u, const float* mean, float* atlas, int n,
+                      int d0, int d1, int d2, void* stream) {
+  DARC_TRY(check_dims("darc_atlas_median", n, d0, d1, d2));
+  if (n < 1) return fail(DARC_EINVAL, "darc_atlas_median: n must be >= 1");
+  if (median_threads(n) == 0)
+    return fail(DARC_EUNSUPPORTED, "darc_atlas_median: n = %d > 512 subjects", n);
+  if (!images || !u || !atlas) return fail(DARC_EINVAL, "darc_atlas_median: NULL pointer");
+  launch_atlas_median(images, u, mean, atlas, make_geom(d0, d1, d2), n, as_stream(stream));
+  return check_launch("darc_atlas_median");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------- stochastic atlas
+
+namespace {
+
+struct SgdLayout {
+  size_t fields, ga, m, s, sloss, total;
+};
+
+SgdLayout sgd_layout(int d0, int d1, int d2, int batch) {
+  const size_t V = static_cast<size_t>(d0) * d1 * d2;
+  SgdLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  L.fields = take(static_cast<size_t>(batch) * 4 * V * sizeof(float));
+  L.ga = take(static_cast<size_t>(batch) * V * sizeof(float));
+  L.m = take(V * sizeof(float));
+  L.s = take(V * sizeof(float));
+  L.sloss = take(static_cast<size_t>(batch) * sizeof(double));
+  L.total = off;
+  return L;
+}
+
+int check_sgd(const char* fn, int batch, int epochs, int win, float eps, float lr, double b1,
+              double b2, float aeps) {
+  if (batch < 1) return fail(DARC_EINVAL, "%s: atlas batch must be >= 1", fn);
+  if (epochs < 1) return fail(DARC_EINVAL, "%s: epochs must be >= 1", fn);
+  if (win < 1 || win % 2 == 0) return fail(DARC_EINVAL, "%s: window %d must be odd", fn, win);
+  if (!lncc_window_supported(win))
+    return fail(DARC_EUNSUPPORTED, "%s: window %d not built (3, 5, 7, 9, 11)", fn, win);
+  if (!(eps > 0.0f)) return fail(DARC_EINVAL, "%s: eps must be > 0", fn);
+  if (!(lr > 0.0f)) return fail(DARC_EINVAL, "%s: learning rate must be > 0", fn);
+  if (!(b1 >= 0.0 && b1 < 1.0 && b2 >= 0.0 && b2 < 1.0))
+    return fail(DARC_EINVAL, "%s: betas must lie in [0, 1)", fn);
+  if (!(aeps > 0.0f)) return fail(DARC_EINVAL, "%s: adam eps must be > 0", fn);
+  return DARC_OK;
+}
+
+// epochs x minibatches of one Adam step on the atlas each
+void run_atlas_sgd(const float* warped, float* atlas, int n, const Geom& g, int batch, int epochs,
+                   int win, float eps, float lr, double b1, double b2, float aeps, double* losses,
+                   char* ws, hipStream_t s) {
+  const SgdLayout L = sgd_layout(g.d0, g.d1, g.d2, batch);
+  float* fields = reinterpret_cast<float*>(ws + L.fields);
+  float* ga = reinterpret_cast<float*>(ws + L.ga);
+  float* m = reinterpret_cast<float*>(ws + L.m);
+  float* sv = reinterpret_cast<float*>(ws + L.s);
+  double* sloss = reinterpret_cast<double*>(ws + L.sloss);
+  launch_fill_f32(m, g.V, 0.0f, s);
+  launch_fill_f32(sv, g.V, 0.0f, s);
+  long long t = 0;
+  for (int e = 0; e < epochs; ++e) {
+    for (int b0 = 0; b0 < n; b0 += batch) {
+      const int nb = n - b0 < batch ? n - b0 : batch;
+      ++t;
+      launch_fill_f64(sloss, nb, 0.0, s);
+      launch_lncc_atlas_grad(warped + static_cast<size_t>(b0) * g.V, atlas, fields, ga, sloss, 1,
+                             win, eps, g, nb, s);
+      if (losses) launch_sum_f64(sloss, nb, 1.0 / nb, losses + (t - 1), s);
+      launch_adam_batch_mean(atlas, m, sv, ga, nb, g.V, t, lr, b1, b2, aeps, s);
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t darc_atlas_sgd_ws_bytes(int n, int d0, int d1, int d2, int batch) {
+  if (n < 1 || batch < 1 || d0 < 2 || d1 < 2 || d2 < 2) return 0;
+  return sgd_layout(d0, d1, d2, batch < n ? batch : n).total;
+}
+
+int darc_atlas_sgd(const float* warped, float* atlas, int n, int d0, int d1, int d2, int batch,
+                   int epochs, int win, float eps, float lr, double beta1, double beta2,
+                   float adam_eps, double* losses, void* ws, size_t ws_bytes, void* stream) {
+  DARC_TRY(check_dims("darc_atlas_sgd", n, d0, d1, d2));
+  if (n < 1) return fail(DARC_EINVAL, "darc_atlas_sgd: n must be >= 1");
+  DARC_TRY(check_sgd("darc_atlas_sgd", batch, epochs, win, eps, lr, beta1, beta2, adam_eps));
+  if (!warped || !atlas) return fail(DARC_EINVAL, "darc_atlas_sgd: NULL pointer");
+  const int b = batch < n ? batch : n;
+  DARC_TRY(check_ws("darc_atlas_sgd", ws, ws_bytes, darc_atlas_sgd_ws_bytes(n, d0, d1, d2, b)));
+  run_atlas_sgd(warped, atlas, n, make_geom(d0, d1, d2), b, epochs, win, eps, lr, beta1, beta2,
+                adam_eps, losses, static_cast<char*>(ws), as_stream(stream));
+  return check_launch("darc_atlas_sgd");
+}
+
+// ------------------------------------------------- one-shot segmentation
+
+int darc_warp_labels(const unsigned char* labels, const float* u, unsigned char* out, int n,
+                     int d0, int d1, int d2, void* stream) {
+  DARC_TRY(check_dims("darc_warp_labels", n, d0, d1, d2));
+  if (n == 0) return ok();
+  if (!labels || !u || !out) return fail(DARC_EINVAL, "darc_warp_labels: NULL pointer");
+  launch_warp_labels(labels, u, out, make_geom(d0, d1, d2), n, as_stream(stream));
+  return check_launch("darc_warp_labels");
+}
+
+size_t darc_segment_ws_bytes(int n, int d0, int d1, int d2, int n_sq) {
+  if (n <= 0 || n_sq < 1 || n_sq > 16 || d0 < 2 || d1 < 2 || d2 < 2) return 0;
+  return (n_sq >= 2 ? 2 : 1) * align256(field_bytes(n, d0, d1, d2));
+}
+
+int darc_segment(const unsigned char* labels, const float* v, unsigned char* out, int n, int d0,
+                 int d1, int d2, int n_sq, void* ws, size_t ws_bytes, void* stream) {
+  DARC_TRY(check_dims("darc_segment", n, d0, d1, d2));
+  if (n_sq < 1 || n_sq > 16) return fail(DARC_EINVAL, "darc_segment: n_sq must be in 1..16");
+  if (n == 0) return ok();
+  if (!labels || !v || !out) return fail(DARC_EINVAL, "darc_segment: NULL pointer");
+  DARC_TRY(check_ws("darc_segment", ws, ws_bytes, darc_segment_ws_bytes(n, d0, d1, d2, n_sq)));
+  const Geom g = make_geom(d0, d1, d2);
+  hipStream_t st = as_stream(stream);
+  float* u = static_cast<float*>(ws);
+  float* tmp = n_sq >= 2
+                   ? reinterpret_cast<float*>(static_cast<char*>(ws) +
+                                              align256(field_bytes(n, d0, d1, d2)))
+                   : nullptr;
+  run_exp_fwd(v, u, nullptr, tmp, nullptr, g, n, n_sq, st, /*negate=*/true);
+  launch_warp_labels(labels, u, out, g, n, st);
+  return check_launch("darc_segment");
+}
+
+int darc_dice_counts(const unsigned char* a, const unsigned char* b, int n, long long V,
+                     int num_labels, unsigned long long* counts, void* stream) {
+  if (n < 0 || V < 0) return fail(DARC_EINVAL, "darc_dice_counts: n and V must be >= 0");
+  if (V > (1ll << 40)) return fail(DARC_EINVAL, "darc_dice_counts: V above 2^40");
+  if (n > 65535) return fail(DARC_EINVAL, "darc_dice_counts: n above 65535");
+  if (num_labels < 1 || num_labels > 256)
+    return fail(DARC_EINVAL, "darc_dice_counts: num_labels must be in 1..256");
+  if (n == 0 || V == 0) return ok();
+  if (!a || !b || !counts) return fail(DARC_EINVAL, "darc_dice_counts: NULL pointer");
+  launch_dice_counts(a, b, n, V, num_labels, counts, as_stream(stream));
+  return check_launch("darc_dice_counts");
+}
+
+// ------------------------------------------------------------- resampling
+
+int darc_down2(const float* in, float* out, int nchan, int d0, int d1, int d2, void* stream) {
+  DARC_TRY(check_dims("darc_down2", nchan, d0, d1, d2));
+  if (d0 % 2 || d1 % 2 || d2 % 2 || d0 < 4 || d1 < 4 || d2 < 4)
+    return fail(DARC_EINVAL, "darc_down2: fine dims must be even and >= 4");
+  if (nchan == 0) return ok();
+  if (!in || !out || in == out) return fail(DARC_EINVAL, "darc_down2: bad pointers");
+  launch_down2(in, out, make_geom(d0, d1, d2), nchan, as_stream(stream));
+  return check_launch("darc_down2");
+}
+
+int darc_up2(const float* in, float* out, int nchan, int d0, int d1, int d2, float scale,
+             void* stream) {
+  DARC_TRY(check_dims("darc_up2", nchan, d0, d1, d2));
+  if (d0 % 2 || d1 % 2 || d2 % 2 || d0 < 4 || d1 < 4 || d2 < 4)
+    return fail(DARC_EINVAL, "darc_up2: fine dims must be even and >= 4");
+  if (nchan == 0) return ok();
+  if (!in || !out || in == out) return fail(DARC_EINVAL, "darc_up2: bad pointers");
+  launch_up2(in, out, make_geom(d0, d1, d2), nchan, scale, as_stream(stream));
+  return check_launch("darc_up2");
+}
+
 }  // extern "C"
 
 // ------------------------------------------------------------------- sweep
@@ -373,7 +547,7 @@ namespace {
 
 struct SweepLayout {
   int B;
-  size_t ckpt, aux, uN, gU, gA, gB, gV, iw, fields, vtmp, uhat, sloss, bc, total;
+  size_t ckpt, aux, uN, gU, gA, gB, gV, iw, fields, vtmp, uhat, sloss, bc, wall, sgd, total;
 };
 
 SweepLayout sweep_layout(const darc_state* st, const darc_params* p) {
@@ -402,6 +576,10 @@ SweepLayout sweep_layout(const darc_state* st, const darc_params* p) {
   L.uhat = take(st->u_hat ? 0 : static_cast<size_t>(n) * 3 * V * sizeof(float));
   L.sloss = take(static_cast<size_t>(n) * sizeof(double));
   L.bc = take(static_cast<size_t>(p->k2) * 2 * sizeof(float));
+  const bool sgd = p->atlas_mode == DARC_ATLAS_SGD;
+  const int ab = p->atlas_batch < n ? p->atlas_batch : n;
+  L.wall = take(sgd ? static_cast<size_t>(n) * V * sizeof(float) : 0);
+  L.sgd = take(sgd ? sgd_layout(st->d0, st->d1, st->d2, ab).total : 0);
   L.total = off;
   return L;
 }
@@ -412,7 +590,7 @@ int check_sweep(const darc_state* st, const darc_params* p) {
   if (st->n < 1) return fail(DARC_EINVAL, "darc_sweep: n must be >= 1");
   if (!st->images || !st->v || !st->m || !st->s || !st->atlas)
     return fail(DARC_EINVAL, "darc_sweep: images, v, m, s and atlas must not be NULL");
-  if (p->metric != DARC_MSE && p->metric != DARC_LNCC)
+  if (p->metric != DARC_MSE && p->metric != DARC_LNCC && p->metric != DARC_L1)
     return fail(DARC_EINVAL, "darc_sweep: unknown metric %d", p->metric);
   if (p->metric == DARC_LNCC) {
     if (p->win < 1 || p->win % 2 == 0)
@@ -429,7 +607,18 @@ int check_sweep(const darc_state* st, const darc_params* p) {
       return fail(DARC_EUNSUPPORTED, "darc_sweep: Gaussian radius %d not in 1..8", r);
   }
   if (p->n_sq < 1 || p->n_sq > 16) return fail(DARC_EINVAL, "darc_sweep: n_sq must be in 1..16");
-  if (p->k2 < 1) return fail(DARC_EINVAL, "darc_sweep: k2 must be >= 1");
+  if (p->k2 < 0) return fail(DARC_EINVAL, "darc_sweep: k2 must be >= 0");
+  if (p->atlas_mode == DARC_ATLAS_MEDIAN) {
+    if (median_threads(st->n) == 0)
+      return fail(DARC_EUNSUPPORTED, "darc_sweep: median atlas of n = %d > 512 subjects", st->n);
+  } else if (p->atlas_mode == DARC_ATLAS_SGD) {
+    if (p->metric != DARC_LNCC)
+      return fail(DARC_EINVAL, "darc_sweep: the stochastic atlas update is for the LNCC metric");
+    DARC_TRY(check_sgd("darc_sweep", p->atlas_batch, p->k3, p->win, p->ncc_eps, p->atlas_lr,
+                       p->beta1, p->beta2, p->adam_eps));
+  } else if (p->atlas_mode != DARC_ATLAS_MEAN) {
+    return fail(DARC_EINVAL, "darc_sweep: unknown atlas_mode %d", p->atlas_mode);
+  }
   if (!(p->beta1 >= 0.0 && p->beta1 < 1.0 && p->beta2 >= 0.0 && p->beta2 < 1.0))
     return fail(DARC_EINVAL, "darc_sweep: betas must lie in [0, 1)");
   if (!(p->adam_eps > 0.0f)) return fail(DARC_EINVAL, "darc_sweep: adam_eps must be > 0");
@@ -477,6 +666,7 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
   float* bc = reinterpret_cast<float*>(w + L.bc);
   const RegW rw = make_regw(g, 3, p->lam);
   const bool lncc = p->metric == DARC_LNCC;
+  const bool l1 = p->metric == DARC_L1;
   const bool smooth = p->smooth_sigma > 0.0f;
 
   launch_fill_f64(losses, static_cast<long long>(n) * k2 + 1, 0.0, s);
@@ -502,7 +692,7 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
       double* lslot = losses + static_cast<size_t>(b0) * k2 + k;
       run_exp_fwd(vb, uN, ckpt, nullptr, aux, g, nb, N, s);
       if (!lncc) {
-        launch_mse_fused(ib, st->atlas, uN, gU, lslot, k2, rw, g, nb, s);
+        launch_mse_fused(ib, st->atlas, uN, gU, lslot, k2, rw, g, nb, l1, s);
       } else {
         launch_warp(ib, uN, iw, g, nb, s);
         launch_lncc_fwd(iw, st->atlas, fields, lslot, k2, p->win, p->ncc_eps, g, nb, s);
@@ -531,8 +721,17 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
   }
   if (p->center_mode == DARC_CENTER_DISPLACEMENT) launch_center(uh, nullptr, g, n, s);
 
-  // step 3: atlas = mean of the warped subjects
-  launch_atlas(st->images, uh, nullptr, st->atlas, g, n, s);
+  // step 3: the atlas update from the warped subjects
+  if (p->atlas_mode == DARC_ATLAS_MEDIAN) {
+    launch_atlas_median(st->images, uh, nullptr, st->atlas, g, n, s);
+  } else if (p->atlas_mode == DARC_ATLAS_SGD) {
+    float* wall = reinterpret_cast<float*>(w + L.wall);
+    launch_warp(st->images, uh, wall, g, n, s);
+    run_atlas_sgd(wall, st->atlas, n, g, p->atlas_batch < n ? p->atlas_batch : n, p->k3, p->win,
+                  p->ncc_eps, p->atlas_lr, p->beta1, p->beta2, p->adam_eps, nullptr, w + L.sgd, s);
+  } else {
+    launch_atlas(st->images, uh, nullptr, st->atlas, g, n, s);
+  }
 
   // group loss at the new atlas
   launch_fill_f64(sloss, n, 0.0, s);
@@ -540,7 +739,7 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
     const int nb = n - b0 < B ? n - b0 : B;
     const float* ib = st->images + static_cast<size_t>(b0) * g.V;
     if (!lncc) {
-      launch_mse_fused(ib, st->atlas, uh + b0 * fsv, nullptr, sloss + b0, 1, rw, g, nb, s);
+      launch_mse_fused(ib, st->atlas, uh + b0 * fsv, nullptr, sloss + b0, 1, rw, g, nb, l1, s);
     } else {
       launch_warp(ib, uh + b0 * fsv, iw, g, nb, s);
       launch_lncc_fwd(iw, st->atlas, nullptr, sloss + b0, 1, p->win, p->ncc_eps, g, nb, s);

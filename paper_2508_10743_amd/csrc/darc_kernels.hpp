@@ -18,10 +18,11 @@ RegW make_regw(const Geom& g, int ncomp, float lam);
 // without global atomics.  `aux` holds [n_sq][n][ntiles][8] boxes followed by
 // [n_sq][n][8] reaches (ints).
 size_t exp_aux_bytes(const Geom& g, int n, int n_sq);
-// Full Exp(v): ckpt ([n_sq-1][n][3][V]) or tmp ([n][3][V]) must be given when
-// n_sq >= 2; aux (nullable) receives the boxes the adjoint needs.
+// Full Exp(v) (Exp(-v) when negate, n_sq >= 1): ckpt ([n_sq-1][n][3][V]) or
+// tmp ([n][3][V]) must be given when n_sq >= 2; aux (nullable) receives the
+// boxes the adjoint needs.
 void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, int* aux, const Geom& g, int n,
-                 int n_sq, hipStream_t st);
+                 int n_sq, hipStream_t st, bool negate = false);
 // Full adjoint; tmp_a, tmp_b are [n][3][V]; g_v must not alias g_u.  When
 // aux_ready is false the boxes in aux are recomputed from v and ckpt first.
 void run_exp_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, float* tmp_a,
@@ -40,13 +41,15 @@ void launch_warp_bwd(const float* img, const float* u, const float* gout, float*
                      int n, hipStream_t st);
 
 // --- dissimilarities and regulariser --------------------------------------
-// MSE on given warped images: loss[i * loss_stride] += D_i; gw may be null.
+// MSE (or L1 when l1) on given warped images: loss[i * loss_stride] += D_i;
+// gw may be null.
 void launch_mse(const float* w, const float* atlas, double* loss, int loss_stride, float* gw,
-                const Geom& g, int n, hipStream_t st);
-// Warp + MSE + (optional) diffusion regulariser, fused.  With gu non-null it
-// also writes gu = dL/du (overwrite); loss[i * loss_stride] += D_i + lam R(u_i).
+                const Geom& g, int n, bool l1, hipStream_t st);
+// Warp + MSE or L1 + (optional) diffusion regulariser, fused.  With gu
+// non-null it also writes gu = dL/du (overwrite); loss[i * loss_stride] +=
+// D_i + lam R(u_i).
 void launch_mse_fused(const float* img, const float* atlas, const float* u, float* gu,
-                      double* loss, int loss_stride, const RegW& rw, const Geom& g, int n,
+                      double* loss, int loss_stride, const RegW& rw, const Geom& g, int n, bool l1,
                       hipStream_t st);
 // Diffusion regulariser of an ncomp-component field: out += lam dR/din
 // (when out is non-null) and loss[i * loss_stride] += lam R (when non-null).
@@ -67,6 +70,13 @@ bool launch_lncc_bwd_fused(const float* fields, const float* w, const float* atl
                            const float* img, const float* u, float* gu, double* loss,
                            int loss_stride, const RegW& rw, int win, const Geom& g, int n,
                            hipStream_t st);
+
+// dD(warped_i, A)/dA for each of n warped subjects (the LNCC of one atlas
+// against n images; cc is symmetric in its two images): ga [n][V] (overwrite),
+// fields [n][4][V] scratch, loss[i * loss_stride] += D_i.
+bool launch_lncc_atlas_grad(const float* warped, const float* atlas, float* fields, float* ga,
+                            double* loss, int loss_stride, int win, double eps, const Geom& g,
+                            int n, hipStream_t st);
 
 bool lncc_window_supported(int win);
 int gauss_radius(float sigma);
@@ -100,6 +110,28 @@ void launch_adam_dev(const float* v_in, float* v_out, float* m, float* s, const 
                      long long count, const long long* step_dev, int k, float* bc, float lr,
                      double b1, double b2, float eps, hipStream_t st);
 void launch_step_add(long long* step_dev, long long k, hipStream_t st);
+
+// --- other branches: L1 atlas, stochastic NCC atlas, labels, resampling ----
+// Threads per block of the median atlas for n subjects (0: n > 512 is not
+// supported); each thread keeps n samples in LDS.
+int median_threads(int n);
+void launch_atlas_median(const float* images, const float* u, const float* mean, float* atlas,
+                         const Geom& g, int n, hipStream_t st);
+// a <- Adam(a, (1/nb) sum_j ga[j]) with step count t; ga is [nb][V].
+void launch_adam_batch_mean(float* a, float* m, float* s, const float* ga, int nb, long long V,
+                            long long t, float lr, double b1, double b2, float eps,
+                            hipStream_t st);
+// out [n][V] = labels [V] carried by u [n][3][V] (nearest voxel, 0 outside).
+void launch_warp_labels(const uint8_t* labels, const float* u, uint8_t* out, const Geom& g, int n,
+                        hipStream_t st);
+// counts [n][L][3] += per-label (intersection, |a = l|, |b = l|); L <= 256.
+void launch_dice_counts(const uint8_t* a, const uint8_t* b, int n, long long V, int L,
+                        unsigned long long* counts, hipStream_t st);
+// 2x2x2 averaging of nchan volumes of the (even) fine geometry, and trilinear
+// upsampling of nchan coarse volumes onto the fine geometry, times scale.
+void launch_down2(const float* in, float* out, const Geom& fine, int nchan, hipStream_t st);
+void launch_up2(const float* in, float* out, const Geom& fine, int nchan, float scale,
+                hipStream_t st);
 
 // --- small helpers --------------------------------------------------------
 void launch_fill_f32(float* p, long long count, float value, hipStream_t st);

@@ -954,7 +954,7 @@ int march_tz(const TileGeom& tg, int n) {
 }
 
 void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, int* aux, const Geom& g, int n,
-                 int n_sq, hipStream_t st) {
+                 int n_sq, hipStream_t st, bool negate) {
   const size_t fs = static_cast<size_t>(n) * 3 * g.V;
   if (n_sq == 0) {
     prof_begin(st, KC_MISC);
@@ -969,7 +969,8 @@ void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, int* aux, co
   if (aux)
     launch_fill_f32(reinterpret_cast<float*>(ap.reach),
                     static_cast<long long>(ap.reach_stride) * n_sq, 0.0f, st);
-  const float scale = ldexpf(1.0f, -n_sq);
+  // Exp(-v) negates the scaled field of the first step (exact)
+  const float scale = negate ? -ldexpf(1.0f, -n_sq) : ldexpf(1.0f, -n_sq);
   const float* src = v;
   for (int t = 0; t < n_sq; ++t) {
     float* dst;

@@ -62,6 +62,20 @@ __global__ __launch_bounds__(kBlock) void k_warp_bwd(const float* __restrict__ i
 
 // -------------------------------------------------------------------- MSE
 
+// Pointwise dissimilarity of d = Iw - A: MSE (d^2, gradient 2d/V) or L1
+// (|d|, subgradient sign(d)/V with sign(0) = 0).  The difference is formed in
+// FP64 from the FP32 inputs, so the sign is exact.
+template <bool L1>
+__device__ __forceinline__ double point_loss(double d) {
+  return L1 ? fabs(d) : d * d;
+}
+template <bool L1>
+__device__ __forceinline__ float point_grad(double d, double inv_v) {
+  return L1 ? static_cast<float>(((d > 0.0) - (d < 0.0)) * inv_v)
+            : static_cast<float>(2.0 * inv_v * d);
+}
+
+template <bool L1>
 __global__ __launch_bounds__(kBlock) void k_mse(const float* __restrict__ w,
                                                 const float* __restrict__ atlas,
                                                 double* __restrict__ loss, int loss_stride,
@@ -73,15 +87,15 @@ __global__ __launch_bounds__(kBlock) void k_mse(const float* __restrict__ w,
   if (vb.lin < g.V) {
     const size_t idx = static_cast<size_t>(vb.s) * g.V + vb.lin;
     const double diff = static_cast<double>(w[idx]) - static_cast<double>(atlas[vb.lin]);
-    acc = diff * diff;
-    if (gw) gw[idx] = static_cast<float>(2.0 * inv_v * diff);
+    acc = point_loss<L1>(diff);
+    if (gw) gw[idx] = point_grad<L1>(diff, inv_v);
   }
   const double tot = block_sum<kBlock>(acc, red);
   if (threadIdx.x == 0) atomicAdd(loss + static_cast<size_t>(vb.s) * loss_stride, tot * inv_v);
 }
 
-// Warp + MSE + diffusion regulariser (+ their adjoints when GRAD).
-template <bool GRAD>
+// Warp + MSE or L1 + diffusion regulariser (+ their adjoints when GRAD).
+template <bool L1, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_mse_fused(const float* __restrict__ img,
                                                       const float* __restrict__ atlas,
                                                       const float* __restrict__ u,
@@ -101,7 +115,7 @@ __global__ __launch_bounds__(kBlock) void k_mse_fused(const float* __restrict__ 
     voxel_coords(g, lin, x0, x1, x2);
     const Tri t = sample_zero(I, g, x0, x1, x2, f[lin], f[g.V + lin], f[2 * g.V + lin]);
     const double diff = static_cast<double>(t.v) - static_cast<double>(atlas[lin]);
-    acc = diff * diff * inv_v;
+    acc = point_loss<L1>(diff) * inv_v;
     float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f;
     if (rw.on) {
       double racc = 0.0;
@@ -111,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_mse_fused(const float* __restrict__ 
       acc += rw.lam * racc;
     }
     if (GRAD) {
-      const float gw = static_cast<float>(2.0 * inv_v * diff);
+      const float gw = point_grad<L1>(diff, inv_v);
       float* o = gu + off;
       o[lin] = gw * t.d0 + r0;
       o[g.V + lin] = gw * t.d1 + r1;
@@ -314,25 +328,38 @@ void launch_warp_bwd(const float* img, const float* u, const float* gout, float*
 }
 
 void launch_mse(const float* w, const float* atlas, double* loss, int loss_stride, float* gw,
-                const Geom& g, int n, hipStream_t st) {
+                const Geom& g, int n, bool l1, hipStream_t st) {
   const uint32_t nbx = blocks_for(g.V, kBlock), total = nbx * n;
   prof_begin(st, KC_MSE);
-  hipLaunchKernelGGL(k_mse, dim3(total), dim3(kBlock), 0, st, w, atlas, loss, loss_stride, gw, g,
-                     1.0 / g.V, nbx, total);
+  if (l1)
+    hipLaunchKernelGGL(k_mse<true>, dim3(total), dim3(kBlock), 0, st, w, atlas, loss, loss_stride,
+                       gw, g, 1.0 / g.V, nbx, total);
+  else
+    hipLaunchKernelGGL(k_mse<false>, dim3(total), dim3(kBlock), 0, st, w, atlas, loss, loss_stride,
+                       gw, g, 1.0 / g.V, nbx, total);
   prof_end(st, KC_MSE);
 }
 
-void launch_mse_fused(const float* img, const float* atlas, const float* u, float* gu,
-                      double* loss, int loss_stride, const RegW& rw, const Geom& g, int n,
-                      hipStream_t st) {
+template <bool L1>
+void mse_fused_l(const float* img, const float* atlas, const float* u, float* gu, double* loss,
+                 int loss_stride, const RegW& rw, const Geom& g, int n, hipStream_t st) {
   const uint32_t nbx = blocks_for(g.V, kBlock), total = nbx * n;
-  prof_begin(st, KC_MSE);
   if (gu)
-    hipLaunchKernelGGL((k_mse_fused<true>), dim3(total), dim3(kBlock), 0, st, img, atlas, u, gu,
-                       loss, loss_stride, rw, g, 1.0 / g.V, nbx, total);
+    hipLaunchKernelGGL((k_mse_fused<L1, true>), dim3(total), dim3(kBlock), 0, st, img, atlas, u,
+                       gu, loss, loss_stride, rw, g, 1.0 / g.V, nbx, total);
   else
-    hipLaunchKernelGGL((k_mse_fused<false>), dim3(total), dim3(kBlock), 0, st, img, atlas, u, gu,
-                       loss, loss_stride, rw, g, 1.0 / g.V, nbx, total);
+    hipLaunchKernelGGL((k_mse_fused<L1, false>), dim3(total), dim3(kBlock), 0, st, img, atlas, u,
+                       gu, loss, loss_stride, rw, g, 1.0 / g.V, nbx, total);
+}
+
+void launch_mse_fused(const float* img, const float* atlas, const float* u, float* gu,
+                      double* loss, int loss_stride, const RegW& rw, const Geom& g, int n, bool l1,
+                      hipStream_t st) {
+  prof_begin(st, KC_MSE);
+  if (l1)
+    mse_fused_l<true>(img, atlas, u, gu, loss, loss_stride, rw, g, n, st);
+  else
+    mse_fused_l<false>(img, atlas, u, gu, loss, loss_stride, rw, g, n, st);
   prof_end(st, KC_MSE);
 }
 

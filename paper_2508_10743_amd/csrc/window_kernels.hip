@@ -77,7 +77,8 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
                                                   const float* __restrict__ atlas,
                                                   float* __restrict__ fields,
                                                   double* __restrict__ loss, int loss_stride,
-                                                  MarchGeom mg, double eps, double neg_inv_v) {
+                                                  MarchGeom mg, double eps, double neg_inv_v,
+                                                  long long wstr, long long astr) {
   constexpr int R = W / 2, HX = kTX + 2 * R, HY = kTY + 2 * R;
   constexpr double kInvN = 1.0 / (W * W * W);
   __shared__ double sI[HY * HX];
@@ -87,7 +88,8 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
   const Geom& g = mg.g;
   const Tile tl = march_tile(mg);
   const int tid = threadIdx.x, lx = tid % kTX, ly = tid / kTX;
-  const float* I = wimg + static_cast<size_t>(tl.chan) * g.V;
+  const float* I = wimg + tl.chan * wstr;
+  const float* Jm = atlas + tl.chan * astr;
   double ring[W][5];
   double S[5];
 #pragma unroll
@@ -112,7 +114,7 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
           if (zin && y >= 0 && y < g.d1 && x >= 0 && x < g.d2) {
             const int idx = (zz * g.d1 + y) * g.d2 + x;
             vi = I[idx];
-            vj = atlas[idx];
+            vj = Jm[idx];
           }
           sI[e] = vi;
           sJ[e] = vj;
@@ -184,7 +186,7 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
     const float* __restrict__ fields, const float* __restrict__ wimg,
     const float* __restrict__ atlas, float* __restrict__ gw, const float* __restrict__ img,
     const float* __restrict__ u, float* __restrict__ gu, double* __restrict__ loss,
-    int loss_stride, RegW rw, MarchGeom mg, double neg_inv_v) {
+    int loss_stride, RegW rw, MarchGeom mg, double neg_inv_v, long long wstr, long long astr) {
   constexpr int R = W / 2, HX = kTX + 2 * R, HY = kTY + 2 * R;
   __shared__ double sIn[4][HY * HX];
   __shared__ double sr[4][HY * kTX];
@@ -251,8 +253,8 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
         if (zo >= tl.z0 && y < g.d1 && x < g.d2) {
           const int idx = (zo * g.d1 + y) * g.d2 + x;
           const size_t vidx = static_cast<size_t>(tl.chan) * g.V + idx;
-          const double Jc = atlas[idx];
-          const double Ic = wimg[vidx];
+          const double Jc = atlas[tl.chan * astr + idx];
+          const double Ic = wimg[tl.chan * wstr + idx];
           const double gI = neg_inv_v * (Jc * S[0] - S[1] - Ic * S[2] + S[3]);
           if (!FUSED) {
             gw[vidx] = static_cast<float>(gI);
@@ -348,38 +350,58 @@ __global__ __launch_bounds__(kNT) void k_gauss(const float* __restrict__ in,
   }
 }
 
+// Operand strides between channels: the image operand advances by wstr
+// and the reference by astr elements (V and 0 for warped subjects against one
+// atlas; 0 and V for the atlas against each warped subject).
+struct Strides {
+  long long w, a;
+};
+
 template <int W>
 void lncc_fwd_w(const float* w, const float* atlas, float* fields, double* loss, int loss_stride,
-                double eps, const Geom& g, int n, hipStream_t st) {
+                double eps, const Geom& g, int n, Strides sd, hipStream_t st) {
   const MarchGeom mg = make_march(g, n, W / 2);
   const double neg_inv_v = -1.0 / g.V;
   if (fields)
     hipLaunchKernelGGL((k_lncc_fwd<W, true>), dim3(mg.total), dim3(kNT), 0, st, w, atlas, fields,
-                       loss, loss_stride, mg, eps, neg_inv_v);
+                       loss, loss_stride, mg, eps, neg_inv_v, sd.w, sd.a);
   else
     hipLaunchKernelGGL((k_lncc_fwd<W, false>), dim3(mg.total), dim3(kNT), 0, st, w, atlas, fields,
-                       loss, loss_stride, mg, eps, neg_inv_v);
+                       loss, loss_stride, mg, eps, neg_inv_v, sd.w, sd.a);
 }
 
 template <int W, bool FUSED>
 void lncc_bwd_w(const float* fields, const float* w, const float* atlas, float* gw,
                 const float* img, const float* u, float* gu, double* loss, int loss_stride,
-                const RegW& rw, const Geom& g, int n, hipStream_t st) {
+                const RegW& rw, const Geom& g, int n, Strides sd, hipStream_t st) {
   const MarchGeom mg = make_march(g, n, W / 2);
   hipLaunchKernelGGL((k_lncc_bwd<W, FUSED>), dim3(mg.total), dim3(kNT), 0, st, fields, w, atlas,
-                     gw, img, u, gu, loss, loss_stride, rw, mg, -1.0 / g.V);
+                     gw, img, u, gu, loss, loss_stride, rw, mg, -1.0 / g.V, sd.w, sd.a);
+}
+
+bool lncc_fwd_dispatch(const float* w, const float* atlas, float* fields, double* loss,
+                       int loss_stride, int win, double eps, const Geom& g, int n, Strides sd,
+                       hipStream_t st) {
+  switch (win) {
+    case 3: lncc_fwd_w<3>(w, atlas, fields, loss, loss_stride, eps, g, n, sd, st); return true;
+    case 5: lncc_fwd_w<5>(w, atlas, fields, loss, loss_stride, eps, g, n, sd, st); return true;
+    case 7: lncc_fwd_w<7>(w, atlas, fields, loss, loss_stride, eps, g, n, sd, st); return true;
+    case 9: lncc_fwd_w<9>(w, atlas, fields, loss, loss_stride, eps, g, n, sd, st); return true;
+    case 11: lncc_fwd_w<11>(w, atlas, fields, loss, loss_stride, eps, g, n, sd, st); return true;
+    default: return false;
+  }
 }
 
 template <bool FUSED>
 bool lncc_bwd_dispatch(const float* fields, const float* w, const float* atlas, float* gw,
                        const float* img, const float* u, float* gu, double* loss, int loss_stride,
-                       const RegW& rw, int win, const Geom& g, int n, hipStream_t st) {
+                       const RegW& rw, int win, const Geom& g, int n, Strides sd, hipStream_t st) {
   switch (win) {
-    case 3: lncc_bwd_w<3, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, st); return true;
-    case 5: lncc_bwd_w<5, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, st); return true;
-    case 7: lncc_bwd_w<7, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, st); return true;
-    case 9: lncc_bwd_w<9, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, st); return true;
-    case 11: lncc_bwd_w<11, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, st); return true;
+    case 3: lncc_bwd_w<3, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, sd, st); return true;
+    case 5: lncc_bwd_w<5, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, sd, st); return true;
+    case 7: lncc_bwd_w<7, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, sd, st); return true;
+    case 9: lncc_bwd_w<9, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, sd, st); return true;
+    case 11: lncc_bwd_w<11, FUSED>(fields, w, atlas, gw, img, u, gu, loss, loss_stride, rw, g, n, sd, st); return true;
     default: return false;
   }
 }
@@ -401,14 +423,24 @@ bool launch_lncc_fwd(const float* w, const float* atlas, float* fields, double* 
                      int loss_stride, int win, double eps, const Geom& g, int n, hipStream_t st) {
   if (!lncc_window_supported(win)) return false;
   prof_begin(st, KC_LNCC_FWD);
-  switch (win) {
-    case 3: lncc_fwd_w<3>(w, atlas, fields, loss, loss_stride, eps, g, n, st); break;
-    case 5: lncc_fwd_w<5>(w, atlas, fields, loss, loss_stride, eps, g, n, st); break;
-    case 7: lncc_fwd_w<7>(w, atlas, fields, loss, loss_stride, eps, g, n, st); break;
-    case 9: lncc_fwd_w<9>(w, atlas, fields, loss, loss_stride, eps, g, n, st); break;
-    default: lncc_fwd_w<11>(w, atlas, fields, loss, loss_stride, eps, g, n, st); break;
-  }
+  lncc_fwd_dispatch(w, atlas, fields, loss, loss_stride, win, eps, g, n, Strides{g.V, 0}, st);
   prof_end(st, KC_LNCC_FWD);
+  return true;
+}
+
+bool launch_lncc_atlas_grad(const float* warped, const float* atlas, float* fields, float* ga,
+                            double* loss, int loss_stride, int win, double eps, const Geom& g,
+                            int n, hipStream_t st) {
+  if (!lncc_window_supported(win)) return false;
+  RegW none{};
+  const Strides sd{0, g.V};
+  prof_begin(st, KC_LNCC_FWD);
+  lncc_fwd_dispatch(atlas, warped, fields, loss, loss_stride, win, eps, g, n, sd, st);
+  prof_end(st, KC_LNCC_FWD);
+  prof_begin(st, KC_LNCC_BWD);
+  lncc_bwd_dispatch<false>(fields, atlas, warped, ga, nullptr, nullptr, nullptr, nullptr, 0, none,
+                           win, g, n, sd, st);
+  prof_end(st, KC_LNCC_BWD);
   return true;
 }
 
@@ -418,7 +450,7 @@ bool launch_lncc_bwd(const float* fields, const float* w, const float* atlas, fl
   RegW none{};
   prof_begin(st, KC_LNCC_BWD);
   lncc_bwd_dispatch<false>(fields, w, atlas, gw, nullptr, nullptr, nullptr, nullptr, 0, none, win,
-                           g, n, st);
+                           g, n, Strides{g.V, 0}, st);
   prof_end(st, KC_LNCC_BWD);
   return true;
 }
@@ -430,7 +462,7 @@ bool launch_lncc_bwd_fused(const float* fields, const float* w, const float* atl
   if (!lncc_window_supported(win)) return false;
   prof_begin(st, KC_LNCC_BWD);
   lncc_bwd_dispatch<true>(fields, w, atlas, nullptr, img, u, gu, loss, loss_stride, rw, win, g, n,
-                          st);
+                          Strides{g.V, 0}, st);
   prof_end(st, KC_LNCC_BWD);
   return true;
 }

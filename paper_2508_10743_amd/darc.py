@@ -21,7 +21,8 @@ import torch
 from . import _lib as L
 from ._lib import DarcError  # noqa: F401
 
-METRICS = {"mse": L.DARC_MSE, "lncc": L.DARC_LNCC}
+METRICS = {"mse": L.DARC_MSE, "lncc": L.DARC_LNCC, "l1": L.DARC_L1}
+ATLAS_MODES = {"mean": L.DARC_ATLAS_MEAN, "median": L.DARC_ATLAS_MEDIAN, "sgd": L.DARC_ATLAS_SGD}
 CENTER_MODES = {"displacement": L.DARC_CENTER_DISPLACEMENT, "velocity": L.DARC_CENTER_VELOCITY}
 
 
@@ -230,6 +231,107 @@ def atlas_update(images: torch.Tensor, u: torch.Tensor,
     return atlas
 
 
+def atlas_median(images: torch.Tensor, u: torch.Tensor,
+                 mean: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """A(x) = median_i I_i(x + u_i(x) - mean(x)) (the L1 atlas; even n
+    averages the two middle samples)."""
+    n, d0, d1, d2 = _images("images", images)
+    _same("u", u.shape, "expected", (n, 3, d0, d1, d2))
+    _field("u", u)
+    if mean is not None:
+        _dev("mean", mean, ndim=4)
+        _same("mean", mean.shape, "expected", (3, d0, d1, d2))
+    atlas = torch.empty((d0, d1, d2), dtype=images.dtype, device=images.device)
+    _call("darc_atlas_median", _p(images), _p(u), _p(mean), _p(atlas), n, d0, d1, d2, _stream())
+    return atlas
+
+
+def atlas_sgd(warped: torch.Tensor, atlas: torch.Tensor, epochs: int = 20, batch: int = 4,
+              win: int = 9, eps: float = 1e-5, lr: float = 1e-2, beta1: float = 0.9,
+              beta2: float = 0.999, adam_eps: float = 1e-8) -> torch.Tensor:
+    """In-place minibatch Adam on the atlas against the LNCC of the warped
+    subjects; returns the per-minibatch losses (FP64)."""
+    n, d0, d1, d2 = _images("warped", warped)
+    _dev("atlas", atlas, ndim=3)
+    _same("atlas", atlas.shape, "volume", (d0, d1, d2))
+    b = min(batch, n)
+    nbatch = (n + b - 1) // b
+    losses = torch.zeros(epochs * nbatch, dtype=torch.float64, device=warped.device)
+    ws = _workspace(lib().darc_atlas_sgd_ws_bytes(n, d0, d1, d2, b), warped.device)
+    _call("darc_atlas_sgd", _p(warped), _p(atlas), n, d0, d1, d2, b, epochs, win, eps, lr, beta1,
+          beta2, adam_eps, _p(losses), _p(ws), 0 if ws is None else ws.numel(), _stream())
+    return losses
+
+
+# ---------------------------------------------------- one-shot segmentation
+
+
+def _labels(name: str, t: torch.Tensor, ndim: int) -> None:
+    _dev(name, t, dtype=torch.uint8, ndim=ndim)
+
+
+def warp_labels(labels: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+    """out_i(x) = labels(round(x + u_i(x))), 0 outside; labels ``[D0, D1, D2]``
+    uint8, u ``[n, 3, D0, D1, D2]``."""
+    _labels("labels", labels, 3)
+    n, d0, d1, d2 = _field("u", u)
+    _same("labels", labels.shape, "volume", (d0, d1, d2))
+    out = torch.empty((n, d0, d1, d2), dtype=torch.uint8, device=u.device)
+    _call("darc_warp_labels", _p(labels), _p(u), _p(out), n, d0, d1, d2, _stream())
+    return out
+
+
+def segment(labels: torch.Tensor, v: torch.Tensor, n_sq: int = 7) -> torch.Tensor:
+    """One-shot segmentation: the atlas labels carried to each subject by
+    Exp(-v_i)."""
+    _labels("labels", labels, 3)
+    n, d0, d1, d2 = _field("v", v)
+    _same("labels", labels.shape, "volume", (d0, d1, d2))
+    out = torch.empty((n, d0, d1, d2), dtype=torch.uint8, device=v.device)
+    ws = _workspace(lib().darc_segment_ws_bytes(n, d0, d1, d2, n_sq), v.device)
+    _call("darc_segment", _p(labels), _p(v), _p(out), n, d0, d1, d2, n_sq, _p(ws),
+          0 if ws is None else ws.numel(), _stream())
+    return out
+
+
+def dice_counts(a: torch.Tensor, b: torch.Tensor, num_labels: int) -> torch.Tensor:
+    """Per subject and label: (|a = l and b = l|, |a = l|, |b = l|) as int64
+    ``[n, num_labels, 3]``; a and b are ``[n, ...]`` uint8."""
+    _dev("a", a, dtype=torch.uint8)
+    _dev("b", b, dtype=torch.uint8)
+    _same("a", a.shape, "b", b.shape)
+    n = a.shape[0]
+    V = a[0].numel() if n else 0
+    counts = torch.zeros((n, num_labels, 3), dtype=torch.int64, device=a.device)
+    _call("darc_dice_counts", _p(a), _p(b), n, V, num_labels, _p(counts), _stream())
+    return counts
+
+
+# ---------------------------------------------------------------- resampling
+
+
+def down2(x: torch.Tensor) -> torch.Tensor:
+    """2x2x2 block means over the last three (even) axes of a contiguous
+    FP32 tensor ``[..., D0, D1, D2]``."""
+    _dev("x", x)
+    *lead, d0, d1, d2 = x.shape
+    nchan = x[..., 0, 0, 0].numel()
+    out = torch.empty(tuple(lead) + (d0 // 2, d1 // 2, d2 // 2), dtype=x.dtype, device=x.device)
+    _call("darc_down2", _p(x), _p(out), nchan, d0, d1, d2, _stream())
+    return out
+
+
+def up2(x: torch.Tensor, scale: float = 1.0) -> torch.Tensor:
+    """Trilinear (border) upsampling of ``[..., d0, d1, d2]`` to twice the
+    size, out(x) = scale * x_coarse((x - 1/2) / 2)."""
+    _dev("x", x)
+    *lead, d0, d1, d2 = x.shape
+    nchan = x[..., 0, 0, 0].numel()
+    out = torch.empty(tuple(lead) + (2 * d0, 2 * d1, 2 * d2), dtype=x.dtype, device=x.device)
+    _call("darc_up2", _p(x), _p(out), nchan, 2 * d0, 2 * d1, 2 * d2, scale, _stream())
+    return out
+
+
 # ---------------------------------------------------------------------- sweep
 
 
@@ -251,12 +353,23 @@ class SweepParams:
     center_mode: str = "displacement"
     reinit_v: bool = False
     batch: int = 0  # subjects per launch; 0 = all
+    atlas_mode: str = "auto"  # mean | median | sgd; auto: median for L1, else mean
+    k3: int = 20  # stochastic atlas: epochs
+    atlas_batch: int = 4  # stochastic atlas: subjects per minibatch
+    atlas_lr: float = 1e-2  # stochastic atlas: Adam learning rate
 
-    def to_c(self) -> L.DarcParams:
+    def resolved_atlas_mode(self) -> str:
+        if self.atlas_mode != "auto":
+            return self.atlas_mode
+        return "median" if self.metric == "l1" else "mean"
+
+    def to_c(self, k2: Optional[int] = None) -> L.DarcParams:
         return L.DarcParams(METRICS[self.metric], self.win, self.ncc_eps, self.lam,
-                            self.smooth_sigma, self.n_sq, self.k2, self.lr, self.beta1,
-                            self.beta2, self.adam_eps, CENTER_MODES[self.center_mode],
-                            int(self.reinit_v), self.batch)
+                            self.smooth_sigma, self.n_sq, self.k2 if k2 is None else k2, self.lr,
+                            self.beta1, self.beta2, self.adam_eps,
+                            CENTER_MODES[self.center_mode], int(self.reinit_v), self.batch,
+                            ATLAS_MODES[self.resolved_atlas_mode()], self.k3, self.atlas_batch,
+                            self.atlas_lr)
 
 
 class Cohort:
@@ -272,22 +385,29 @@ class Cohort:
     """
 
     def __init__(self, images: torch.Tensor, params: SweepParams, keep_u_hat: bool = True,
-                 device_step: bool = False):
+                 device_step: bool = False, v0: Optional[torch.Tensor] = None):
         n, d0, d1, d2 = _images("images", images)
         self.images = images
         self.params = params
         dev = images.device
         shape = (n, 3, d0, d1, d2)
-        self.v = torch.zeros(shape, dtype=torch.float32, device=dev)
-        self.m = torch.zeros_like(self.v)
-        self.s = torch.zeros_like(self.v)
-        self.u_hat = torch.zeros_like(self.v) if keep_u_hat else None
-        self.atlas = atlas_update(images, self.v)
+        self.m = torch.zeros(shape, dtype=torch.float32, device=dev)
+        self.s = torch.zeros_like(self.m)
+        if v0 is None:
+            self.v = torch.zeros_like(self.m)
+        else:
+            _field("v0", v0)
+            _same("v0", v0.shape, "expected", shape)
+            self.v = v0  # adopted, not copied
+        self.u_hat = torch.zeros_like(self.m) if keep_u_hat else None
+        # A^0: the mean of the unwarped subjects (m is still all zeros here)
+        self.atlas = atlas_update(images, self.m)
         self.step = 0
         self.sweeps = 0
         self.step_dev = torch.zeros(1, dtype=torch.int64, device=dev) if device_step else None
         self._state = L.DarcState()
         self._cparams = params.to_c()
+        self._cparams_start = params.to_c(k2=0)
         self._refresh_state()
         nbytes = lib().darc_sweep_ws_bytes(ctypes.byref(self._state), ctypes.byref(self._cparams))
         if nbytes == 0:
@@ -322,6 +442,16 @@ class Cohort:
     def group_loss(self) -> float:
         return float(self.losses[-1].item())
 
+    def level_start(self) -> torch.Tensor:
+        """Steps 2 and 3 of a sweep without step 1 (k2 = 0): centred Exp of
+        the current velocities, the atlas update from the current atlas, and
+        the group loss (written to ``losses[0]``).  The start of a level of a
+        coarse-to-fine schedule."""
+        self._refresh_state()
+        _call("darc_sweep", ctypes.byref(self._state), ctypes.byref(self._cparams_start),
+              _p(self.losses), _p(self.ws), self.ws.numel(), _stream())
+        return self.losses[:1]
+
     def autotune(self) -> tuple:
         """Time the candidate plane-chunk lengths of the marching kernels on
         this cohort's shapes and keep the fastest for later launches; returns
@@ -353,6 +483,44 @@ class Cohort:
                 graph.capture_end()
         torch.cuda.current_stream().wait_stream(side)
         return SweepGraph(self, graph)
+
+
+class Pyramid:
+    """Coarse-to-fine DARC: the cohort at 1/2^(levels-1), ..., 1/2, 1 of its
+    size (2x2x2 block means of the images).  Each level starts from the
+    velocities of the coarser one carried up by ``up2(v, 2)`` (fresh Adam
+    moments and step count, the atlas re-derived by :meth:`Cohort.level_start`)
+    and runs :meth:`sweep` as often as the caller wants before
+    :meth:`next_level`."""
+
+    def __init__(self, images: torch.Tensor, params: SweepParams, levels: int,
+                 keep_u_hat: bool = True):
+        if levels < 1:
+            raise ValueError("levels must be >= 1")
+        pyr = [images]
+        for _ in range(levels - 1):
+            pyr.append(down2(pyr[-1]))
+        self.images = pyr[::-1]
+        self.params = params
+        self.keep_u_hat = keep_u_hat
+        self.level = 0
+        self.cohort = Cohort(self.images[0], params, keep_u_hat)
+
+    @property
+    def levels(self) -> int:
+        return len(self.images)
+
+    def sweep(self) -> torch.Tensor:
+        return self.cohort.sweep()
+
+    def next_level(self) -> Cohort:
+        if self.level + 1 >= self.levels:
+            raise ValueError("already at the finest level")
+        v = up2(self.cohort.v, 2.0)
+        self.level += 1
+        self.cohort = Cohort(self.images[self.level], self.params, self.keep_u_hat, v0=v)
+        self.cohort.level_start()
+        return self.cohort
 
 
 class SweepGraph:

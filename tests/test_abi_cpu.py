@@ -84,6 +84,20 @@ def test_bad_dims_and_pointers_are_rejected_without_a_gpu(lib):
     _status(lib, lib.darc_adam_step(dummy, dummy, dummy, dummy, 10, 1, 1e-2, 1.0, 0.999, 1e-8,
                                     None), L.DARC_EINVAL)
     _status(lib, lib.darc_atlas_update(dummy, dummy, None, dummy, 0, 4, 4, 4, None), L.DARC_EINVAL)
+    _status(lib, lib.darc_atlas_median(dummy, dummy, None, dummy, 513, 4, 4, 4, None),
+            L.DARC_EUNSUPPORTED)
+    _status(lib, lib.darc_atlas_sgd(dummy, dummy, 4, 4, 4, 4, 0, 1, 9, 1e-5, 1e-2, 0.9, 0.999,
+                                    1e-8, None, dummy, 1 << 30, None), L.DARC_EINVAL)  # batch 0
+    _status(lib, lib.darc_atlas_sgd(dummy, dummy, 4, 4, 4, 4, 2, 1, 9, 1e-5, 1e-2, 0.9, 0.999,
+                                    1e-8, None, dummy, 16, None), L.DARC_EWORKSPACE)
+    _status(lib, lib.darc_segment(dummy, dummy, dummy, 1, 4, 4, 4, 0, dummy, 1 << 30, None),
+            L.DARC_EINVAL)  # n_sq 0
+    _status(lib, lib.darc_segment(dummy, dummy, dummy, 1, 4, 4, 4, 7, dummy, 16, None),
+            L.DARC_EWORKSPACE)
+    _status(lib, lib.darc_dice_counts(dummy, dummy, 1, 64, 257, dummy, None), L.DARC_EINVAL)
+    _status(lib, lib.darc_down2(dummy, ctypes.c_void_p(0x2000), 1, 6, 6, 5, None), L.DARC_EINVAL)
+    _status(lib, lib.darc_up2(dummy, dummy, 1, 6, 6, 6, 2.0, None), L.DARC_EINVAL)  # aliasing
+    assert lib.darc_segment_ws_bytes(2, 4, 4, 4, 7) == 2 * lib.darc_segment_ws_bytes(2, 4, 4, 4, 1)
 
 
 def test_empty_batches_are_no_ops(lib):
@@ -97,7 +111,8 @@ def test_empty_batches_are_no_ops(lib):
 
 def _params(**kw):
     base = dict(metric=0, win=9, ncc_eps=1e-5, lam=0.01, smooth_sigma=0.0, n_sq=7, k2=5, lr=1e-2,
-                beta1=0.9, beta2=0.999, adam_eps=1e-8, center_mode=0, reinit_v=0, batch=0)
+                beta1=0.9, beta2=0.999, adam_eps=1e-8, center_mode=0, reinit_v=0, batch=0,
+                atlas_mode=0, k3=20, atlas_batch=4, atlas_lr=1e-2)
     base.update(kw)
     return L.DarcParams(**base)
 
@@ -115,8 +130,20 @@ def test_sweep_validation_and_workspace_sizes(lib):
     assert lib.darc_sweep_ws_bytes(ctypes.byref(st), ctypes.byref(p_lncc)) > nbytes
     p_b1 = _params(batch=1)
     assert lib.darc_sweep_ws_bytes(ctypes.byref(st), ctypes.byref(p_b1)) < nbytes
-    for bad in (_params(k2=0), _params(n_sq=0), _params(metric=1, win=8), _params(lam=-1.0),
-                _params(beta2=1.0), _params(center_mode=3), _params(smooth_sigma=5.0)):
+    # the stochastic atlas needs the warped subjects and its own scratch
+    p_sgd = _params(metric=1, atlas_mode=2)
+    assert lib.darc_sweep_ws_bytes(ctypes.byref(st), ctypes.byref(p_sgd)) >= \
+        lib.darc_sweep_ws_bytes(ctypes.byref(st), ctypes.byref(_params(metric=1))) + 4 * V * 4
+    # k2 = 0 (atlas and group loss only) and the L1 metric are valid
+    assert lib.darc_sweep_ws_bytes(ctypes.byref(st), ctypes.byref(_params(k2=0))) > 0
+    assert lib.darc_sweep_ws_bytes(ctypes.byref(st), ctypes.byref(_params(metric=2,
+                                                                           atlas_mode=1))) > 0
+    for bad in (_params(k2=-1), _params(n_sq=0), _params(metric=1, win=8), _params(lam=-1.0),
+                _params(beta2=1.0), _params(center_mode=3), _params(smooth_sigma=5.0),
+                _params(metric=3), _params(atlas_mode=3), _params(atlas_mode=2),
+                _params(metric=1, atlas_mode=2, k3=0), _params(metric=1, atlas_mode=2,
+                                                                atlas_batch=0),
+                _params(metric=1, atlas_mode=2, atlas_lr=0.0)):
         assert lib.darc_sweep_ws_bytes(ctypes.byref(st), ctypes.byref(bad)) == 0
         rc = lib.darc_sweep(ctypes.byref(st), ctypes.byref(bad), d, d, 1 << 30, None)
         assert rc in (L.DARC_EINVAL, L.DARC_EUNSUPPORTED)

@@ -93,6 +93,53 @@ def measured_traffic(workload, kernel_class):
         return None
 
 
+def time_extras(D, cohort, w, reps=3):
+    """Time the other branches of the method on the bench cohort (its
+    current state): each entry gives ms per call and the achieved rate of its
+    algorithmic bytes (FP32 state read or written once, gathers from cache)."""
+    import torch
+
+    n, V = w.n, w.voxels
+    imgs, u, atlas = cohort.images, cohort.u_hat, cohort.atlas
+
+    def timed(fn):
+        fn()
+        start = torch.cuda.Event(enable_timing=True)
+        stop = torch.cuda.Event(enable_timing=True)
+        start.record()
+        for _ in range(reps):
+            fn()
+        stop.record()
+        stop.synchronize()
+        return start.elapsed_time(stop) / reps
+
+    warped = D.warp3d(imgs, u)
+    labels = (imgs[0] > 0.35).to(torch.uint8) + (imgs[0] > 0.65).to(torch.uint8)
+    a_sgd = atlas.clone()
+    coarse = D.down2(u)
+    batch = 4
+    cases = {
+        # read n images (gathered) and n displacements, write the atlas
+        "atlas_median": (lambda: D.atlas_median(imgs, u), n * V * 16 + V * 4),
+        # one epoch: per minibatch LNCC statistics and adjoint of the atlas
+        # against each subject (read 2, write 4 factors; read 4 factors and 2,
+        # write 1), then Adam on the atlas reading the minibatch gradients
+        "atlas_sgd_epoch": (lambda: D.atlas_sgd(warped, a_sgd, epochs=1, batch=batch, win=w.win),
+                            n * V * (24 + 28) + ((n + batch - 1) // batch) * V * 24 + n * V * 4),
+        # Exp(-v) (7 squaring steps) and the label lookup
+        "segment": (lambda: D.segment(labels, cohort.v), n * V * (7 * 24 + 13)),
+        # 2x2x2 means of the displacements; trilinear upsampling back
+        "down2_fields": (lambda: D.down2(u), n * 3 * V * 4 + n * 3 * V // 2),
+        "up2_fields": (lambda: D.up2(coarse, 2.0), n * 3 * V * 4 + n * 3 * V // 2),
+    }
+    res = {}
+    for name, (fn, nbytes) in cases.items():
+        ms = timed(fn)
+        res[name] = {"ms": round(ms, 3), "algo_GB": round(nbytes / 1e9, 4),
+                     "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    return res
+
+
 def cpu_baseline(w, seconds_hint=True):
     """The FP64 oracle on one subject's central crop (1/8 of the voxels),
     two inner iterations, one thread."""
@@ -143,6 +190,9 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="subjects per launch (0 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
+    ap.add_argument("--extras", action="store_true",
+                    help="also time the method's other branches (median and stochastic atlas, "
+                         "one-shot segmentation, pyramid resampling) on the same cohort")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (a known-size kernel for "
                          "calibrating HBM byte counters)")
@@ -222,6 +272,7 @@ def main():
             "traffic_unit": "GB per launch (HBM, from counters)",
         }
 
+    extras = time_extras(D, cohort, w) if args.extras else None
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     value = w.n * w.voxels * w.k2 / (ms_per_step * 1e-3)
     out = {
@@ -253,6 +304,8 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
     }
+    if extras is not None:
+        out["extras"] = extras
     print(json.dumps(out), flush=True)
 
 

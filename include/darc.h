@@ -287,6 +287,50 @@ int darc_dice_counts(const unsigned char* a, const unsigned char* b, int n, long
                      int num_labels, unsigned long long* counts, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Learned warm start: a 3-D U-Net mapping an (atlas, subject) pair to an
+ * initial velocity field, from which DARC's per-subject registration then
+ * starts instead of v = 0.  Its convolutions run on the BF16 matrix cores
+ * (FP32 accumulation).
+ *
+ * darc_conv3d -- one convolution, zero padding (ksize - 1) / 2, bias,
+ * optional leaky ReLU (slope) -- as deep-learning frameworks define it
+ * (cross-correlation):
+ *   y[o][co] = bias[co] + sum_{tap, ci} w[co][tap][ci] x[o * stride + tap - pad][ci].
+ *   Input x = concat(x0, x1) along channels, channels-last BF16 (raw bits):
+ *     x0 [n][h0][h1][h2][c0], at (d0, d1, d2) or, when up0, at half of each
+ *        dim and doubled by nearest neighbour; x1 [n][d0][d1][d2][c1] or NULL
+ *        with c1 = 0.  c0 >= 8 and c1 multiples of 8.
+ *   w   [cout][kpad] BF16, kpad = darc_conv3d_kpad(c0 + c1, ksize):
+ *       entry k = (tap * (cin / 8) + v) * 8 + j holds the weight of channel
+ *       8 v + j at tap = (a * 3 + b) * 3 + c, offset (a-1, b-1, c-1) along
+ *       (d0, d1, d2) (tap 0 only for ksize 1); entries past the taps are 0.
+ *   bias [cout] FP32 or NULL.  stride 1 or 2; output dims (d - 1) / stride + 1.
+ *   Exactly one output: y_bf16 channels-last [n][o][cout] (rounded to nearest
+ *   even) or y_f32 planar [n][cout][o] (the field layout when cout = 3).
+ *
+ * darc_unet_forward -- v = UNet(A, I_i) for n subjects:
+ *   e0 = act(conv(cat(A, I), 2 -> 16)); e1, e2, e3 = act(conv stride 2)
+ *   to 32, 64, 128 channels at 1/2, 1/4, 1/8 of the dims; d2, d1, d0 =
+ *   act(conv(cat(up(deeper), skip))) to 64, 32, 16 channels; v = conv(d0, 16
+ *   -> 3), FP32 [n][3][V].  act: leaky ReLU 0.2; activations BF16.
+ *   Parameters: layer l (0..7 in that order) has weights [cout][kpad] at
+ *   w + w_offset and biases at b + b_offset (darc_unet_layout); the input
+ *   layer's 2 channels are padded to 8 with zero weights.  dims multiples
+ *   of 8.  ws: scratch of darc_unet_ws_bytes().
+ * ---------------------------------------------------------------------- */
+int darc_conv3d_kpad(int cin, int ksize);
+int darc_conv3d(const unsigned short* x0, int c0, int up0, const unsigned short* x1, int c1,
+                int n, int d0, int d1, int d2, int ksize, int stride, const unsigned short* w,
+                const float* bias, int cout, int act, float slope, unsigned short* y_bf16,
+                float* y_f32, void* stream);
+int darc_unet_layout(int layer, int* cin, int* cout, int* kpad, size_t* w_offset,
+                     size_t* b_offset);
+size_t darc_unet_ws_bytes(int n, int d0, int d1, int d2);
+int darc_unet_forward(const unsigned short* w, const float* b, const float* atlas,
+                      const float* images, float* v, int n, int d0, int d1, int d2, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
  * darc_down2 / darc_up2 -- factor-2 resampling between the levels of a
  * coarse-to-fine schedule.  Coarse voxel k averages the fine voxels 2k and
  * 2k+1 of every axis, so fine voxel x sits at coarse coordinate (x - 1/2)/2.

@@ -113,6 +113,13 @@ PROTOTYPES = {
     "darc_segment_ws_bytes": (c_size_t, [_I, _I, _I, _I, _I]),
     "darc_segment": (c_int, [_P, _P, _P, _I, _I, _I, _I, _I, _P, _Z, _P]),
     "darc_dice_counts": (c_int, [_P, _P, _I, c_longlong, _I, _P, _P]),
+    "darc_conv3d_kpad": (c_int, [_I, _I]),
+    "darc_conv3d": (c_int, [_P, _I, _I, _P, _I, _I, _I, _I, _I, _I, _I, _P, _P, _I, _I, c_float,
+                            _P, _P, _P]),
+    "darc_unet_layout": (c_int, [_I, POINTER(c_int), POINTER(c_int), POINTER(c_int),
+                                 POINTER(c_size_t), POINTER(c_size_t)]),
+    "darc_unet_ws_bytes": (c_size_t, [_I, _I, _I, _I]),
+    "darc_unet_forward": (c_int, [_P, _P, _P, _P, _P, _I, _I, _I, _I, _P, _Z, _P]),
     "darc_down2": (c_int, [_P, _P, _I, _I, _I, _I, _P]),
     "darc_up2": (c_int, [_P, _P, _I, _I, _I, _I, c_float, _P]),
     "darc_sizeof_state": (c_size_t, []),

@@ -516,6 +516,161 @@ int darc_dice_counts(const unsigned char* a, const unsigned char* b, int n, long
   return check_launch("darc_dice_counts");
 }
 
+// ------------------------------------------------------ warm-start network
+
+int darc_conv3d_kpad(int cin, int ksize) {
+  if (cin < 1 || (ksize != 1 && ksize != 3)) return 0;
+  return conv_kpad(cin, ksize == 3 ? 27 : 1);
+}
+
+int darc_conv3d(const unsigned short* x0, int c0, int up0, const unsigned short* x1, int c1,
+                int n, int d0, int d1, int d2, int ksize, int stride, const unsigned short* w,
+                const float* bias, int cout, int act, float slope, unsigned short* y_bf16,
+                float* y_f32, void* stream) {
+  DARC_TRY(check_dims("darc_conv3d", n, d0, d1, d2));
+  if (c0 < 8 || c0 % 8 || c1 < 0 || c1 % 8)
+    return fail(DARC_EINVAL, "darc_conv3d: channel counts must be multiples of 8 (c0 >= 8)");
+  if (ksize != 1 && ksize != 3) return fail(DARC_EINVAL, "darc_conv3d: ksize must be 1 or 3");
+  if (stride != 1 && stride != 2) return fail(DARC_EINVAL, "darc_conv3d: stride must be 1 or 2");
+  if (cout < 1 || cout > 4096) return fail(DARC_EINVAL, "darc_conv3d: cout must be in 1..4096");
+  if (up0 && (d0 % 2 || d1 % 2 || d2 % 2))
+    return fail(DARC_EINVAL, "darc_conv3d: an upsampled x0 needs even dims");
+  if ((y_bf16 == nullptr) == (y_f32 == nullptr))
+    return fail(DARC_EINVAL, "darc_conv3d: exactly one of y_bf16 and y_f32 must be given");
+  if (n == 0) return ok();
+  if (!x0 || (c1 && !x1) || !w) return fail(DARC_EINVAL, "darc_conv3d: NULL pointer");
+  ConvGeom cg{};
+  cg.i0 = d0;
+  cg.i1 = d1;
+  cg.i2 = d2;
+  cg.o0 = (d0 - 1) / stride + 1;
+  cg.o1 = (d1 - 1) / stride + 1;
+  cg.o2 = (d2 - 1) / stride + 1;
+  cg.nvox = static_cast<long long>(n) * cg.o0 * cg.o1 * cg.o2;
+  cg.stride = stride;
+  cg.ntaps = ksize == 3 ? 27 : 1;
+  cg.c0 = c0;
+  cg.c1 = c1;
+  cg.up0 = up0 ? 1 : 0;
+  cg.kpad = conv_kpad(c0 + c1, cg.ntaps);
+  cg.cout = cout;
+  cg.act = act ? 1 : 0;
+  cg.slope = slope;
+  launch_conv3d(x0, x1, w, bias, y_bf16, y_f32, cg, as_stream(stream));
+  return check_launch("darc_conv3d");
+}
+
+}  // extern "C"
+
+namespace {
+
+struct UnetLayer {
+  int cin, cout, stride, act;  // cin padded to a multiple of 8
+};
+// e0 e1 e2 e3 d2 d1 d0 out
+const UnetLayer kUnet[8] = {{8, 16, 1, 1},   {16, 32, 2, 1}, {32, 64, 2, 1}, {64, 128, 2, 1},
+                            {192, 64, 1, 1}, {96, 32, 1, 1}, {48, 16, 1, 1}, {16, 3, 1, 0}};
+
+struct UnetWs {
+  size_t x, e0, e1, e2, e3, d2, d1, d0, total;
+};
+
+UnetWs unet_ws(int n, int d0, int d1, int d2) {
+  const size_t V = static_cast<size_t>(d0) * d1 * d2 * n;
+  UnetWs L{};
+  size_t off = 0;
+  auto take = [&](size_t elems) {
+    const size_t o = off;
+    off += align256(elems * sizeof(uint16_t));
+    return o;
+  };
+  L.x = take(V * 8);
+  L.e0 = take(V * 16);
+  L.e1 = take(V / 8 * 32);
+  L.e2 = take(V / 64 * 64);
+  L.e3 = take(V / 512 * 128);
+  L.d2 = take(V / 64 * 64);
+  L.d1 = take(V / 8 * 32);
+  L.d0 = take(V * 16);
+  L.total = off;
+  return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+int darc_unet_layout(int layer, int* cin, int* cout, int* kpad, size_t* w_offset,
+                     size_t* b_offset) {
+  if (layer < 0 || layer >= 8) return fail(DARC_EINVAL, "darc_unet_layout: layer must be 0..7");
+  size_t wo = 0, bo = 0;
+  for (int l = 0; l < layer; ++l) {
+    wo += static_cast<size_t>(kUnet[l].cout) * conv_kpad(kUnet[l].cin, 27);
+    bo += kUnet[l].cout;
+  }
+  if (cin) *cin = kUnet[layer].cin;
+  if (cout) *cout = kUnet[layer].cout;
+  if (kpad) *kpad = conv_kpad(kUnet[layer].cin, 27);
+  if (w_offset) *w_offset = wo;
+  if (b_offset) *b_offset = bo;
+  return ok();
+}
+
+size_t darc_unet_ws_bytes(int n, int d0, int d1, int d2) {
+  if (n < 1 || d0 < 8 || d1 < 8 || d2 < 8 || d0 % 8 || d1 % 8 || d2 % 8) return 0;
+  return unet_ws(n, d0, d1, d2).total;
+}
+
+int darc_unet_forward(const unsigned short* w, const float* b, const float* atlas,
+                      const float* images, float* v, int n, int d0, int d1, int d2, void* ws,
+                      size_t ws_bytes, void* stream) {
+  DARC_TRY(check_dims("darc_unet_forward", n, d0, d1, d2));
+  if (d0 % 8 || d1 % 8 || d2 % 8 || d0 < 8 || d1 < 8 || d2 < 8)
+    return fail(DARC_EINVAL, "darc_unet_forward: dims must be multiples of 8");
+  if (n == 0) return ok();
+  if (!w || !b || !atlas || !images || !v) return fail(DARC_EINVAL, "darc_unet_forward: NULL pointer");
+  DARC_TRY(check_ws("darc_unet_forward", ws, ws_bytes, darc_unet_ws_bytes(n, d0, d1, d2)));
+  const UnetWs L = unet_ws(n, d0, d1, d2);
+  hipStream_t st = as_stream(stream);
+  char* base = static_cast<char*>(ws);
+  auto buf = [&](size_t o) { return reinterpret_cast<uint16_t*>(base + o); };
+  launch_pack_pair(atlas, images, buf(L.x), static_cast<long long>(d0) * d1 * d2, n, 8, st);
+  size_t wo = 0, bo = 0;
+  auto conv = [&](int l, const uint16_t* x0, int c0, int up0, const uint16_t* x1, int c1, int lev,
+                  uint16_t* y16, float* y32) {
+    const UnetLayer& U = kUnet[l];
+    ConvGeom cg{};
+    cg.i0 = d0 >> lev;
+    cg.i1 = d1 >> lev;
+    cg.i2 = d2 >> lev;
+    cg.stride = U.stride;
+    cg.o0 = (cg.i0 - 1) / U.stride + 1;
+    cg.o1 = (cg.i1 - 1) / U.stride + 1;
+    cg.o2 = (cg.i2 - 1) / U.stride + 1;
+    cg.nvox = static_cast<long long>(n) * cg.o0 * cg.o1 * cg.o2;
+    cg.ntaps = 27;
+    cg.c0 = c0;
+    cg.c1 = c1;
+    cg.up0 = up0;
+    cg.kpad = conv_kpad(U.cin, 27);
+    cg.cout = U.cout;
+    cg.act = U.act;
+    cg.slope = 0.2f;
+    launch_conv3d(x0, x1, w + wo, b + bo, y16, y32, cg, st);
+    wo += static_cast<size_t>(U.cout) * cg.kpad;
+    bo += U.cout;
+  };
+  conv(0, buf(L.x), 8, 0, nullptr, 0, 0, buf(L.e0), nullptr);
+  conv(1, buf(L.e0), 16, 0, nullptr, 0, 0, buf(L.e1), nullptr);
+  conv(2, buf(L.e1), 32, 0, nullptr, 0, 1, buf(L.e2), nullptr);
+  conv(3, buf(L.e2), 64, 0, nullptr, 0, 2, buf(L.e3), nullptr);
+  conv(4, buf(L.e3), 128, 1, buf(L.e2), 64, 2, buf(L.d2), nullptr);
+  conv(5, buf(L.d2), 64, 1, buf(L.e1), 32, 1, buf(L.d1), nullptr);
+  conv(6, buf(L.d1), 32, 1, buf(L.e0), 16, 0, buf(L.d0), nullptr);
+  conv(7, buf(L.d0), 16, 0, nullptr, 0, 0, nullptr, v);
+  return check_launch("darc_unet_forward");
+}
+
 // ------------------------------------------------------------- resampling
 
 int darc_down2(const float* in, float* out, int nchan, int d0, int d1, int d2, void* stream) {

@@ -133,6 +133,28 @@ void launch_down2(const float* in, float* out, const Geom& fine, int nchan, hipS
 void launch_up2(const float* in, float* out, const Geom& fine, int nchan, float scale,
                 hipStream_t st);
 
+// --- warm-start network ----------------------------------------------------
+// One 3x3x3 (ntaps 27) or 1x1x1 (ntaps 1) convolution, zero padding, as an
+// implicit GEMM on the BF16 matrix cores (see unet_kernels.hip for layouts).
+struct ConvGeom {
+  long long nvox;     // n * o0 * o1 * o2 (GEMM rows)
+  int i0, i1, i2;     // input dims (full resolution)
+  int o0, o1, o2;     // output dims, (i - 1) / stride + 1
+  int stride, ntaps;  // 1 or 2; 27 or 1
+  int c0, c1;         // channels of x0 and x1 (multiples of 8; c1 may be 0)
+  int up0;            // x0 is at half resolution, doubled by nearest neighbour
+  int kpad, cout, act;
+  float slope;
+};
+// Weight row length for cin input channels: ntaps * ceil(cin/8) * 8 rounded up to 32.
+int conv_kpad(int cin, int ntaps);
+// y16 (channels-last BF16 [nvox][cout]) or y32 (planar FP32 [n][cout][O]).
+void launch_conv3d(const uint16_t* x0, const uint16_t* x1, const uint16_t* w, const float* bias,
+                   uint16_t* y16, float* y32, const ConvGeom& cg, hipStream_t st);
+// x [n][V][cpad] BF16 = (atlas, image_i, 0 ...)
+void launch_pack_pair(const float* atlas, const float* images, uint16_t* x, long long V, int n,
+                      int cpad, hipStream_t st);
+
 // --- small helpers --------------------------------------------------------
 void launch_fill_f32(float* p, long long count, float value, hipStream_t st);
 void launch_fill_f64(double* p, long long count, double value, hipStream_t st);

@@ -620,19 +620,22 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
 
 // Adjoint of one squaring step, marching, for a subject whose every cell
 // offset lies in [-1, 0] (reach 1 in every direction: all |u_t| < 1, the
-// case of the early sweeps and of the first squaring steps).  Then the
-// sources whose cells touch the column's targets at plane z all lie in planes
-// z-1..z+1 of the column and its one-voxel halo, so every block finds them in
-// its ring.  Per plane z: (i) stage u_t of plane z+1; (ii) bin the sources of
-// plane z+1 into the ring of cell planes (one LDS integer atomic each, two
-// zero-initialised slots per cell, further sources into an overflow
-// accumulator); (iii) the direct term g + J^T g of the plane-z targets, whose
-// cells were found when they were binned one plane earlier; (iv) gather, for
-// each target, the sources binned in its 8 neighbouring cells (cell planes
-// z-1 and z).  Thread (ly, lx) stages and bins its own voxel, so a voxel's
-// cell and g stay in its registers from binning to its direct term.  Blocks
-// of subjects with a larger reach return at once: the tiled kernel handles
-// those.
+// case of the early sweeps and of the first squaring steps).  A source in
+// plane p then falls in cell plane p-1 or p, and the targets of plane z
+// gather from cell planes z-1 and z only, so two cell planes (by parity) and
+// two overflow planes are live at a time, which keeps the block's LDS under
+// a third of the CU's.  Iteration z: (i) clear cell plane z and target plane
+// z+1's overflow, stage u_t of plane z+1; (ii) cells of the plane-(z+1)
+// sources; (iii) fill cell plane z with the plane-z sources whose cell is in
+// it (cells kept from the last iteration) and the plane-(z+1) sources whose
+// cell is in it (one LDS integer atomic each, two zero-initialised slots per
+// cell, further sources into the overflow accumulator); (iv) the direct term
+// g + J^T g of the plane-z targets; (v) gather, for each target, the sources
+// binned in its 8 neighbouring cells.  Thread (ly, lx) stages and bins its
+// own voxel, so a voxel's cell and g stay in its registers from staging to
+// its direct term; threads below 84 also stage one voxel of the one-voxel
+// halo ring.  Blocks of subjects with a larger reach return at once: the
+// tiled kernel handles those.
 constexpr int MCX = ETX + 1, MCY = ETY + 1;  // cells per cell plane: 33 x 9
 constexpr int MCP = MCX * MCY;
 constexpr int MRING = MHP - ENT;             // halo ring positions (84)
@@ -643,11 +646,11 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
                                                        float* __restrict__ gout, MarchGeom m,
                                                        float scale, float oscale,
                                                        const int* __restrict__ reach) {
-  __shared__ float uring[3][3][MHP];     // u_t planes z-1, z, z+1
-  __shared__ int bcnt[3][MCP];           // cell planes z-1, z, z+1
-  __shared__ float4 bd4[3][KSLOT][MCP];  // t0, t1, t2, g0 per binned source (0 if empty)
-  __shared__ float2 bd2[3][KSLOT][MCP];  // g1, g2
-  __shared__ float ovf[3][3][ENT];       // target planes z, z+1, z+2
+  __shared__ float uring[3][3][MHP];     // u_t of planes z-1, z, z+1 (slot p % 3)
+  __shared__ int bcnt[2][MCP];           // cell planes by parity
+  __shared__ float4 bd4[2][KSLOT][MCP];  // t0, t1, t2, g0 per binned source (0 if empty)
+  __shared__ float2 bd2[2][KSLOT][MCP];  // g1, g2
+  __shared__ float ovf[2][3][ENT];       // overflow into target planes, by parity
   const Geom& g = m.rec.g;
   const MarchId id = march_id(m);
   {
@@ -695,7 +698,7 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
     poff[j] = min(max(py[j], 0), g.d1 - 1) * g.d2 + min(max(px[j], 0), g.d2 - 1);
   }
 
-  float pu[2][3], pg[2][3];
+  float pu[2][3], pg[2][3];  // the plane being prefetched
   auto load_plane = [&](int z) {
     const int zc = min(max(z, 0), g.d0 - 1);
 #pragma unroll
@@ -719,7 +722,7 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
       }
   };
   auto clear_cells = [&](int cplane) {
-    const int cs = (cplane + 3) % 3;
+    const int cs = cplane & 1;
     const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float2 z2 = make_float2(0.0f, 0.0f);
     for (int i = threadIdx.x; i < MCP; i += ENT) {
@@ -731,52 +734,54 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
       }
     }
   };
-  // bin the staged sources of plane p (values in vu, vg); returns the own
-  // voxel's cell in own_bc
-  auto bin_plane = [&](int p, const float (&vu)[2][3], const float (&vg)[2][3],
-                       BorderCell& own_bc) {
-    if (p < 0 || p >= g.d0) return;
+  auto clear_ovf = [&](int tplane) {
+    float* o = &ovf[tplane & 1][0][0];
+    for (int i = threadIdx.x; i < 3 * ENT; i += ENT) o[i] = 0.0f;
+  };
+  // cells of the staged sources of plane p (ok = a source inside the volume)
+  auto cells_of = [&](int p, const float (&vu)[2][3], BorderCell (&bc)[2], bool (&ok)[2]) {
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      if (!(puse[j] && pin[j])) continue;
+      ok[j] = puse[j] && pin[j] && p >= 0 && p < g.d0;
       float u0 = vu[j][0], u1 = vu[j][1], u2 = vu[j][2];
       if (FIRST) {
         u0 *= scale;
         u1 *= scale;
         u2 *= scale;
       }
-      const BorderCell bc = border_cell(g, p, py[j], px[j], u0, u1, u2);
-      if (j == 0) own_bc = bc;
-      if (bc.i0 < id.z0 - 1 || bc.i0 > id.z1 - 1) continue;  // cell plane not gathered here
-      const int c1 = bc.i1 - id.oy + 1, c2 = bc.i2 - id.ox + 1;
-      if (c1 < 0 || c1 >= MCY || c2 < 0 || c2 >= MCX) continue;
-      const int ci = c1 * MCX + c2;
-      const int cs = (bc.i0 + 3) % 3;
-      const float g0 = vg[j][0], g1 = vg[j][1], g2 = vg[j][2];
-      const int slot = atomicAdd(&bcnt[cs][ci], 1);
-      if (slot < KSLOT) {
-        bd4[cs][slot][ci] = make_float4(bc.t0, bc.t1, bc.t2, g0);
-        bd2[cs][slot][ci] = make_float2(g1, g2);
-      } else {
-        const float w0[2] = {1.0f - bc.t0, bc.t0};
-        const float w1[2] = {1.0f - bc.t1, bc.t1};
-        const float w2[2] = {1.0f - bc.t2, bc.t2};
+      bc[j] = border_cell(g, min(max(p, 0), g.d0 - 1), py[j], px[j], u0, u1, u2);
+    }
+  };
+  // bin one source into its cell (plane bc.i0, which must be the plane being filled)
+  auto bin_one = [&](const BorderCell& bc, float g0, float g1, float g2) {
+    if (bc.i0 < id.z0 - 1 || bc.i0 > id.z1 - 1) return;  // cell plane not gathered here
+    const int c1 = bc.i1 - id.oy + 1, c2 = bc.i2 - id.ox + 1;
+    if (c1 < 0 || c1 >= MCY || c2 < 0 || c2 >= MCX) return;
+    const int ci = c1 * MCX + c2;
+    const int cs = bc.i0 & 1;
+    const int slot = atomicAdd(&bcnt[cs][ci], 1);
+    if (slot < KSLOT) {
+      bd4[cs][slot][ci] = make_float4(bc.t0, bc.t1, bc.t2, g0);
+      bd2[cs][slot][ci] = make_float2(g1, g2);
+    } else {
+      const float w0[2] = {1.0f - bc.t0, bc.t0};
+      const float w1[2] = {1.0f - bc.t1, bc.t1};
+      const float w2[2] = {1.0f - bc.t2, bc.t2};
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const int tz = bc.i0 + a;  // target plane
-          if (tz < id.z0 || tz >= id.z1) continue;
+      for (int a = 0; a < 2; ++a) {
+        const int tz = bc.i0 + a;  // target plane
+        if (tz < id.z0 || tz >= id.z1) continue;
 #pragma unroll
-          for (int b = 0; b < 2; ++b) {
+        for (int b = 0; b < 2; ++b) {
 #pragma unroll
-            for (int ee = 0; ee < 2; ++ee) {
-              const int ty = c1 + b - 1, tx = c2 + ee - 1;
-              if (ty >= 0 && ty < ETY && tx >= 0 && tx < ETX) {
-                const float w = w0[a] * w1[b] * w2[ee];
-                float* ov = &ovf[(tz + 3) % 3][0][0] + ty * ETX + tx;
-                atomicAdd(ov, w * g0);
-                atomicAdd(ov + ENT, w * g1);
-                atomicAdd(ov + 2 * ENT, w * g2);
-              }
+          for (int ee = 0; ee < 2; ++ee) {
+            const int ty = c1 + b - 1, tx = c2 + ee - 1;
+            if (ty >= 0 && ty < ETY && tx >= 0 && tx < ETX) {
+              const float w = w0[a] * w1[b] * w2[ee];
+              float* ov = &ovf[tz & 1][0][0] + ty * ETX + tx;
+              atomicAdd(ov, w * g0);
+              atomicAdd(ov + ENT, w * g1);
+              atomicAdd(ov + 2 * ENT, w * g2);
             }
           }
         }
@@ -785,13 +790,14 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
   };
 
   const bool colv = pin[0];
-  BorderCell cur_bc{}, nxt_bc{};
-  float cur_g[3] = {0.0f, 0.0f, 0.0f};
+  BorderCell cb[2], nb[2];  // cells of the plane-z and plane-(z+1) sources
+  bool cok[2], nok[2];
+  float cg[2][3], qu[2][3], qg[2][3];
 
-  // prologue: planes z0-1 and z0 staged and binned, plane z0+1 in flight
-  for (int c = -1; c <= 1; ++c) clear_cells(id.z0 + c);
-  for (int i = threadIdx.x; i < 9 * ENT; i += ENT) (&ovf[0][0][0])[i] = 0.0f;
-  float qu[2][3], qg[2][3];
+  // prologue: cell plane z0-1 from the sources of planes z0-1 and z0; plane
+  // z0+1 in flight
+  clear_cells(id.z0 - 1);
+  clear_ovf(id.z0);
   load_plane(id.z0 - 1);
   store_u(id.z0 - 1);
 #pragma unroll
@@ -804,16 +810,24 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
   load_plane(id.z0);
   store_u(id.z0);
   __syncthreads();
-  bin_plane(id.z0 - 1, qu, qg, nxt_bc);
-  bin_plane(id.z0, pu, pg, cur_bc);
-  cur_g[0] = pg[0][0];
-  cur_g[1] = pg[0][1];
-  cur_g[2] = pg[0][2];
+  cells_of(id.z0 - 1, qu, nb, nok);
+#pragma unroll
+  for (int j = 0; j < 2; ++j)
+    if (nok[j] && nb[j].i0 == id.z0 - 1) bin_one(nb[j], qg[j][0], qg[j][1], qg[j][2]);
+  cells_of(id.z0, pu, cb, cok);
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    if (cok[j] && cb[j].i0 == id.z0 - 1) bin_one(cb[j], pg[j][0], pg[j][1], pg[j][2]);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) cg[j][c] = pg[j][c];
+  }
   load_plane(id.z0 + 1);
   __syncthreads();
 
   for (int z = id.z0; z < id.z1; ++z) {
-    // (i) stage u of plane z+1, clear cell plane z+1 and target plane z+2
+    // (i) clear cell plane z (held z-2) and target plane z+1 (held z-1); stage u of plane z+1
+    clear_cells(z);
+    clear_ovf(z + 1);
     store_u(z + 1);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
@@ -822,16 +836,20 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
         qu[j][c] = pu[j][c];
         qg[j][c] = pg[j][c];
       }
-    clear_cells(z + 1);
-    for (int i = threadIdx.x; i < 3 * ENT; i += ENT) (&ovf[(z + 2) % 3][0][0])[i] = 0.0f;
     __syncthreads();
     if (z + 2 <= id.z1) load_plane(z + 2);
-    // (ii) bin the sources of plane z+1
-    bin_plane(z + 1, qu, qg, nxt_bc);
-    // (iii) direct term of the plane-z targets
+    // (ii) cells of the plane-(z+1) sources
+    cells_of(z + 1, qu, nb, nok);
+    // (iii) fill cell plane z
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      if (cok[j] && cb[j].i0 == z) bin_one(cb[j], cg[j][0], cg[j][1], cg[j][2]);
+      if (nok[j] && nb[j].i0 == z) bin_one(nb[j], qg[j][0], qg[j][1], qg[j][2]);
+    }
+    // (iv) direct term of the plane-z targets
     float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f;
     if (colv) {
-      const BorderCell& bc = cur_bc;
+      const BorderCell& bc = cb[0];
       const int c0 = bc.i0 - z + 1, c1 = bc.i1 - id.oy + 1, c2 = bc.i2 - id.ox + 1;
       const bool in_ring =
           c0 >= 0 && c0 <= 1 && c1 >= 0 && c1 + 1 < MHY && c2 >= 0 && c2 + 1 < MHX;
@@ -854,20 +872,20 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
           corners_border(f + c * g.V, g, bc.base, cv);
         }
         const Tri t = tri_eval(cv, bc.t0, bc.t1, bc.t2);
-        jt0 += t.d0 * cur_g[c];
-        jt1 += t.d1 * cur_g[c];
-        jt2 += t.d2 * cur_g[c];
+        jt0 += t.d0 * cg[0][c];
+        jt1 += t.d1 * cg[0][c];
+        jt2 += t.d2 * cg[0][c];
       }
-      r0 = cur_g[0] + (bc.k0 ? 0.0f : jt0 * js);
-      r1 = cur_g[1] + (bc.k1 ? 0.0f : jt1 * js);
-      r2 = cur_g[2] + (bc.k2 ? 0.0f : jt2 * js);
+      r0 = cg[0][0] + (bc.k0 ? 0.0f : jt0 * js);
+      r1 = cg[0][1] + (bc.k1 ? 0.0f : jt1 * js);
+      r2 = cg[0][2] + (bc.k2 ? 0.0f : jt2 * js);
     }
     __syncthreads();
-    // (iv) gather from cell planes z-1 (a = 1) and z (a = 0); empty slots hold zeros
+    // (v) gather from cell planes z-1 (a = 1) and z (a = 0); empty slots hold zeros
     if (colv) {
 #pragma unroll
       for (int a = 0; a < 2; ++a) {
-        const int cs = (z - a + 3) % 3;
+        const int cs = (z - a) & 1;
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
 #pragma unroll
@@ -886,7 +904,7 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
           }
         }
       }
-      const float* ov = &ovf[z % 3][0][0];
+      const float* ov = &ovf[z & 1][0][0];
       r0 += ov[threadIdx.x];
       r1 += ov[ENT + threadIdx.x];
       r2 += ov[2 * ENT + threadIdx.x];
@@ -895,11 +913,14 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
       go[g.V + lin] = r1 * oscale;
       go[2 * g.V + lin] = r2 * oscale;
     }
-    // (v) the voxel binned at (ii) is the next plane's target
-    cur_bc = nxt_bc;
-    cur_g[0] = qg[0][0];
-    cur_g[1] = qg[0][1];
-    cur_g[2] = qg[0][2];
+    // (vi) the plane-(z+1) sources become the next iteration's plane-z sources
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      cb[j] = nb[j];
+      cok[j] = nok[j];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) cg[j][c] = qg[j][c];
+    }
     __syncthreads();
   }
 }

@@ -120,23 +120,34 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
           sJ[e] = vj;
         }
         __syncthreads();
-        for (int e = tid; e < HY * kTX; e += kNT) {
-          const int hy = e / kTX, cx = e - hy * kTX;
+        // row sums along x, two neighbouring outputs per thread: the second
+        // slides the first by one (add the entering tap, drop the leaving one)
+        for (int e = tid; e < HY * (kTX / 2); e += kNT) {
+          const int hy = e / (kTX / 2), cx = 2 * (e - hy * (kTX / 2));
+          const double* rI = sI + hy * HX + cx;
+          const double* rJ = sJ + hy * HX + cx;
           double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
 #pragma unroll
           for (int k = 0; k < W; ++k) {
-            const double vi = sI[hy * HX + cx + k], vj = sJ[hy * HX + cx + k];
+            const double vi = rI[k], vj = rJ[k];
             a0 += vi;
             a1 += vj;
             a2 += vi * vi;
             a3 += vj * vj;
             a4 += vi * vj;
           }
-          sr[0][e] = a0;
-          sr[1][e] = a1;
-          sr[2][e] = a2;
-          sr[3][e] = a3;
-          sr[4][e] = a4;
+          const double io = rI[0], jo = rJ[0], in = rI[W], jn = rJ[W];
+          const int o = hy * kTX + cx;
+          sr[0][o] = a0;
+          sr[1][o] = a1;
+          sr[2][o] = a2;
+          sr[3][o] = a3;
+          sr[4][o] = a4;
+          sr[0][o + 1] = a0 + (in - io);
+          sr[1][o + 1] = a1 + (jn - jo);
+          sr[2][o + 1] = a2 + (in * in - io * io);
+          sr[3][o + 1] = a3 + (jn * jn - jo * jo);
+          sr[4][o + 1] = a4 + (in * jn - io * jo);
         }
         __syncthreads();
 #pragma unroll
@@ -229,14 +240,18 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
           sIn[3][e] = v3;
         }
         __syncthreads();
-        for (int e = tid; e < HY * kTX; e += kNT) {
-          const int hy = e / kTX, cx = e - hy * kTX;
+        // row sums along x, two neighbouring outputs per thread (sliding)
+        for (int e = tid; e < HY * (kTX / 2); e += kNT) {
+          const int hy = e / (kTX / 2), cx = 2 * (e - hy * (kTX / 2));
+          const int o = hy * kTX + cx;
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
+            const double* r = &sIn[c][hy * HX + cx];
             double a = 0.0;
 #pragma unroll
-            for (int k = 0; k < W; ++k) a += sIn[c][hy * HX + cx + k];
-            sr[c][e] = a;
+            for (int k = 0; k < W; ++k) a += r[k];
+            sr[c][o] = a;
+            sr[c][o + 1] = a + (r[W] - r[0]);
           }
         }
         __syncthreads();

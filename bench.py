@@ -24,6 +24,7 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
+BF16_PEAK_FLOPS = 2.5e15  # MI355X dense BF16 matrix-core peak, vendor figure
 
 DEFAULT_WORKLOAD = "brain-16x160x192x160-lncc9"
 
@@ -137,6 +138,28 @@ def time_extras(D, cohort, w, reps=3):
         ms = timed(fn)
         res[name] = {"ms": round(ms, 3), "algo_GB": round(nbytes / 1e9, 4),
                      "GB/s": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+    # the warm-start network on 4 subjects: matrix-core bound, so its rate is
+    # given in TFLOP/s against the dense BF16 peak
+    from paper_2508_10743_amd import unet as N
+
+    net = N.UNet(seed=0)
+    sub = imgs[:4].contiguous()
+    flop = 0.0
+    for level, (cin, cout, stride, _) in zip((0, 1, 2, 3, 2, 1, 0, 0), N.LAYERS):
+        flop += 2.0 * 27 * cin * cout * sub.shape[0] * V / 8 ** level
+    ms = timed(lambda: net(atlas, sub))
+    res["unet_forward_4"] = {"ms": round(ms, 3), "GFLOP": round(flop / 1e9, 1),
+                             "TFLOP/s": round(flop / (ms * 1e-3) / 1e12, 1),
+                             "frac_bf16_peak": round(flop / (ms * 1e-3) / BF16_PEAK_FLOPS, 4)}
+    # one training step on 2 subjects against their current velocities:
+    # forward, input and weight gradients (3x the forward's products)
+    tr = N.Trainer(N.UNet(seed=1), lr=1e-4)
+    sub2, tgt2 = imgs[:2].contiguous(), cohort.v[:2].contiguous()
+    ms = timed(lambda: tr.step(atlas, sub2, tgt2))
+    flop2 = 3.0 * flop / 2.0
+    res["unet_train_step_2"] = {"ms": round(ms, 3), "GFLOP": round(flop2 / 1e9, 1),
+                                "TFLOP/s": round(flop2 / (ms * 1e-3) / 1e12, 1),
+                                "frac_bf16_peak": round(flop2 / (ms * 1e-3) / BF16_PEAK_FLOPS, 4)}
     return res
 
 

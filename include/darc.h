@@ -323,12 +323,70 @@ int darc_conv3d(const unsigned short* x0, int c0, int up0, const unsigned short*
                 int n, int d0, int d1, int d2, int ksize, int stride, const unsigned short* w,
                 const float* bias, int cout, int act, float slope, unsigned short* y_bf16,
                 float* y_f32, void* stream);
+/* darc_conv3d_grad -- adjoint of darc_conv3d (ksize 3, no activation) given
+ * the output gradient dz, channels-last BF16 [n][o][cz] (cz >= cout, a
+ * multiple of 8, zero beyond cout):
+ *   dw [cout][kpad] += sum_o dz[o][co] x(o, k)   (FP32; x read as darc_conv3d reads it)
+ *   db [cout] += sum_o dz[o][co]                 (or NULL)
+ *   dx [n][d0][d1][d2][c0 + c1] FP32 channels-last = the gradient with respect
+ *      to the concatenated (full-resolution) input, or NULL: the stride-1
+ *      convolution of dz (on the zero-dilated grid for stride 2) with the
+ *      taps flipped and the channels exchanged, from the BF16 rounding of the
+ *      FP32 weights w [cout][kpad].
+ *   wt scratch BF16 [c0 + c1][darc_conv3d_kpad(cz, 3)] (needed with dx). */
+int darc_conv3d_grad(const unsigned short* dz, int cz, const unsigned short* x0, int c0, int up0,
+                     const unsigned short* x1, int c1, int n, int d0, int d1, int d2, int stride,
+                     const float* w, int cout, float* dw, float* db, float* dx,
+                     unsigned short* wt, void* stream);
 int darc_unet_layout(int layer, int* cin, int* cout, int* kpad, size_t* w_offset,
                      size_t* b_offset);
+size_t darc_unet_num_weights(void); /* packed weights of all 8 layers */
+int darc_unet_num_biases(void);
 size_t darc_unet_ws_bytes(int n, int d0, int d1, int d2);
 int darc_unet_forward(const unsigned short* w, const float* b, const float* atlas,
                       const float* images, float* v, int n, int d0, int d1, int d2, void* ws,
                       size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Training of the warm start on (atlas, subject, DARC velocity) triples:
+ * loss = mean over n*3*V entries of (UNet(A, I_i) - v_target_i)^2.
+ *
+ * darc_unet_backward -- the loss (loss[0] += ...) and its gradient with
+ * respect to the FP32 weights and biases (dw [num_weights], db [num_biases],
+ * overwritten; zero at the padded entries).  The forward pass uses the BF16
+ * weights wq; the backward pass reads the output gradient of every layer as
+ * BF16 (rounded to nearest even) and accumulates in FP32; the input gradient
+ * of a layer is the convolution of its output gradient with flipped,
+ * channel-exchanged BF16 weights (on the zero-dilated grid for stride 2).
+ * v_pred [n][3][V] receives the prediction, or NULL.
+ * ws: scratch of darc_unet_train_ws_bytes().
+ *
+ * darc_unet_train_step -- darc_unet_backward, then one Adam step on the FP32
+ * weights and biases (the paper's optimiser and constants, step count
+ * t->step + 1), refreshing t->wq; t->step is advanced on the host.
+ * ---------------------------------------------------------------------- */
+typedef struct darc_unet_train {
+  float* w;            /* [num_weights] FP32 master weights (packed layout), in/out */
+  float* b;            /* [num_biases] FP32 biases, in/out */
+  float* mw;           /* Adam moments of w and b, in/out */
+  float* sw;
+  float* mb;
+  float* sb;
+  unsigned short* wq;  /* [num_weights] BF16 copy of w used by the convolutions, out */
+  float* dw;           /* [num_weights] gradient scratch */
+  float* db;           /* [num_biases] gradient scratch */
+  long long step;      /* Adam steps taken, in/out */
+} darc_unet_train;
+
+size_t darc_unet_train_ws_bytes(int n, int d0, int d1, int d2);
+int darc_unet_backward(const unsigned short* wq, const float* w, const float* b,
+                       const float* atlas, const float* images, const float* v_target,
+                       float* dw, float* db, double* loss, float* v_pred, int n, int d0, int d1,
+                       int d2, void* ws, size_t ws_bytes, void* stream);
+int darc_unet_train_step(darc_unet_train* t, const float* atlas, const float* images,
+                         const float* v_target, float lr, double beta1, double beta2, float eps,
+                         double* loss, int n, int d0, int d1, int d2, void* ws, size_t ws_bytes,
+                         void* stream);
 
 /* ------------------------------------------------------------------------
  * darc_down2 / darc_up2 -- factor-2 resampling between the levels of a

@@ -101,3 +101,104 @@ def flops(dims) -> float:
         level = {"e0": 0, "e1": 1, "e2": 2, "e3": 3, "d2": 2, "d1": 1, "d0": 0, "out": 0}[name]
         total += 2.0 * 27 * cin * cout * V / 8 ** level
     return total
+
+
+# ---------------------------------------------------------------------------
+# training: gradient of the mean squared velocity error
+#
+# The backward pass mirrors the kernels' precision points: each layer's
+# output gradient dz = dy * act'(y) is rounded to BF16 (act'(y) = 1 where the
+# stored output y > 0, else the slope), weights are the BF16 values, and
+# everything else is exact here (FP32 accumulation on the GPU).  With
+# ``rounded=False`` no rounding is applied anywhere, which is what the pins
+# compare with automatic differentiation.
+
+
+def conv3d_input_grad(dz: np.ndarray, w: np.ndarray, in_dims, stride: int = 1) -> np.ndarray:
+    """Adjoint of ``conv3d`` with respect to its input: the stride-1
+    convolution, zero padding 1, of dz (spread onto the zero-dilated input
+    grid for stride 2) with the taps flipped and the channel axes exchanged."""
+    dz = np.asarray(dz, dtype=np.float64)
+    if stride == 2:
+        dil = np.zeros((dz.shape[0],) + tuple(in_dims))
+        dil[:, ::2, ::2, ::2] = dz
+        dz = dil
+    wt = np.transpose(np.asarray(w, dtype=np.float64)[:, :, ::-1, ::-1, ::-1], (1, 0, 2, 3, 4))
+    return conv3d(dz, wt, np.zeros(wt.shape[0]))
+
+
+def conv3d_weight_grad(dz: np.ndarray, x: np.ndarray, stride: int = 1):
+    """(dL/dw [Cout, Cin, 3, 3, 3], dL/db [Cout]) of ``conv3d`` given the
+    output gradient dz and the input x."""
+    dz = np.asarray(dz, dtype=np.float64)
+    xp = np.pad(np.asarray(x, dtype=np.float64), ((0, 0), (1, 1), (1, 1), (1, 1)))
+    O0, O1, O2 = dz.shape[1:]
+    dw = np.zeros((dz.shape[0], x.shape[0], 3, 3, 3))
+    for a in range(3):
+        for bb in range(3):
+            for c in range(3):
+                patch = xp[:, a:a + stride * O0:stride, bb:bb + stride * O1:stride,
+                           c:c + stride * O2:stride]
+                dw[:, :, a, bb, c] = np.tensordot(dz, patch, axes=([1, 2, 3], [1, 2, 3]))
+    return dw, dz.sum(axis=(1, 2, 3))
+
+
+def down2_sum(x: np.ndarray) -> np.ndarray:
+    """Adjoint of ``up2_nearest``: the sum over each 2x2x2 block."""
+    C, D0, D1, D2 = x.shape
+    return x.reshape(C, D0 // 2, 2, D1 // 2, 2, D2 // 2, 2).sum(axis=(2, 4, 6))
+
+
+def backward(params: dict, atlas: np.ndarray, images: np.ndarray, targets: np.ndarray,
+             rounded: bool = True):
+    """Loss mean((UNet(A, I_i) - v_i)^2) over all subjects and entries, and its
+    gradients {layer: (dw, db)}."""
+    rb = bf16 if rounded else (lambda a: np.asarray(a, dtype=np.float64))
+    n = len(images)
+    count = n * targets[0].size
+    grads = {name: (0.0, 0.0) for name, *_ in layer_specs()}
+    loss = 0.0
+    for i in range(n):
+        inp, out = {}, {}
+
+        def layer(name, x, stride=1, act=True):
+            inp[name] = x
+            z = conv3d(x, *params[name], stride)
+            out[name] = rb(leaky(z)) if act else z
+            return out[name]
+
+        x = rb(np.stack([atlas, images[i]]))
+        e0 = layer("e0", x)
+        e1 = layer("e1", e0, 2)
+        e2 = layer("e2", e1, 2)
+        e3 = layer("e3", e2, 2)
+        d2 = layer("d2", np.concatenate([up2_nearest(e3), e2]))
+        d1 = layer("d1", np.concatenate([up2_nearest(d2), e1]))
+        d0 = layer("d0", np.concatenate([up2_nearest(d1), e0]))
+        v = layer("out", d0, act=False)
+        diff = v - targets[i]
+        loss += float((diff ** 2).sum()) / count
+        dy = {"out": 2.0 * diff / count}
+        strides = {name: s for name, _, _, s, _ in layer_specs()}
+        acts = {name: a for name, _, _, _, a in layer_specs()}
+        for name in ("out", "d0", "d1", "d2", "e3", "e2", "e1", "e0"):
+            g = dy[name]
+            if acts[name]:
+                g = g * np.where(out[name] > 0, 1.0, SLOPE)
+            dz = rb(g)
+            dw, db = conv3d_weight_grad(dz, inp[name], strides[name])
+            grads[name] = (grads[name][0] + dw, grads[name][1] + db)
+            if name == "e0":
+                break
+            dx = conv3d_input_grad(dz, params[name][0], inp[name].shape[1:], strides[name])
+            if name == "out":
+                dy["d0"] = dx
+            elif name in ("d0", "d1", "d2"):
+                deep, skip = {"d0": ("d1", "e0"), "d1": ("d2", "e1"), "d2": ("e3", "e2")}[name]
+                cd = params[deep][0].shape[0]
+                dy[deep] = down2_sum(dx[:cd])
+                dy[skip] = dx[cd:]
+            else:
+                prev = {"e3": "e2", "e2": "e1", "e1": "e0"}[name]
+                dy[prev] = dy[prev] + dx
+    return loss, grads

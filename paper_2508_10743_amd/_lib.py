@@ -85,6 +85,13 @@ class DarcParams(ctypes.Structure):
     ]
 
 
+class DarcUnetTrain(ctypes.Structure):
+    """Mirror of ``darc_unet_train``."""
+
+    _fields_ = [(name, c_void_p) for name in ("w", "b", "mw", "sw", "mb", "sb", "wq", "dw", "db")] + [
+        ("step", c_longlong)]
+
+
 _P = c_void_p  # device pointer
 _I = c_int
 _Z = c_size_t
@@ -116,9 +123,18 @@ PROTOTYPES = {
     "darc_conv3d_kpad": (c_int, [_I, _I]),
     "darc_conv3d": (c_int, [_P, _I, _I, _P, _I, _I, _I, _I, _I, _I, _I, _P, _P, _I, _I, c_float,
                             _P, _P, _P]),
+    "darc_conv3d_grad": (c_int, [_P, _I, _P, _I, _I, _P, _I, _I, _I, _I, _I, _I, _P, _I, _P, _P,
+                                 _P, _P, _P]),
     "darc_unet_layout": (c_int, [_I, POINTER(c_int), POINTER(c_int), POINTER(c_int),
                                  POINTER(c_size_t), POINTER(c_size_t)]),
     "darc_unet_ws_bytes": (c_size_t, [_I, _I, _I, _I]),
+    "darc_unet_num_weights": (c_size_t, []),
+    "darc_unet_num_biases": (c_int, []),
+    "darc_unet_train_ws_bytes": (c_size_t, [_I, _I, _I, _I]),
+    "darc_unet_backward": (c_int, [_P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _I, _I, _I, _I, _P, _Z,
+                                   _P]),
+    "darc_unet_train_step": (c_int, [POINTER(DarcUnetTrain), _P, _P, _P, c_float, c_double,
+                                     c_double, c_float, _P, _I, _I, _I, _I, _P, _Z, _P]),
     "darc_unet_forward": (c_int, [_P, _P, _P, _P, _P, _I, _I, _I, _I, _P, _Z, _P]),
     "darc_down2": (c_int, [_P, _P, _I, _I, _I, _I, _P]),
     "darc_up2": (c_int, [_P, _P, _I, _I, _I, _I, c_float, _P]),

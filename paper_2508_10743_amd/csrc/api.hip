@@ -560,6 +560,56 @@ int darc_conv3d(const unsigned short* x0, int c0, int up0, const unsigned short*
   return check_launch("darc_conv3d");
 }
 
+int darc_conv3d_grad(const unsigned short* dz, int cz, const unsigned short* x0, int c0, int up0,
+                     const unsigned short* x1, int c1, int n, int d0, int d1, int d2, int stride,
+                     const float* w, int cout, float* dw, float* db, float* dx,
+                     unsigned short* wt, void* stream) {
+  DARC_TRY(check_dims("darc_conv3d_grad", n, d0, d1, d2));
+  if (c0 < 8 || c0 % 8 || c1 < 0 || c1 % 8 || cz < 8 || cz % 8 || cout < 1 || cout > cz)
+    return fail(DARC_EINVAL, "darc_conv3d_grad: bad channel counts");
+  if (stride != 1 && stride != 2) return fail(DARC_EINVAL, "darc_conv3d_grad: stride must be 1 or 2");
+  if ((up0 || stride == 2) && (d0 % 2 || d1 % 2 || d2 % 2))
+    return fail(DARC_EINVAL, "darc_conv3d_grad: odd dims with upsampling or stride 2");
+  if (n == 0) return ok();
+  if (!dz || !x0 || (c1 && !x1) || !w || !dw || (dx && !wt))
+    return fail(DARC_EINVAL, "darc_conv3d_grad: NULL pointer");
+  hipStream_t st = as_stream(stream);
+  ConvGeom cg{};
+  cg.i0 = d0;
+  cg.i1 = d1;
+  cg.i2 = d2;
+  cg.stride = stride;
+  cg.o0 = (d0 - 1) / stride + 1;
+  cg.o1 = (d1 - 1) / stride + 1;
+  cg.o2 = (d2 - 1) / stride + 1;
+  cg.nvox = static_cast<long long>(n) * cg.o0 * cg.o1 * cg.o2;
+  cg.ntaps = 27;
+  cg.c0 = c0;
+  cg.c1 = c1;
+  cg.up0 = up0 ? 1 : 0;
+  cg.kpad = conv_kpad(c0 + c1, 27);
+  cg.cout = cout;
+  launch_conv_wgrad(dz, cz, x0, x1, cg, dw, db, st);
+  if (dx) {
+    const int kt = conv_kpad(cz, 27);
+    launch_pack_wt(w, c0 + c1, cout, cz, cg.kpad, kt, wt, st);
+    ConvGeom g{};
+    g.i0 = g.o0 = d0;
+    g.i1 = g.o1 = d1;
+    g.i2 = g.o2 = d2;
+    g.nvox = static_cast<long long>(n) * d0 * d1 * d2;
+    g.stride = 1;
+    g.ntaps = 27;
+    g.c0 = cz;
+    g.dil0 = stride == 2;
+    g.kpad = kt;
+    g.cout = c0 + c1;
+    g.ycl32 = 1;
+    launch_conv3d(dz, nullptr, wt, nullptr, nullptr, dx, g, st);
+  }
+  return check_launch("darc_conv3d_grad");
+}
+
 }  // extern "C"
 
 namespace {
@@ -571,29 +621,195 @@ struct UnetLayer {
 const UnetLayer kUnet[8] = {{8, 16, 1, 1},   {16, 32, 2, 1}, {32, 64, 2, 1}, {64, 128, 2, 1},
                             {192, 64, 1, 1}, {96, 32, 1, 1}, {48, 16, 1, 1}, {16, 3, 1, 0}};
 
+// Scratch of the network: BF16 activations (forward), then for training the
+// prediction, its gradient, FP32 activation gradients, one BF16 output
+// gradient, one FP32 concatenated-input gradient and one BF16 weight pack.
 struct UnetWs {
-  size_t x, e0, e1, e2, e3, d2, d1, d0, total;
+  size_t x, e0, e1, e2, e3, d2, d1, d0, fwd;                   // forward part
+  size_t vp, dv, dz, dx, wt, gd0, gd1, gd2, ge3, ge2, ge1, ge0, total;  // training part
 };
 
 UnetWs unet_ws(int n, int d0, int d1, int d2) {
   const size_t V = static_cast<size_t>(d0) * d1 * d2 * n;
   UnetWs L{};
   size_t off = 0;
-  auto take = [&](size_t elems) {
+  auto take = [&](size_t bytes) {
     const size_t o = off;
-    off += align256(elems * sizeof(uint16_t));
+    off += align256(bytes);
     return o;
   };
-  L.x = take(V * 8);
-  L.e0 = take(V * 16);
-  L.e1 = take(V / 8 * 32);
-  L.e2 = take(V / 64 * 64);
-  L.e3 = take(V / 512 * 128);
-  L.d2 = take(V / 64 * 64);
-  L.d1 = take(V / 8 * 32);
-  L.d0 = take(V * 16);
+  const size_t h = sizeof(uint16_t), f = sizeof(float);
+  L.x = take(V * 8 * h);
+  L.e0 = take(V * 16 * h);
+  L.e1 = take(V / 8 * 32 * h);
+  L.e2 = take(V / 64 * 64 * h);
+  L.e3 = take(V / 512 * 128 * h);
+  L.d2 = take(V / 64 * 64 * h);
+  L.d1 = take(V / 8 * 32 * h);
+  L.d0 = take(V * 16 * h);
+  L.fwd = off;
+  L.vp = take(V * 3 * f);
+  L.dv = take(V * 3 * f);
+  L.dz = take(V * 16 * h);
+  L.dx = take(V * 48 * f);
+  L.wt = take(static_cast<size_t>(192) * conv_kpad(64, 27) * h);
+  L.gd0 = take(V * 16 * f);
+  L.gd1 = take(V / 8 * 32 * f);
+  L.gd2 = take(V / 64 * 64 * f);
+  L.ge3 = take(V / 512 * 128 * f);
+  L.ge2 = take(V / 64 * 64 * f);
+  L.ge1 = take(V / 8 * 32 * f);
+  L.ge0 = take(V * 16 * f);
   L.total = off;
   return L;
+}
+
+// Per layer: inputs (x0 with c0 channels, optionally doubled; x1 with c1),
+// input level, BF16 output (or the FP32 velocity), and the forward geometry.
+struct UnetStep {
+  const uint16_t *x0, *x1;
+  int c0, c1, up0, lev;
+  uint16_t* y;
+  ConvGeom cg;
+  size_t wo, bo;
+};
+
+void unet_plan(char* base, const UnetWs& L, int n, int d0, int d1, int d2, UnetStep (&P)[8]) {
+  auto buf = [&](size_t o) { return reinterpret_cast<uint16_t*>(base + o); };
+  const struct {
+    size_t x0;
+    int c0, up0;
+    size_t x1;
+    int c1, lev;
+    size_t y;
+  } T[8] = {{L.x, 8, 0, 0, 0, 0, L.e0},       {L.e0, 16, 0, 0, 0, 0, L.e1},
+            {L.e1, 32, 0, 0, 0, 1, L.e2},     {L.e2, 64, 0, 0, 0, 2, L.e3},
+            {L.e3, 128, 1, L.e2, 64, 2, L.d2}, {L.d2, 64, 1, L.e1, 32, 1, L.d1},
+            {L.d1, 32, 1, L.e0, 16, 0, L.d0}, {L.d0, 16, 0, 0, 0, 0, 0}};
+  size_t wo = 0, bo = 0;
+  for (int l = 0; l < 8; ++l) {
+    const UnetLayer& U = kUnet[l];
+    UnetStep& S = P[l];
+    S.x0 = buf(T[l].x0);
+    S.x1 = T[l].c1 ? buf(T[l].x1) : nullptr;
+    S.c0 = T[l].c0;
+    S.c1 = T[l].c1;
+    S.up0 = T[l].up0;
+    S.lev = T[l].lev;
+    S.y = l < 7 ? buf(T[l].y) : nullptr;
+    ConvGeom cg{};
+    cg.i0 = d0 >> S.lev;
+    cg.i1 = d1 >> S.lev;
+    cg.i2 = d2 >> S.lev;
+    cg.stride = U.stride;
+    cg.o0 = (cg.i0 - 1) / U.stride + 1;
+    cg.o1 = (cg.i1 - 1) / U.stride + 1;
+    cg.o2 = (cg.i2 - 1) / U.stride + 1;
+    cg.nvox = static_cast<long long>(n) * cg.o0 * cg.o1 * cg.o2;
+    cg.ntaps = 27;
+    cg.c0 = S.c0;
+    cg.c1 = S.c1;
+    cg.up0 = S.up0;
+    cg.kpad = conv_kpad(U.cin, 27);
+    cg.cout = U.cout;
+    cg.act = U.act;
+    cg.slope = 0.2f;
+    S.cg = cg;
+    S.wo = wo;
+    S.bo = bo;
+    wo += static_cast<size_t>(U.cout) * cg.kpad;
+    bo += U.cout;
+  }
+}
+
+void unet_run_forward(const uint16_t* w, const float* b, const float* atlas, const float* images,
+                      float* v, int n, int d0, int d1, int d2, char* base, const UnetWs& L,
+                      const UnetStep (&P)[8], hipStream_t st) {
+  launch_pack_pair(atlas, images, reinterpret_cast<uint16_t*>(base + L.x),
+                   static_cast<long long>(d0) * d1 * d2, n, 8, st);
+  for (int l = 0; l < 8; ++l)
+    launch_conv3d(P[l].x0, P[l].x1, w + P[l].wo, b + P[l].bo, P[l].y, l == 7 ? v : nullptr,
+                  P[l].cg, st);
+}
+
+size_t unet_num_weights() {
+  size_t t = 0;
+  for (const UnetLayer& U : kUnet) t += static_cast<size_t>(U.cout) * conv_kpad(U.cin, 27);
+  return t;
+}
+
+int unet_num_biases() {
+  int t = 0;
+  for (const UnetLayer& U : kUnet) t += U.cout;
+  return t;
+}
+
+int check_unet(const char* fn, int n, int d0, int d1, int d2) {
+  DARC_TRY(check_dims(fn, n, d0, d1, d2));
+  if (d0 % 8 || d1 % 8 || d2 % 8 || d0 < 8 || d1 < 8 || d2 < 8)
+    return fail(DARC_EINVAL, "%s: dims must be multiples of 8", fn);
+  return DARC_OK;
+}
+
+// Gradient of the mean squared error of the prediction against v_target
+// with respect to the FP32 weights: dw, db overwritten; loss += the error.
+void unet_run_backward(const uint16_t* wq, const float* w, const float* b, const float* atlas,
+                       const float* images, const float* target, int n, int d0, int d1, int d2,
+                       char* base, const UnetWs& L, const UnetStep (&P)[8], float* dw, float* db,
+                       double* loss, float* vpred, hipStream_t st) {
+  auto f32 = [&](size_t o) { return reinterpret_cast<float*>(base + o); };
+  auto b16 = [&](size_t o) { return reinterpret_cast<uint16_t*>(base + o); };
+  float* vp = vpred ? vpred : f32(L.vp);
+  unet_run_forward(wq, b, atlas, images, vp, n, d0, d1, d2, base, L, P, st);
+  const long long V = static_cast<long long>(d0) * d1 * d2;
+  launch_vec_mse(vp, target, static_cast<long long>(n) * 3 * V, loss, f32(L.dv), st);
+  launch_fill_f32(dw, static_cast<long long>(unet_num_weights()), 0.0f, st);
+  launch_fill_f32(db, unet_num_biases(), 0.0f, st);
+  // gradient with respect to each layer's output (FP32 channels-last)
+  float* dy[8] = {f32(L.ge0), f32(L.ge1), f32(L.ge2), f32(L.ge3),
+                  f32(L.gd2), f32(L.gd1), f32(L.gd0), f32(L.dv)};
+  uint16_t* dz = b16(L.dz);
+  uint16_t* wt = b16(L.wt);
+  float* dx = f32(L.dx);
+  for (int l = 7; l >= 0; --l) {
+    const UnetStep& S = P[l];
+    const UnetLayer& U = kUnet[l];
+    const int cz = (U.cout + 7) / 8 * 8;
+    launch_act_bwd(dy[l], S.y, S.cg.nvox, n, U.cout, cz, U.act, l == 7, 0.2f, dz, st);
+    launch_conv_wgrad(dz, cz, S.x0, S.x1, S.cg, dw + S.wo, db + S.bo, st);
+    if (l == 0) break;
+    // input gradient: a stride-1 convolution of dz (on the dilated grid for
+    // stride-2 layers) with flipped taps and exchanged channels
+    const int kt = conv_kpad(cz, 27);
+    launch_pack_wt(w + S.wo, U.cin, U.cout, cz, S.cg.kpad, kt, wt, st);
+    ConvGeom g{};
+    g.i0 = S.cg.i0;
+    g.i1 = S.cg.i1;
+    g.i2 = S.cg.i2;
+    g.o0 = g.i0;
+    g.o1 = g.i1;
+    g.o2 = g.i2;
+    g.nvox = static_cast<long long>(n) * g.i0 * g.i1 * g.i2;
+    g.stride = 1;
+    g.ntaps = 27;
+    g.c0 = cz;
+    g.c1 = 0;
+    g.dil0 = U.stride == 2;
+    g.kpad = kt;
+    g.cout = U.cin;
+    g.ycl32 = 1;
+    const Geom full = make_geom(g.i0, g.i1, g.i2);
+    if (S.c1) {  // concatenated input: split into the deeper and the skip tensor
+      launch_conv3d(dz, nullptr, wt, nullptr, nullptr, dx, g, st);
+      // layer 4 reads (e3, e2), layer 5 (d2, e1), layer 6 (d1, e0)
+      launch_split_grad(dx, full, n, S.c0, S.c1, dy[l - 1], dy[6 - l], st);
+    } else if (l == 7) {
+      launch_conv3d(dz, nullptr, wt, nullptr, nullptr, dy[6], g, st);
+    } else {  // stride-2 encoder layers: their input already holds the skip part
+      g.accum = 1;
+      launch_conv3d(dz, nullptr, wt, nullptr, nullptr, dy[l - 1], g, st);
+    }
+  }
 }
 
 }  // namespace
@@ -616,7 +832,15 @@ int darc_unet_layout(int layer, int* cin, int* cout, int* kpad, size_t* w_offset
   return ok();
 }
 
+size_t darc_unet_num_weights(void) { return unet_num_weights(); }
+int darc_unet_num_biases(void) { return unet_num_biases(); }
+
 size_t darc_unet_ws_bytes(int n, int d0, int d1, int d2) {
+  if (n < 1 || d0 < 8 || d1 < 8 || d2 < 8 || d0 % 8 || d1 % 8 || d2 % 8) return 0;
+  return unet_ws(n, d0, d1, d2).fwd;
+}
+
+size_t darc_unet_train_ws_bytes(int n, int d0, int d1, int d2) {
   if (n < 1 || d0 < 8 || d1 < 8 || d2 < 8 || d0 % 8 || d1 % 8 || d2 % 8) return 0;
   return unet_ws(n, d0, d1, d2).total;
 }
@@ -624,51 +848,56 @@ size_t darc_unet_ws_bytes(int n, int d0, int d1, int d2) {
 int darc_unet_forward(const unsigned short* w, const float* b, const float* atlas,
                       const float* images, float* v, int n, int d0, int d1, int d2, void* ws,
                       size_t ws_bytes, void* stream) {
-  DARC_TRY(check_dims("darc_unet_forward", n, d0, d1, d2));
-  if (d0 % 8 || d1 % 8 || d2 % 8 || d0 < 8 || d1 < 8 || d2 < 8)
-    return fail(DARC_EINVAL, "darc_unet_forward: dims must be multiples of 8");
+  DARC_TRY(check_unet("darc_unet_forward", n, d0, d1, d2));
   if (n == 0) return ok();
   if (!w || !b || !atlas || !images || !v) return fail(DARC_EINVAL, "darc_unet_forward: NULL pointer");
   DARC_TRY(check_ws("darc_unet_forward", ws, ws_bytes, darc_unet_ws_bytes(n, d0, d1, d2)));
   const UnetWs L = unet_ws(n, d0, d1, d2);
-  hipStream_t st = as_stream(stream);
+  UnetStep P[8];
   char* base = static_cast<char*>(ws);
-  auto buf = [&](size_t o) { return reinterpret_cast<uint16_t*>(base + o); };
-  launch_pack_pair(atlas, images, buf(L.x), static_cast<long long>(d0) * d1 * d2, n, 8, st);
-  size_t wo = 0, bo = 0;
-  auto conv = [&](int l, const uint16_t* x0, int c0, int up0, const uint16_t* x1, int c1, int lev,
-                  uint16_t* y16, float* y32) {
-    const UnetLayer& U = kUnet[l];
-    ConvGeom cg{};
-    cg.i0 = d0 >> lev;
-    cg.i1 = d1 >> lev;
-    cg.i2 = d2 >> lev;
-    cg.stride = U.stride;
-    cg.o0 = (cg.i0 - 1) / U.stride + 1;
-    cg.o1 = (cg.i1 - 1) / U.stride + 1;
-    cg.o2 = (cg.i2 - 1) / U.stride + 1;
-    cg.nvox = static_cast<long long>(n) * cg.o0 * cg.o1 * cg.o2;
-    cg.ntaps = 27;
-    cg.c0 = c0;
-    cg.c1 = c1;
-    cg.up0 = up0;
-    cg.kpad = conv_kpad(U.cin, 27);
-    cg.cout = U.cout;
-    cg.act = U.act;
-    cg.slope = 0.2f;
-    launch_conv3d(x0, x1, w + wo, b + bo, y16, y32, cg, st);
-    wo += static_cast<size_t>(U.cout) * cg.kpad;
-    bo += U.cout;
-  };
-  conv(0, buf(L.x), 8, 0, nullptr, 0, 0, buf(L.e0), nullptr);
-  conv(1, buf(L.e0), 16, 0, nullptr, 0, 0, buf(L.e1), nullptr);
-  conv(2, buf(L.e1), 32, 0, nullptr, 0, 1, buf(L.e2), nullptr);
-  conv(3, buf(L.e2), 64, 0, nullptr, 0, 2, buf(L.e3), nullptr);
-  conv(4, buf(L.e3), 128, 1, buf(L.e2), 64, 2, buf(L.d2), nullptr);
-  conv(5, buf(L.d2), 64, 1, buf(L.e1), 32, 1, buf(L.d1), nullptr);
-  conv(6, buf(L.d1), 32, 1, buf(L.e0), 16, 0, buf(L.d0), nullptr);
-  conv(7, buf(L.d0), 16, 0, nullptr, 0, 0, nullptr, v);
+  unet_plan(base, L, n, d0, d1, d2, P);
+  unet_run_forward(w, b, atlas, images, v, n, d0, d1, d2, base, L, P, as_stream(stream));
   return check_launch("darc_unet_forward");
+}
+
+int darc_unet_backward(const unsigned short* wq, const float* w, const float* b,
+                       const float* atlas, const float* images, const float* v_target,
+                       float* dw, float* db, double* loss, float* v_pred, int n, int d0, int d1,
+                       int d2, void* ws, size_t ws_bytes, void* stream) {
+  DARC_TRY(check_unet("darc_unet_backward", n, d0, d1, d2));
+  if (n < 1) return fail(DARC_EINVAL, "darc_unet_backward: n must be >= 1");
+  if (!wq || !w || !b || !atlas || !images || !v_target || !dw || !db || !loss)
+    return fail(DARC_EINVAL, "darc_unet_backward: NULL pointer");
+  DARC_TRY(check_ws("darc_unet_backward", ws, ws_bytes, darc_unet_train_ws_bytes(n, d0, d1, d2)));
+  const UnetWs L = unet_ws(n, d0, d1, d2);
+  UnetStep P[8];
+  char* base = static_cast<char*>(ws);
+  unet_plan(base, L, n, d0, d1, d2, P);
+  unet_run_backward(wq, w, b, atlas, images, v_target, n, d0, d1, d2, base, L, P, dw, db, loss,
+                    v_pred, as_stream(stream));
+  return check_launch("darc_unet_backward");
+}
+
+int darc_unet_train_step(darc_unet_train* t, const float* atlas, const float* images,
+                         const float* v_target, float lr, double beta1, double beta2, float eps,
+                         double* loss, int n, int d0, int d1, int d2, void* ws, size_t ws_bytes,
+                         void* stream) {
+  DARC_TRY(check_unet("darc_unet_train_step", n, d0, d1, d2));
+  if (!t || !t->w || !t->b || !t->mw || !t->sw || !t->mb || !t->sb || !t->wq || !t->dw || !t->db)
+    return fail(DARC_EINVAL, "darc_unet_train_step: NULL pointer in the training state");
+  if (t->step < 0) return fail(DARC_EINVAL, "darc_unet_train_step: step must be >= 0");
+  if (!(beta1 >= 0.0 && beta1 < 1.0 && beta2 >= 0.0 && beta2 < 1.0) || !(eps > 0.0f))
+    return fail(DARC_EINVAL, "darc_unet_train_step: bad Adam constants");
+  DARC_TRY(darc_unet_backward(t->wq, t->w, t->b, atlas, images, v_target, t->dw, t->db, loss,
+                              nullptr, n, d0, d1, d2, ws, ws_bytes, stream));
+  hipStream_t st = as_stream(stream);
+  const long long nw = static_cast<long long>(unet_num_weights());
+  launch_adam(t->w, t->w, t->mw, t->sw, t->dw, nw, t->step + 1, lr, beta1, beta2, eps, st);
+  launch_adam(t->b, t->b, t->mb, t->sb, t->db, unet_num_biases(), t->step + 1, lr, beta1, beta2,
+              eps, st);
+  launch_to_bf16(t->w, t->wq, nw, st);
+  t->step += 1;
+  return check_launch("darc_unet_train_step");
 }
 
 // ------------------------------------------------------------- resampling

@@ -143,8 +143,10 @@ struct ConvGeom {
   int stride, ntaps;  // 1 or 2; 27 or 1
   int c0, c1;         // channels of x0 and x1 (multiples of 8; c1 may be 0)
   int up0;            // x0 is at half resolution, doubled by nearest neighbour
+  int dil0;           // x0 is at half resolution on the even positions only (zeros between)
   int kpad, cout, act;
   float slope;
+  int ycl32, accum;   // y32 channels-last [nvox][cout] instead of planar; add to y32
 };
 // Weight row length for cin input channels: ntaps * ceil(cin/8) * 8 rounded up to 32.
 int conv_kpad(int cin, int ntaps);
@@ -154,6 +156,31 @@ void launch_conv3d(const uint16_t* x0, const uint16_t* x1, const uint16_t* w, co
 // x [n][V][cpad] BF16 = (atlas, image_i, 0 ...)
 void launch_pack_pair(const float* atlas, const float* images, uint16_t* x, long long V, int n,
                       int cpad, hipStream_t st);
+
+// --- training of the warm-start network ------------------------------------
+// dw [cout][kpad] += sum over the forward conv cg's output voxels of
+// dz[v][co] * X(v, k) (X the conv's input patch, as the forward loader reads
+// it); dz channels-last BF16 [nvox][cz].  db [cout] += sum_v dz[v][co].
+void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uint16_t* x1,
+                       const ConvGeom& cg, float* dw, float* db, hipStream_t st);
+// Weights of the input-gradient convolution: wt[ci][k'] for k' = tap' * cz + co,
+// = w[co][(26 - tap') * cin + ci] (flipped taps, exchanged channels), from the
+// FP32 master weights w [cout][kpad_f]; zero for co >= cout, tap' >= 27.
+void launch_pack_wt(const float* w, int cin, int cout, int cz, int kpad_f, int kpad_t,
+                    uint16_t* wt, hipStream_t st);
+// dz = BF16(dy * act'(y)) channels-last [nvox][cz], dy FP32 [nvox][c] (planar
+// [n][c][nvox/n] when planar), y the layer's BF16 output (ignored when !act).
+void launch_act_bwd(const float* dy, const uint16_t* y, long long nvox, int n, int c, int cz,
+                    int act, int planar, float slope, uint16_t* dz, hipStream_t st);
+// Gradient of cat(up2(x0), x1) split: d0 [n][half][c0] = sum over the 8 children
+// of dx[..][0:c0]; d1 [n][full][c1] = dx[..][c0:c0+c1] (both overwritten).
+void launch_split_grad(const float* dx, const Geom& full, int n, int c0, int c1, float* d0,
+                       float* d1, hipStream_t st);
+// out = BF16(in), count values
+void launch_to_bf16(const float* in, uint16_t* out, long long count, hipStream_t st);
+// loss += sum (p - t)^2 / count (FP64), g = 2 (p - t) / count
+void launch_vec_mse(const float* p, const float* t, long long count, double* loss, float* g,
+                    hipStream_t st);
 
 // --- small helpers --------------------------------------------------------
 void launch_fill_f32(float* p, long long count, float value, hipStream_t st);

@@ -38,6 +38,33 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
   return static_cast<uint16_t>(u >> 16);
 }
 
+// Address of input channel ch (8-aligned for vector reads) at tap `tap` of
+// output voxel (s, o0, o1, o2), or nullptr where the input is zero (padding,
+// taps beyond the kernel, odd positions of a dilated x0).
+__device__ __forceinline__ const uint16_t* input_at(const ConvGeom& cg, const uint16_t* x0,
+                                                    const uint16_t* x1, int s, int o0, int o1,
+                                                    int o2, int tap, int ch) {
+  if (tap >= cg.ntaps) return nullptr;
+  int a = 1, b = 1, c = 1;
+  if (cg.ntaps == 27) {
+    a = tap / 9;
+    b = (tap / 3) % 3;
+    c = tap % 3;
+  }
+  const int p0 = o0 * cg.stride + a - 1, p1 = o1 * cg.stride + b - 1, p2 = o2 * cg.stride + c - 1;
+  if (p0 < 0 || p0 >= cg.i0 || p1 < 0 || p1 >= cg.i1 || p2 < 0 || p2 >= cg.i2) return nullptr;
+  if (ch < cg.c0) {
+    if (cg.dil0 && ((p0 | p1 | p2) & 1)) return nullptr;
+    const bool half = cg.up0 || cg.dil0;
+    const int h1 = half ? cg.i1 / 2 : cg.i1, h2 = half ? cg.i2 / 2 : cg.i2;
+    const int h0 = half ? cg.i0 / 2 : cg.i0;
+    const int q0 = half ? p0 >> 1 : p0, q1 = half ? p1 >> 1 : p1, q2 = half ? p2 >> 1 : p2;
+    return x0 + ((((static_cast<long long>(s) * h0 + q0) * h1 + q1) * h2 + q2) * cg.c0 + ch);
+  }
+  return x1 + ((((static_cast<long long>(s) * cg.i0 + p0) * cg.i1 + p1) * cg.i2 + p2) * cg.c1 +
+               (ch - cg.c0));
+}
+
 template <int NT16>
 __global__ __launch_bounds__(CNT) void k_conv3d(const uint16_t* __restrict__ x0,
                                                 const uint16_t* __restrict__ x1,
@@ -65,35 +92,14 @@ __global__ __launch_bounds__(CNT) void k_conv3d(const uint16_t* __restrict__ x0,
 #pragma unroll
   for (int t = 0; t < NT16; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   const int cvec = (cg.c0 + cg.c1) >> 3;
-  const int h0 = cg.up0 ? cg.i0 / 2 : cg.i0, h1 = cg.up0 ? cg.i1 / 2 : cg.i1,
-            h2 = cg.up0 ? cg.i2 / 2 : cg.i2;
   for (int kc = 0; kc < cg.kpad; kc += 32) {
     // A fragment: 8 channels of one tap at this lane's voxel
     const int kv = (kc >> 3) + kg;
     const int tap = kv / cvec, v = kv - tap * cvec;
     uint4 araw = make_uint4(0u, 0u, 0u, 0u);
-    if (mv && tap < cg.ntaps) {
-      int a = 1, b = 1, c = 1;
-      if (cg.ntaps == 27) {
-        a = tap / 9;
-        b = (tap / 3) % 3;
-        c = tap % 3;
-      }
-      const int p0 = o0 * cg.stride + a - 1, p1 = o1 * cg.stride + b - 1,
-                p2 = o2 * cg.stride + c - 1;
-      if (p0 >= 0 && p0 < cg.i0 && p1 >= 0 && p1 < cg.i1 && p2 >= 0 && p2 < cg.i2) {
-        const int ch = v * 8;
-        const uint16_t* src;
-        if (ch < cg.c0) {
-          const int q0 = cg.up0 ? p0 >> 1 : p0, q1 = cg.up0 ? p1 >> 1 : p1,
-                    q2 = cg.up0 ? p2 >> 1 : p2;
-          src = x0 + ((((static_cast<long long>(s) * h0 + q0) * h1 + q1) * h2 + q2) * cg.c0 + ch);
-        } else {
-          src = x1 + ((((static_cast<long long>(s) * cg.i0 + p0) * cg.i1 + p1) * cg.i2 + p2) *
-                          cg.c1 + (ch - cg.c0));
-        }
-        araw = *reinterpret_cast<const uint4*>(src);
-      }
+    if (mv) {
+      const uint16_t* src = input_at(cg, x0, x1, s, o0, o1, o2, tap, v * 8);
+      if (src) araw = *reinterpret_cast<const uint4*>(src);
     }
     const bf16x8 afrag = __builtin_bit_cast(bf16x8, araw);
 #pragma unroll
@@ -121,6 +127,9 @@ __global__ __launch_bounds__(CNT) void k_conv3d(const uint16_t* __restrict__ x0,
       if (cg.act) val = val > 0.0f ? val : cg.slope * val;
       if (y16) {
         y16[mo * cg.cout + co] = to_bf16(val);
+      } else if (cg.ycl32) {
+        float* d = y32 + mo * cg.cout + co;
+        *d = cg.accum ? *d + val : val;
       } else {
         const long long so = mo / ov;
         y32[(so * cg.cout + co) * ov + (mo - so * ov)] = val;
@@ -143,7 +152,226 @@ __global__ __launch_bounds__(kBlock) void k_pack_pair(const float* __restrict__ 
   for (int c = 2; c < cpad; ++c) o[c] = 0;
 }
 
+// ------------------------------------------------------------- training
+
+__device__ __forceinline__ float from_bf16(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+// dW tile 16 (co) x 16 (k) of one wave over a chunk of output voxels:
+// C[co][k] = sum_v dz[v][co] X(v, k) with A = dz^T (lane: row co, 8
+// consecutive voxels) and B = X (lane: column k, the same 8 voxels).
+constexpr int WCH = 1024;  // voxels per wave
+__global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ dz, int cz,
+                                                   const uint16_t* __restrict__ x0,
+                                                   const uint16_t* __restrict__ x1, ConvGeom cg,
+                                                   float* __restrict__ dw) {
+  const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+  const int cin = cg.c0 + cg.c1;
+  const int kcol = blockIdx.y * 16 + r;   // this lane's B column
+  const int corow = blockIdx.z * 16 + r;  // this lane's A row
+  const int tap = kcol / cin, ci = kcol - tap * cin;
+  const long long ov = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
+  f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int step = 0; step < WCH; step += 32) {
+    const long long vb = static_cast<long long>(blockIdx.x) * WCH + step;
+    if (vb >= cg.nvox) break;  // uniform across the wave: every lane keeps its operands
+    const long long v0 = vb + 8 * g;
+    int s = static_cast<int>(v0 / ov);
+    int rem = static_cast<int>(v0 - s * ov);
+    int o2 = rem % cg.o2;
+    rem /= cg.o2;
+    int o1 = rem % cg.o1, o0 = rem / cg.o1;
+    uint16_t av[8], bv[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const long long v = v0 + j;
+      av[j] = 0;
+      bv[j] = 0;
+      if (v < cg.nvox) {
+        if (corow < cz) av[j] = dz[v * cz + corow];
+        const uint16_t* src = input_at(cg, x0, x1, s, o0, o1, o2, tap, ci);
+        if (src) bv[j] = *src;
+      }
+      if (++o2 == cg.o2) {
+        o2 = 0;
+        if (++o1 == cg.o1) {
+          o1 = 0;
+          if (++o0 == cg.o0) {
+            o0 = 0;
+            ++s;
+          }
+        }
+      }
+    }
+    uint4 ar, br;
+    ar.x = av[0] | (static_cast<uint32_t>(av[1]) << 16);
+    ar.y = av[2] | (static_cast<uint32_t>(av[3]) << 16);
+    ar.z = av[4] | (static_cast<uint32_t>(av[5]) << 16);
+    ar.w = av[6] | (static_cast<uint32_t>(av[7]) << 16);
+    br.x = bv[0] | (static_cast<uint32_t>(bv[1]) << 16);
+    br.y = bv[2] | (static_cast<uint32_t>(bv[3]) << 16);
+    br.z = bv[4] | (static_cast<uint32_t>(bv[5]) << 16);
+    br.w = bv[6] | (static_cast<uint32_t>(bv[7]) << 16);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ar),
+                                                  __builtin_bit_cast(bf16x8, br), acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int co = blockIdx.z * 16 + 4 * g + i;
+    if (co < cg.cout && kcol < cg.kpad) atomicAdd(dw + static_cast<long long>(co) * cg.kpad + kcol, acc[i]);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bias_grad(const uint16_t* __restrict__ dz, int cz,
+                                                      int cout, long long nvox,
+                                                      float* __restrict__ db) {
+  const int c = threadIdx.x % cz, lane_v = threadIdx.x / cz, per = kBlock / cz;
+  const long long v0 = static_cast<long long>(blockIdx.x) * 4096;
+  float acc = 0.0f;
+  for (long long v = v0 + lane_v; v < v0 + 4096 && v < nvox; v += per) acc += from_bf16(dz[v * cz + c]);
+  if (c < cout) atomicAdd(db + c, acc);
+}
+
+__global__ __launch_bounds__(kBlock) void k_pack_wt(const float* __restrict__ w, int cin, int cout,
+                                                    int cz, int kpad_f, int kpad_t,
+                                                    uint16_t* __restrict__ wt) {
+  const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= static_cast<long long>(cin) * kpad_t) return;
+  const int ci = static_cast<int>(i / kpad_t), k = static_cast<int>(i - static_cast<long long>(ci) * kpad_t);
+  const int tp = k / cz, co = k - tp * cz;
+  float val = 0.0f;
+  if (tp < 27 && co < cout) val = w[static_cast<long long>(co) * kpad_f + (26 - tp) * cin + ci];
+  wt[i] = to_bf16(val);
+}
+
+__global__ __launch_bounds__(kBlock) void k_act_bwd(const float* __restrict__ dy,
+                                                    const uint16_t* __restrict__ y, long long nvox,
+                                                    long long vps, int c, int cz, int act,
+                                                    int planar, float slope,
+                                                    uint16_t* __restrict__ dz) {
+  const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= nvox * cz) return;
+  const long long v = i / cz;
+  const int ch = static_cast<int>(i - v * cz);
+  float d = 0.0f;
+  if (ch < c) {
+    if (planar) {
+      const long long s = v / vps;
+      d = dy[(s * c + ch) * vps + (v - s * vps)];
+    } else {
+      d = dy[v * c + ch];
+    }
+    if (act && !(from_bf16(y[v * c + ch]) > 0.0f)) d *= slope;
+  }
+  dz[i] = to_bf16(d);
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_half(const float* __restrict__ dx, Geom full,
+                                                       int n, int c0, int c1,
+                                                       float* __restrict__ d0) {
+  const int h0 = full.d0 / 2, h1 = full.d1 / 2, h2 = full.d2 / 2;
+  const long long hv = static_cast<long long>(h0) * h1 * h2;
+  const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= n * hv * c0) return;
+  const long long q = i / c0;
+  const int ch = static_cast<int>(i - q * c0);
+  const long long s = q / hv;
+  int rem = static_cast<int>(q - s * hv);
+  const int q2 = rem % h2;
+  rem /= h2;
+  const int q1 = rem % h1, q0 = rem / h1;
+  const int ct = c0 + c1;
+  float acc = 0.0f;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const long long p = ((s * full.d0 + 2 * q0 + a) * full.d1 + 2 * q1 + b) * full.d2 + 2 * q2 + e;
+        acc += dx[p * ct + ch];
+      }
+  d0[i] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_split_skip(const float* __restrict__ dx, long long nv,
+                                                       int c0, int c1, float* __restrict__ d1) {
+  const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i >= nv * c1) return;
+  const long long v = i / c1;
+  d1[i] = dx[v * (c0 + c1) + c0 + (i - v * c1)];
+}
+
+__global__ __launch_bounds__(kBlock) void k_to_bf16(const float* __restrict__ in,
+                                                    uint16_t* __restrict__ out, long long count) {
+  const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  if (i < count) out[i] = to_bf16(in[i]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_vec_mse(const float* __restrict__ p,
+                                                    const float* __restrict__ t, long long count,
+                                                    double inv, double* __restrict__ loss,
+                                                    float* __restrict__ g) {
+  __shared__ double red[kBlock / 64];
+  const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  double acc = 0.0;
+  if (i < count) {
+    const double d = static_cast<double>(p[i]) - static_cast<double>(t[i]);
+    acc = d * d * inv;
+    g[i] = static_cast<float>(2.0 * d * inv);
+  }
+  const double tot = block_sum<kBlock>(acc, red);
+  if (threadIdx.x == 0) atomicAdd(loss, tot);
+}
+
 }  // namespace
+
+uint32_t grid_1d(long long count) { return static_cast<uint32_t>((count + kBlock - 1) / kBlock); }
+
+void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uint16_t* x1,
+                       const ConvGeom& cg, float* dw, float* db, hipStream_t st) {
+  prof_begin(st, KC_MISC);
+  const dim3 grid(static_cast<uint32_t>((cg.nvox + WCH - 1) / WCH),
+                  static_cast<uint32_t>(cg.kpad / 16), static_cast<uint32_t>((cg.cout + 15) / 16));
+  hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(64), 0, st, dz, cz, x0, x1, cg, dw);
+  if (db)
+    hipLaunchKernelGGL(k_bias_grad, dim3(static_cast<uint32_t>((cg.nvox + 4095) / 4096)),
+                       dim3(kBlock), 0, st, dz, cz, cg.cout, cg.nvox, db);
+  prof_end(st, KC_MISC);
+}
+
+void launch_pack_wt(const float* w, int cin, int cout, int cz, int kpad_f, int kpad_t,
+                    uint16_t* wt, hipStream_t st) {
+  hipLaunchKernelGGL(k_pack_wt, dim3(grid_1d(static_cast<long long>(cin) * kpad_t)), dim3(kBlock),
+                     0, st, w, cin, cout, cz, kpad_f, kpad_t, wt);
+}
+
+void launch_act_bwd(const float* dy, const uint16_t* y, long long nvox, int n, int c, int cz,
+                    int act, int planar, float slope, uint16_t* dz, hipStream_t st) {
+  hipLaunchKernelGGL(k_act_bwd, dim3(grid_1d(nvox * cz)), dim3(kBlock), 0, st, dy, y, nvox,
+                     nvox / n, c, cz, act, planar, slope, dz);
+}
+
+void launch_split_grad(const float* dx, const Geom& full, int n, int c0, int c1, float* d0,
+                       float* d1, hipStream_t st) {
+  const long long hv = static_cast<long long>(full.d0 / 2) * (full.d1 / 2) * (full.d2 / 2);
+  hipLaunchKernelGGL(k_split_half, dim3(grid_1d(n * hv * c0)), dim3(kBlock), 0, st, dx, full, n,
+                     c0, c1, d0);
+  const long long nv = static_cast<long long>(n) * full.V;
+  hipLaunchKernelGGL(k_split_skip, dim3(grid_1d(nv * c1)), dim3(kBlock), 0, st, dx, nv, c0, c1,
+                     d1);
+}
+
+void launch_to_bf16(const float* in, uint16_t* out, long long count, hipStream_t st) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_1d(count)), dim3(kBlock), 0, st, in, out, count);
+}
+
+void launch_vec_mse(const float* p, const float* t, long long count, double* loss, float* g,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_vec_mse, dim3(grid_1d(count)), dim3(kBlock), 0, st, p, t, count,
+                     1.0 / static_cast<double>(count), loss, g);
+}
 
 int conv_kpad(int cin, int ntaps) {
   const int cv = (cin + 7) / 8;

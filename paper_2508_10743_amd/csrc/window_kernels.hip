@@ -81,8 +81,8 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
                                                   long long wstr, long long astr) {
   constexpr int R = W / 2, HX = kTX + 2 * R, HY = kTY + 2 * R;
   constexpr double kInvN = 1.0 / (W * W * W);
-  __shared__ double sI[HY * HX];
-  __shared__ double sJ[HY * HX];
+  __shared__ __attribute__((aligned(16))) double sI[HY * HX];
+  __shared__ __attribute__((aligned(16))) double sJ[HY * HX];
   __shared__ double sr[5][HY * kTX];
   __shared__ double red[kNT / 64];
   const Geom& g = mg.g;
@@ -124,6 +124,8 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
         // slides the first by one (add the entering tap, drop the leaving one)
         for (int e = tid; e < HY * (kTX / 2); e += kNT) {
           const int hy = e / (kTX / 2), cx = 2 * (e - hy * (kTX / 2));
+          // (scalar loads: staging the W + 1 taps in registers would push
+          // the kernel past the register budget of three waves per SIMD)
           const double* rI = sI + hy * HX + cx;
           const double* rJ = sJ + hy * HX + cx;
           double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
@@ -199,7 +201,7 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
     const float* __restrict__ u, float* __restrict__ gu, double* __restrict__ loss,
     int loss_stride, RegW rw, MarchGeom mg, double neg_inv_v, long long wstr, long long astr) {
   constexpr int R = W / 2, HX = kTX + 2 * R, HY = kTY + 2 * R;
-  __shared__ double sIn[4][HY * HX];
+  __shared__ __attribute__((aligned(16))) double sIn[4][HY * HX];
   __shared__ double sr[4][HY * kTX];
   __shared__ double red[kNT / 64];
   const Geom& g = mg.g;
@@ -246,12 +248,20 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
           const int o = hy * kTX + cx;
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            const double* r = &sIn[c][hy * HX + cx];
+            // aligned 16-byte pairs, conflict-free across the wave
+            const double2* pr = reinterpret_cast<const double2*>(&sIn[c][hy * HX + cx]);
+            double t[W + 1];
+#pragma unroll
+            for (int q = 0; q < (W + 1) / 2; ++q) {
+              const double2 a = pr[q];
+              t[2 * q] = a.x;
+              t[2 * q + 1] = a.y;
+            }
             double a = 0.0;
 #pragma unroll
-            for (int k = 0; k < W; ++k) a += r[k];
+            for (int k = 0; k < W; ++k) a += t[k];
             sr[c][o] = a;
-            sr[c][o + 1] = a + (r[W] - r[0]);
+            sr[c][o + 1] = a + (t[W] - t[0]);
           }
         }
         __syncthreads();

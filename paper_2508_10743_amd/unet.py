@@ -123,3 +123,97 @@ def conv3d(x0: torch.Tensor, w: torch.Tensor, bias: Optional[torch.Tensor], cout
     _call("darc_conv3d", _p(x0), c0, int(up0), _p(x1), c1, n, d0, d1, d2, ksize, stride, _p(w),
           _p(bias), cout, int(act), slope, _p(y16), _p(y32), _stream())
     return y32 if out_planar else y16
+
+
+def conv3d_grad(dz: torch.Tensor, x0: torch.Tensor, w32: torch.Tensor, cout: int,
+                stride: int = 1, x1: Optional[torch.Tensor] = None, up0: bool = False,
+                input_grad: bool = True):
+    """Adjoint of :func:`conv3d` (ksize 3) through ``darc_conv3d_grad``: dz
+    channels-last BF16 ``[n, O0, O1, O2, cz]``; w32 packed FP32 ``[cout, kpad]``.
+    Returns (dw FP32 ``[cout, kpad]``, db ``[cout]``, dx FP32 channels-last
+    ``[n, D0, D1, D2, c0 + c1]`` or None)."""
+    _dev("dz", dz, dtype=torch.bfloat16, ndim=5)
+    _dev("x0", x0, dtype=torch.bfloat16, ndim=5)
+    n, h0, h1, h2, c0 = x0.shape
+    d0, d1, d2 = (2 * h0, 2 * h1, 2 * h2) if up0 else (h0, h1, h2)
+    c1 = 0 if x1 is None else x1.shape[4]
+    cz = dz.shape[4]
+    dw = torch.zeros_like(w32)
+    db = torch.zeros(cout, dtype=torch.float32, device=dz.device)
+    dx = wt = None
+    if input_grad:
+        dx = torch.empty((n, d0, d1, d2, c0 + c1), dtype=torch.float32, device=dz.device)
+        wt = torch.empty((c0 + c1, lib().darc_conv3d_kpad(cz, 3)), dtype=torch.bfloat16,
+                         device=dz.device)
+    _call("darc_conv3d_grad", _p(dz), cz, _p(x0), c0, int(up0), _p(x1), c1, n, d0, d1, d2,
+          stride, _p(w32), cout, _p(dw), _p(db), _p(dx), _p(wt), _stream())
+    return dw, db, dx
+
+
+def unpack_weights(packed: np.ndarray, cin: int, ksize: int = 3) -> np.ndarray:
+    """Inverse of :func:`pack_weights`: [cout][kpad] -> [cout][cin][k][k][k]."""
+    cout = packed.shape[0]
+    cin_p = (cin + 7) // 8 * 8
+    taps = ksize ** 3
+    t = packed[:, :taps * cin_p].reshape(cout, taps, cin_p)[:, :, :cin]
+    return np.moveaxis(t, 2, 1).reshape(cout, cin, ksize, ksize, ksize)
+
+
+class Trainer:
+    """Adam training of a :class:`UNet` on (atlas, subject, target velocity)
+    triples through ``darc_unet_train_step``: FP32 master weights and moments
+    on the device, the BF16 copy refreshed after every step (and used by the
+    network's forward pass from then on)."""
+
+    def __init__(self, net: UNet, lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999,
+                 eps: float = 1e-8):
+        self.net, self.lr, self.beta1, self.beta2, self.eps = net, lr, beta1, beta2, eps
+        dev = net.device
+        w = np.concatenate([pack_weights(w).ravel() for w in net.weights])
+        b = np.concatenate(net.biases)
+        self.w = torch.from_numpy(w).to(dev)
+        self.b = torch.from_numpy(b).to(dev)
+        self.mw, self.sw = torch.zeros_like(self.w), torch.zeros_like(self.w)
+        self.mb, self.sb = torch.zeros_like(self.b), torch.zeros_like(self.b)
+        self.dw, self.db = torch.zeros_like(self.w), torch.zeros_like(self.b)
+        self.wq = to_bf16_device(w, dev)
+        assert self.w.numel() == lib().darc_unet_num_weights()
+        assert self.b.numel() == lib().darc_unet_num_biases()
+        self.state = L.DarcUnetTrain(*[t.data_ptr() for t in (self.w, self.b, self.mw, self.sw,
+                                                             self.mb, self.sb, self.wq, self.dw,
+                                                             self.db)], 0)
+        net._packed = (self.wq, self.b)
+
+    def _ws(self, images):
+        n, d0, d1, d2 = _images("images", images)
+        return _workspace(lib().darc_unet_train_ws_bytes(n, d0, d1, d2), images.device)
+
+    def step(self, atlas: torch.Tensor, images: torch.Tensor, targets: torch.Tensor) -> torch.Tensor:
+        """One Adam step; returns the loss before it (FP64 device scalar)."""
+        n, d0, d1, d2 = _images("images", images)
+        _field("targets", targets)
+        loss = torch.zeros(1, dtype=torch.float64, device=images.device)
+        ws = self._ws(images)
+        _call("darc_unet_train_step", ctypes.byref(self.state), _p(atlas), _p(images),
+              _p(targets), self.lr, self.beta1, self.beta2, self.eps, _p(loss), n, d0, d1, d2,
+              _p(ws), ws.numel(), _stream())
+        return loss
+
+    def gradients(self, atlas: torch.Tensor, images: torch.Tensor, targets: torch.Tensor):
+        """(loss, [(dw [cout][cin][3][3][3], db [cout]) per layer]) at the current
+        weights, on the host."""
+        n, d0, d1, d2 = _images("images", images)
+        loss = torch.zeros(1, dtype=torch.float64, device=images.device)
+        ws = self._ws(images)
+        _call("darc_unet_backward", _p(self.wq), _p(self.w), _p(self.b), _p(atlas), _p(images),
+              _p(targets), _p(self.dw), _p(self.db), _p(loss), None, n, d0, d1, d2, _p(ws),
+              ws.numel(), _stream())
+        dw, db = self.dw.cpu().numpy(), self.db.cpu().numpy()
+        out, wo, bo = [], 0, 0
+        for cin, cout, _, _ in LAYERS:
+            kpad = lib().darc_conv3d_kpad((cin + 7) // 8 * 8, 3)
+            out.append((unpack_weights(dw[wo:wo + cout * kpad].reshape(cout, kpad), cin),
+                        db[bo:bo + cout]))
+            wo += cout * kpad
+            bo += cout
+        return float(loss.item()), out

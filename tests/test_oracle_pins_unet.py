@@ -67,3 +67,57 @@ def test_nearest_doubling_and_shapes():
         2 * 27 * ci * co * 96 * 112 * 96 / 8 ** lev for ci, co, lev in
         [(2, 16, 0), (16, 32, 1), (32, 64, 2), (64, 128, 3), (192, 64, 2), (96, 32, 1),
          (48, 16, 0), (16, 3, 0)]))
+
+
+def _torch_net(params):
+    import torch.nn.functional as F
+
+    tp = {k: (torch.from_numpy(w).requires_grad_(True), torch.from_numpy(b).requires_grad_(True))
+          for k, (w, b) in params.items()}
+
+    def fwd(a, i):
+        act = lambda x: F.leaky_relu(x, U.SLOPE)
+        conv = lambda x, k, s=1: F.conv3d(x, tp[k][0], tp[k][1], stride=s, padding=1)
+        up = lambda x: F.interpolate(x, scale_factor=2, mode="nearest")
+        x = torch.stack([a, i])[None]
+        e0 = act(conv(x, "e0"))
+        e1 = act(conv(e0, "e1", 2))
+        e2 = act(conv(e1, "e2", 2))
+        e3 = act(conv(e2, "e3", 2))
+        d2 = act(conv(torch.cat([up(e3), e2], 1), "d2"))
+        d1 = act(conv(torch.cat([up(d2), e1], 1), "d1"))
+        d0 = act(conv(torch.cat([up(d1), e0], 1), "d0"))
+        return conv(d0, "out")[0]
+
+    return tp, fwd
+
+
+def test_unrounded_backward_matches_autograd():
+    rng = np.random.default_rng(5)
+    params = {name: (rng.normal(0, 0.3, (co, ci, 3, 3, 3)), rng.normal(0, 0.05, co))
+              for name, ci, co, _, _ in U.layer_specs()}
+    dims = (8, 8, 16)
+    atlas = rng.uniform(size=dims)
+    imgs = rng.uniform(size=(2,) + dims)
+    tgt = rng.normal(0, 0.1, (2, 3) + dims)
+    loss, grads = U.backward(params, atlas, imgs, tgt, rounded=False)
+    tp, fwd = _torch_net(params)
+    tl = sum(((fwd(torch.from_numpy(atlas), torch.from_numpy(imgs[i])) - torch.from_numpy(tgt[i])) ** 2).sum()
+             for i in range(2)) / tgt.size
+    tl.backward()
+    assert loss == pytest.approx(float(tl), rel=1e-12)
+    for name, (w, b) in tp.items():
+        assert np.abs(grads[name][0] - w.grad.numpy()).max() <= 1e-10 * np.abs(w.grad.numpy()).max()
+        assert np.abs(grads[name][1] - b.grad.numpy()).max() <= 1e-10 * np.abs(b.grad.numpy()).max() + 1e-15
+
+
+def test_input_gradient_of_strided_conv_is_the_adjoint():
+    rng = np.random.default_rng(6)
+    x = rng.normal(size=(3, 6, 8, 4))
+    w = rng.normal(size=(5, 3, 3, 3, 3))
+    for s in (1, 2):
+        y = U.conv3d(x, w, np.zeros(5), s)
+        dz = rng.normal(size=y.shape)
+        dx = U.conv3d_input_grad(dz, w, x.shape[1:], s)
+        # <conv(x), dz> = <x, conv^T(dz)>
+        assert float((y * dz).sum()) == pytest.approx(float((x * dx).sum()), rel=1e-12)

@@ -743,13 +743,17 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       ok[j] = puse[j] && pin[j] && p >= 0 && p < g.d0;
-      float u0 = vu[j][0], u1 = vu[j][1], u2 = vu[j][2];
-      if (FIRST) {
-        u0 *= scale;
-        u1 *= scale;
-        u2 *= scale;
+      bc[j] = BorderCell{};
+      // lanes without a halo voxel (all of waves 2 and 3) skip the halo cell
+      if (puse[j]) {
+        float u0 = vu[j][0], u1 = vu[j][1], u2 = vu[j][2];
+        if (FIRST) {
+          u0 *= scale;
+          u1 *= scale;
+          u2 *= scale;
+        }
+        bc[j] = border_cell(g, min(max(p, 0), g.d0 - 1), py[j], px[j], u0, u1, u2);
       }
-      bc[j] = border_cell(g, min(max(p, 0), g.d0 - 1), py[j], px[j], u0, u1, u2);
     }
   };
   // bin one source into its cell (plane bc.i0, which must be the plane being filled)

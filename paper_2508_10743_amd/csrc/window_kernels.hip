@@ -218,29 +218,51 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
   }
   double racc = 0.0;
   const int nplanes = (tl.z1 - tl.z0) + 2 * R;
+  // the next plane's four factors are loaded into registers while the
+  // current plane is summed
+  constexpr int NE = (HY * HX + kNT - 1) / kNT;
+  int eoff[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int e = tid + k * kNT;
+    const int hy = e / HX, hx = e - hy * HX;
+    const int y = tl.yb - R + hy, x = tl.xb - R + hx;
+    eoff[k] = (e < HY * HX && y >= 0 && y < g.d1 && x >= 0 && x < g.d2) ? y * g.d2 + x : -1;
+  }
+  float pre[NE][4];
+  auto load_plane = [&](int p) {
+    const int zz = tl.z0 - R + p;
+    const bool zin = (zz >= 0) && (zz < g.d0);
+#pragma unroll
+    for (int k = 0; k < NE; ++k) {
+      pre[k][0] = pre[k][1] = pre[k][2] = pre[k][3] = 0.0f;
+      if (zin && eoff[k] >= 0) {
+        const int idx = zz * g.plane + eoff[k];
+        pre[k][0] = F[idx];
+        pre[k][1] = F[g.V + idx];
+        pre[k][2] = F[2 * g.V + idx];
+        pre[k][3] = F[3 * g.V + idx];
+      }
+    }
+  };
+  load_plane(0);
   for (int base = 0; base < nplanes; base += W) {
 #pragma unroll
     for (int j = 0; j < W; ++j) {
       const int p = base + j;
       if (p < nplanes) {
         const int zz = tl.z0 - R + p;
-        const bool zin = (zz >= 0) && (zz < g.d0);
-        for (int e = tid; e < HY * HX; e += kNT) {
-          const int hy = e / HX, hx = e - hy * HX;
-          const int y = tl.yb - R + hy, x = tl.xb - R + hx;
-          double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-          if (zin && y >= 0 && y < g.d1 && x >= 0 && x < g.d2) {
-            const int idx = (zz * g.d1 + y) * g.d2 + x;
-            v0 = F[idx];
-            v1 = F[g.V + idx];
-            v2 = F[2 * g.V + idx];
-            v3 = F[3 * g.V + idx];
+#pragma unroll
+        for (int k = 0; k < NE; ++k) {
+          const int e = tid + k * kNT;
+          if (e < HY * HX) {
+            sIn[0][e] = pre[k][0];
+            sIn[1][e] = pre[k][1];
+            sIn[2][e] = pre[k][2];
+            sIn[3][e] = pre[k][3];
           }
-          sIn[0][e] = v0;
-          sIn[1][e] = v1;
-          sIn[2][e] = v2;
-          sIn[3][e] = v3;
         }
+        if (p + 1 < nplanes) load_plane(p + 1);
         __syncthreads();
         // row sums along x, two neighbouring outputs per thread (sliding)
         for (int e = tid; e < HY * (kTX / 2); e += kNT) {
@@ -333,19 +355,36 @@ __global__ __launch_bounds__(kNT) void k_gauss(const float* __restrict__ in,
 #pragma unroll
   for (int j = 0; j < W2; ++j) ring[j] = 0.0f;
   const int nplanes = (tl.z1 - tl.z0) + 2 * R;
+  // the next plane's staged values are loaded into registers while the
+  // current plane is filtered
+  constexpr int NE = (HY * HX + kNT - 1) / kNT;
+  int eoff[NE];
+#pragma unroll
+  for (int k = 0; k < NE; ++k) {
+    const int e = tid + k * kNT;
+    const int hy = e / HX, hx = e - hy * HX;
+    const int y = min(max(tl.yb - R + hy, 0), g.d1 - 1);
+    const int x = min(max(tl.xb - R + hx, 0), g.d2 - 1);
+    eoff[k] = y * g.d2 + x;
+  }
+  float pre[NE];
+  auto load_plane = [&](int p) {
+    const int zc = min(max(tl.z0 - R + p, 0), g.d0 - 1);
+#pragma unroll
+    for (int k = 0; k < NE; ++k)
+      if (tid + k * kNT < HY * HX) pre[k] = src[zc * g.plane + eoff[k]];
+  };
+  load_plane(0);
   for (int base = 0; base < nplanes; base += W2) {
 #pragma unroll
     for (int j = 0; j < W2; ++j) {
       const int p = base + j;
       if (p < nplanes) {
         const int zz = tl.z0 - R + p;
-        const int zc = min(max(zz, 0), g.d0 - 1);
-        for (int e = tid; e < HY * HX; e += kNT) {
-          const int hy = e / HX, hx = e - hy * HX;
-          const int y = min(max(tl.yb - R + hy, 0), g.d1 - 1);
-          const int x = min(max(tl.xb - R + hx, 0), g.d2 - 1);
-          sIn[e] = src[(zc * g.d1 + y) * g.d2 + x];
-        }
+#pragma unroll
+        for (int k = 0; k < NE; ++k)
+          if (tid + k * kNT < HY * HX) sIn[tid + k * kNT] = pre[k];
+        if (p + 1 < nplanes) load_plane(p + 1);
         __syncthreads();
         for (int e = tid; e < HY * kTX; e += kNT) {
           const int hy = e / kTX, cx = e - hy * kTX;

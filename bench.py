@@ -160,7 +160,37 @@ def time_extras(D, cohort, w, reps=3):
     res["unet_train_step_2"] = {"ms": round(ms, 3), "GFLOP": round(flop2 / 1e9, 1),
                                 "TFLOP/s": round(flop2 / (ms * 1e-3) / 1e12, 1),
                                 "frac_bf16_peak": round(flop2 / (ms * 1e-3) / BF16_PEAK_FLOPS, 4)}
+    res["warm_start"] = warm_start_trial(dev=imgs.device)
     return res
+
+
+def warm_start_trial(dev, n_train=64, n_test=8, epochs=10):
+    """Time-to-loss of the learned warm start on 4 x 32^3 blob cohorts:
+    train the U-Net on DARC's velocities (20 sweeps of 20 steps) for n_train
+    cohorts, then on n_test held-out cohorts run the C1 schedule (10 sweeps
+    of 5 steps) from v = 0 and from the network's velocities, and count the
+    sweeps until the group loss is within 0.5 % of plain DARC's final one."""
+    from synthetic.cohorts import WORKLOADS
+
+    from paper_2508_10743_amd import darc as D
+    from paper_2508_10743_amd import warmstart as WS
+
+    w = WORKLOADS["blobs-4x32^3-mse"]
+    t0 = time.perf_counter()
+    train = WS.make_triples(w, range(2000, 2000 + n_train), D.SweepParams(k2=20), 20, dev)
+    t1 = time.perf_counter()
+    net, hist = WS.train(train, epochs=epochs, lr=1e-3)
+    torch_sync = __import__("torch").cuda.synchronize
+    torch_sync()
+    t2 = time.perf_counter()
+    r = WS.evaluate(net, w, range(3000, 3000 + n_test), D.SweepParams(k2=5), 10, dev)
+    return {"train_cohorts": n_train, "epochs": epochs, "triples_s": round(t1 - t0, 2),
+            "train_s": round(t2 - t1, 2), "train_loss_first_last": [round(hist[0], 5),
+                                                                   round(hist[-1], 5)],
+            "sweeps_to_plain_final": {"plain": r["plain_sweeps"], "warm": r["warm_sweeps"]},
+            "seconds_to_plain_final": {"plain": round(r["plain_s"], 4),
+                                       "warm": round(r["warm_s"], 4)},
+            "loss_after_1_sweep": {"plain": r["plain_first"], "warm": r["warm_first"]}}
 
 
 def cpu_baseline(w, seconds_hint=True):

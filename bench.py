@@ -243,6 +243,8 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="subjects per launch (0 = all)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
+    ap.add_argument("--graph", action="store_true",
+                    help="capture one sweep in a HIP graph and time its replays")
     ap.add_argument("--extras", action="store_true",
                     help="also time the method's other branches (median and stochastic atlas, "
                          "one-shot segmentation, pyramid resampling) on the same cohort")
@@ -272,7 +274,7 @@ def main():
     params = D.SweepParams(metric=w.metric, win=w.win, ncc_eps=w.ncc_eps, lam=w.lam,
                            smooth_sigma=w.smooth_sigma, n_sq=w.n_sq, k2=w.k2, lr=w.lr,
                            beta1=w.beta1, beta2=w.beta2, adam_eps=w.adam_eps, batch=args.batch)
-    cohort = D.Cohort(images, params)
+    cohort = D.Cohort(images, params, device_step=args.graph)
     torch.cuda.synchronize()
     if args.calib_copy:
         a = torch.full((1 << 28,), 1.0, dtype=torch.float32, device=dev)
@@ -287,14 +289,23 @@ def main():
         print(f"# warmup sweep {i + 1}/{args.warmup}: F = {cohort.group_loss():.6f}",
               file=sys.stderr, flush=True)
 
-    profile = not args.no_profile
+    # per-kernel events cannot be recorded inside a captured graph
+    profile = not args.no_profile and not args.graph
     if profile:
         D.profile_reset()
         D.profile_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        cohort.sweep()
+    if args.graph:
+        # one sweep captured into a HIP graph, replayed per timed step
+        graph = cohort.capture()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+    else:
+        for _ in range(args.steps):
+            cohort.sweep()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kernels = {}

@@ -63,6 +63,29 @@ MarchGeom make_march(const Geom& g, int nchan, int halo) {
   return mg;
 }
 
+// Window sums along y of NQ row-sum planes sr [NQ][HY][kTX] into
+// sc [NQ][kTY][kTX]: one thread per (quantity, column) slides down the
+// column (add the entering row, drop the leaving one).
+template <int W, int NQ>
+__device__ __forceinline__ void column_sums(const double* __restrict__ sr, double* __restrict__ sc,
+                                            int tid) {
+  constexpr int HY = kTY + W - 1;
+  if (tid < NQ * kTX) {
+    const int c = tid / kTX, cx = tid - c * kTX;
+    const double* col = sr + c * HY * kTX + cx;
+    double* out = sc + c * kTY * kTX + cx;
+    double a = 0.0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) a += col[k * kTX];
+    out[0] = a;
+#pragma unroll
+    for (int r = 1; r < kTY; ++r) {
+      a += col[(r + W - 1) * kTX] - col[(r - 1) * kTX];
+      out[r * kTX] = a;
+    }
+  }
+}
+
 // -------------------------------------------------------------- LNCC forward
 //
 // Window sums S_I, S_J, S_II, S_JJ, S_IJ over the W^3 cube centred at each
@@ -84,6 +107,7 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
   __shared__ __attribute__((aligned(16))) double sI[HY * HX];
   __shared__ __attribute__((aligned(16))) double sJ[HY * HX];
   __shared__ double sr[5][HY * kTX];
+  __shared__ double sc[5][kTY * kTX];
   __shared__ double red[kNT / 64];
   const Geom& g = mg.g;
   const Tile tl = march_tile(mg);
@@ -152,11 +176,11 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
           sr[4][o + 1] = a4 + (in * jn - io * jo);
         }
         __syncthreads();
+        column_sums<W, 5>(&sr[0][0], &sc[0][0], tid);
+        __syncthreads();
 #pragma unroll
         for (int c = 0; c < 5; ++c) {
-          double P = 0.0;
-#pragma unroll
-          for (int k = 0; k < W; ++k) P += sr[c][(ly + k) * kTX + lx];
+          const double P = sc[c][ly * kTX + lx];
           S[c] += P - ring[j][c];
           ring[j][c] = P;
         }
@@ -203,6 +227,7 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
   constexpr int R = W / 2, HX = kTX + 2 * R, HY = kTY + 2 * R;
   __shared__ __attribute__((aligned(16))) double sIn[4][HY * HX];
   __shared__ double sr[4][HY * kTX];
+  __shared__ double sc[4][kTY * kTX];
   __shared__ double red[kNT / 64];
   const Geom& g = mg.g;
   const Tile tl = march_tile(mg);
@@ -287,11 +312,11 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
           }
         }
         __syncthreads();
+        column_sums<W, 4>(&sr[0][0], &sc[0][0], tid);
+        __syncthreads();
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
-          double P = 0.0;
-#pragma unroll
-          for (int k = 0; k < W; ++k) P += sr[c][(ly + k) * kTX + lx];
+          const double P = sc[c][ly * kTX + lx];
           S[c] += P - ring[j][c];
           ring[j][c] = P;
         }

@@ -27,6 +27,7 @@ struct Tile {
   int xb, yb, z0, z1, chan;
 };
 
+template <int TX = kTX, int TY = kTY>
 __device__ __forceinline__ Tile march_tile(const MarchGeom& mg) {
   uint32_t b = xcd_remap(blockIdx.x, mg.total);
   Tile t;
@@ -36,18 +37,18 @@ __device__ __forceinline__ Tile march_tile(const MarchGeom& mg) {
   b /= mg.nty;
   const int zc = static_cast<int>(b % mg.nz);
   t.chan = static_cast<int>(b / mg.nz);
-  t.xb = tx * kTX;
-  t.yb = ty * kTY;
+  t.xb = tx * TX;
+  t.yb = ty * TY;
   t.z0 = zc * mg.tz;
   t.z1 = min(t.z0 + mg.tz, mg.g.d0);
   return t;
 }
 
-MarchGeom make_march(const Geom& g, int nchan, int halo) {
+MarchGeom make_march(const Geom& g, int nchan, int halo, int tx = kTX, int ty = kTY) {
   MarchGeom mg;
   mg.g = g;
-  mg.ntx = (g.d2 + kTX - 1) / kTX;
-  mg.nty = (g.d1 + kTY - 1) / kTY;
+  mg.ntx = (g.d2 + tx - 1) / tx;
+  mg.nty = (g.d1 + ty - 1) / ty;
   // long chunks amortise the 2*halo planes of ramp-up; shorter ones give
   // enough blocks for small cohorts
   int tz = tuned_tz(TUNE_WINDOW, g, nchan);
@@ -365,25 +366,35 @@ struct GaussW {
   float w[17];
 };
 
+// A Gaussian block owns 32 x 32 outputs of a plane: thread (lx, r) holds the
+// kGR consecutive rows r*kGR.. of column lx, so each staged value is reused by
+// four outputs along d1 from registers, and the pass along d2 produces four
+// adjacent outputs from one run of 16-byte LDS reads.
+constexpr int kGX = 32, kGY = 32, kGR = kGY * kGX / kNT;
+
 template <int R>
 __global__ __launch_bounds__(kNT) void k_gauss(const float* __restrict__ in,
                                                float* __restrict__ out, MarchGeom mg, GaussW gw) {
-  constexpr int W2 = 2 * R + 1, HX = kTX + 2 * R, HY = kTY + 2 * R;
-  __shared__ float sIn[HY * HX];
-  __shared__ float sr[HY * kTX];
+  constexpr int W2 = 2 * R + 1, HX = kGX + 2 * R, HY = kGY + 2 * R;
+  constexpr int NV = (4 + 2 * R + 3) / 4;  // 16-byte reads per four d2-outputs
+  constexpr int SX = kGX - 4 + 4 * NV;     // LDS row stride: >= HX, a multiple of 4
+  constexpr int GPR = kGX / 4;             // groups of four outputs per row
+  constexpr int NE = (HY * HX + kNT - 1) / kNT;
+  __shared__ __align__(16) float sIn[HY * SX];
+  __shared__ __align__(16) float sr[HY * kGX];
   const Geom& g = mg.g;
-  const Tile tl = march_tile(mg);
-  const int tid = threadIdx.x, lx = tid % kTX, ly = tid / kTX;
+  const Tile tl = march_tile<kGX, kGY>(mg);
+  const int tid = threadIdx.x, lx = tid % kGX, y0 = (tid / kGX) * kGR;
   const float* src = in + static_cast<size_t>(tl.chan) * g.V;
   float* dst = out + static_cast<size_t>(tl.chan) * g.V;
-  float ring[W2];
+  float ring[W2][kGR];
 #pragma unroll
-  for (int j = 0; j < W2; ++j) ring[j] = 0.0f;
+  for (int j = 0; j < W2; ++j)
+#pragma unroll
+    for (int r = 0; r < kGR; ++r) ring[j][r] = 0.0f;
   const int nplanes = (tl.z1 - tl.z0) + 2 * R;
-  // the next plane's staged values are loaded into registers while the
-  // current plane is filtered
-  constexpr int NE = (HY * HX + kNT - 1) / kNT;
-  int eoff[NE];
+  // staged positions: volume offset (replicated border) and LDS slot
+  int eoff[NE], eslot[NE];
 #pragma unroll
   for (int k = 0; k < NE; ++k) {
     const int e = tid + k * kNT;
@@ -391,7 +402,9 @@ __global__ __launch_bounds__(kNT) void k_gauss(const float* __restrict__ in,
     const int y = min(max(tl.yb - R + hy, 0), g.d1 - 1);
     const int x = min(max(tl.xb - R + hx, 0), g.d2 - 1);
     eoff[k] = y * g.d2 + x;
+    eslot[k] = hy * SX + hx;
   }
+  // the next plane is loaded into registers while the current one is filtered
   float pre[NE];
   auto load_plane = [&](int p) {
     const int zc = min(max(tl.z0 - R + p, 0), g.d0 - 1);
@@ -400,40 +413,65 @@ __global__ __launch_bounds__(kNT) void k_gauss(const float* __restrict__ in,
       if (tid + k * kNT < HY * HX) pre[k] = src[zc * g.plane + eoff[k]];
   };
   load_plane(0);
+  const int x = tl.xb + lx;
   for (int base = 0; base < nplanes; base += W2) {
 #pragma unroll
     for (int j = 0; j < W2; ++j) {
       const int p = base + j;
       if (p < nplanes) {
-        const int zz = tl.z0 - R + p;
 #pragma unroll
         for (int k = 0; k < NE; ++k)
-          if (tid + k * kNT < HY * HX) sIn[tid + k * kNT] = pre[k];
+          if (tid + k * kNT < HY * HX) sIn[eslot[k]] = pre[k];
         if (p + 1 < nplanes) load_plane(p + 1);
         __syncthreads();
-        for (int e = tid; e < HY * kTX; e += kNT) {
-          const int hy = e / kTX, cx = e - hy * kTX;
+        // along d2: four adjacent outputs per work item
+        for (int e = tid; e < HY * GPR; e += kNT) {
+          const int hy = e / GPR, x0 = (e - hy * GPR) * 4;
+          const float4* row = reinterpret_cast<const float4*>(sIn + hy * SX + x0);
+          float t[4 * NV];
+#pragma unroll
+          for (int q = 0; q < NV; ++q) {
+            const float4 a = row[q];
+            t[4 * q] = a.x;
+            t[4 * q + 1] = a.y;
+            t[4 * q + 2] = a.z;
+            t[4 * q + 3] = a.w;
+          }
+          float o[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < W2; ++k) a += gw.w[k] * t[i + k];
+            o[i] = a;
+          }
+          *reinterpret_cast<float4*>(sr + hy * kGX + x0) = make_float4(o[0], o[1], o[2], o[3]);
+        }
+        __syncthreads();
+        // along d1 from one column run in registers, then along d0 from the ring
+        float c[kGR + 2 * R];
+#pragma unroll
+        for (int i = 0; i < kGR + 2 * R; ++i) c[i] = sr[(y0 + i) * kGX + lx];
+#pragma unroll
+        for (int r = 0; r < kGR; ++r) {
           float a = 0.0f;
 #pragma unroll
-          for (int k = 0; k < W2; ++k) a += gw.w[k] * sIn[hy * HX + cx + k];
-          sr[e] = a;
+          for (int k = 0; k < W2; ++k) a += gw.w[k] * c[r + k];
+          ring[j][r] = a;
         }
-        __syncthreads();
-        float P = 0.0f;
+        if (p >= 2 * R && x < g.d2) {
+          const int zo = tl.z0 - 2 * R + p;
 #pragma unroll
-        for (int k = 0; k < W2; ++k) P += gw.w[k] * sr[(ly + k) * kTX + lx];
-        ring[j] = P;
-        if (p >= 2 * R) {
-          const int zo = zz - R;
-          const int y = tl.yb + ly, x = tl.xb + lx;
-          if (y < g.d1 && x < g.d2) {
-            float o = 0.0f;
+          for (int r = 0; r < kGR; ++r) {
+            const int y = tl.yb + y0 + r;
+            if (y < g.d1) {
+              float o = 0.0f;
 #pragma unroll
-            for (int k = 0; k < W2; ++k) o += gw.w[k] * ring[(j + 1 + k) % W2];
-            dst[(zo * g.d1 + y) * g.d2 + x] = o;
+              for (int k = 0; k < W2; ++k) o += gw.w[k] * ring[(j + 1 + k) % W2][r];
+              dst[(zo * g.d1 + y) * g.d2 + x] = o;
+            }
           }
         }
-        __syncthreads();
       }
     }
   }
@@ -498,7 +536,7 @@ bool lncc_bwd_dispatch(const float* fields, const float* w, const float* atlas, 
 template <int R>
 void gauss_r(const float* in, float* out, const GaussW& gw, const Geom& g, int nchan,
              hipStream_t st) {
-  const MarchGeom mg = make_march(g, nchan, R);
+  const MarchGeom mg = make_march(g, nchan, R, kGX, kGY);
   hipLaunchKernelGGL((k_gauss<R>), dim3(mg.total), dim3(kNT), 0, st, in, out, mg, gw);
 }
 

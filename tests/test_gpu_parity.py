@@ -213,8 +213,12 @@ def test_sim_identical_images(dev):
 
 
 @pytest.mark.parametrize("sigma", [0.5, 1.5, 2.5])
-def test_gauss_smooth(dev, sigma):
-    x = random_volume(115, (2, 3) + DIMS, -1.0, 1.0)
+@pytest.mark.parametrize("dims", [DIMS, (11, 70, 45), (5, 33, 3)], ids=["base", "tall", "thin"])
+def test_gauss_smooth(dev, sigma, dims):
+    """The smoother's blocks own 32 x 32 tiles of a plane: the extra shapes
+    give several tiles along d1 with a ragged tail, and a plane narrower
+    than the radius."""
+    x = random_volume(115, (2, 3) + dims, -1.0, 1.0)
     out = h(D.gauss_smooth(g(x, dev), sigma))
     for i in range(2):
         assert rel_linf(out[i], O.gauss_smooth(x[i], sigma)) <= TOL_WARP
@@ -315,6 +319,15 @@ def _check_run(imgs, p_o, p_d, sweeps, dev):
 def test_sweep_matches_oracle(dev, metric, sigma, lam, center, batch):
     imgs = blobs(3, (12, 10, 40), 124)
     kw = dict(metric=metric, win=5, lam=lam, smooth_sigma=sigma, k2=2, center_mode=center)
+    _check_run(imgs, O.SweepParams(**kw), D.SweepParams(batch=batch, **kw), 2, dev)
+
+
+@pytest.mark.parametrize("k2,batch", [(3, 2), (1, 0)])
+def test_smoothed_sweep_with_odd_inner_steps(dev, k2, batch):
+    """Smoothing after each Adam step with an odd number of inner steps, with
+    and without subject batching."""
+    imgs = blobs(3, (12, 10, 40), 127)
+    kw = dict(metric="mse", lam=0.01, smooth_sigma=1.0, k2=k2)
     _check_run(imgs, O.SweepParams(**kw), D.SweepParams(batch=batch, **kw), 2, dev)
 
 

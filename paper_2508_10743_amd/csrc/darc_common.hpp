@@ -227,6 +227,16 @@ __device__ __forceinline__ BorderCell border_cell(const Geom& g, int x0, int x1,
   return b;
 }
 
+// Element access at a 32-bit index from a wave-uniform base pointer: volumes
+// are capped at 2^29 voxels, so the byte offset of one component fits in 32
+// bits and the access needs no per-lane 64-bit address arithmetic.
+__device__ __forceinline__ float ld_at(const float* __restrict__ base, uint32_t i) {
+  return *reinterpret_cast<const float*>(reinterpret_cast<const char*>(base) + (i << 2));
+}
+__device__ __forceinline__ void st_at(float* __restrict__ base, uint32_t i, float v) {
+  *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (i << 2)) = v;
+}
+
 // The 8 corners of one field component at a border cell (always in range).
 __device__ __forceinline__ void corners_border(const float* __restrict__ f, const Geom& g,
                                                int base, float (&c)[8]) {

@@ -698,17 +698,20 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
     poff[j] = min(max(py[j], 0), g.d1 - 1) * g.d2 + min(max(px[j], 0), g.d2 - 1);
   }
 
+  // component base pointers (uniform across the block)
+  const float* fc[3] = {f, f + g.V, f + 2 * static_cast<size_t>(g.V)};
+  const float* gc[3] = {gi, gi + g.V, gi + 2 * static_cast<size_t>(g.V)};
   float pu[2][3], pg[2][3];  // the plane being prefetched
   auto load_plane = [&](int z) {
     const int zc = min(max(z, 0), g.d0 - 1);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
       if (puse[j]) {
-        const int lin = zc * g.plane + poff[j];
+        const uint32_t lin = static_cast<uint32_t>(zc * g.plane + poff[j]);
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          pu[j][c] = f[c * g.V + lin];
-          pg[j][c] = gi[c * g.V + lin];
+          pu[j][c] = ld_at(fc[c], lin);
+          pg[j][c] = ld_at(gc[c], lin);
         }
       }
   };
@@ -857,7 +860,9 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
       const int c0 = bc.i0 - z + 1, c1 = bc.i1 - id.oy + 1, c2 = bc.i2 - id.ox + 1;
       const bool in_ring =
           c0 >= 0 && c0 <= 1 && c1 >= 0 && c1 + 1 < MHY && c2 >= 0 && c2 + 1 < MHX;
-      float jt0 = 0.0f, jt1 = 0.0f, jt2 = 0.0f;
+      // J^T g = grad of the trilinear interpolant of g . u at the sample:
+      // the corner values of g . u first, then one derivative evaluation
+      float h[8];
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
         float cv[8];
@@ -873,16 +878,15 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
           cv[6] = uring[sb][c][pb + MHX];
           cv[7] = uring[sb][c][pb + MHX + 1];
         } else {
-          corners_border(f + c * g.V, g, bc.base, cv);
+          corners_border(fc[c], g, bc.base, cv);
         }
-        const Tri t = tri_eval(cv, bc.t0, bc.t1, bc.t2);
-        jt0 += t.d0 * cg[0][c];
-        jt1 += t.d1 * cg[0][c];
-        jt2 += t.d2 * cg[0][c];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) h[k] = c == 0 ? cg[0][0] * cv[k] : h[k] + cg[0][c] * cv[k];
       }
-      r0 = cg[0][0] + (bc.k0 ? 0.0f : jt0 * js);
-      r1 = cg[0][1] + (bc.k1 ? 0.0f : jt1 * js);
-      r2 = cg[0][2] + (bc.k2 ? 0.0f : jt2 * js);
+      const Tri t = tri_eval(h, bc.t0, bc.t1, bc.t2);
+      r0 = cg[0][0] + (bc.k0 ? 0.0f : t.d0 * js);
+      r1 = cg[0][1] + (bc.k1 ? 0.0f : t.d1 * js);
+      r2 = cg[0][2] + (bc.k2 ? 0.0f : t.d2 * js);
     }
     __syncthreads();
     // (v) gather from cell planes z-1 (a = 1) and z (a = 0); empty slots hold zeros
@@ -912,10 +916,10 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
       r0 += ov[threadIdx.x];
       r1 += ov[ENT + threadIdx.x];
       r2 += ov[2 * ENT + threadIdx.x];
-      const int lin = z * g.plane + py[0] * g.d2 + px[0];
-      go[lin] = r0 * oscale;
-      go[g.V + lin] = r1 * oscale;
-      go[2 * g.V + lin] = r2 * oscale;
+      const uint32_t lin = static_cast<uint32_t>(z * g.plane + py[0] * g.d2 + px[0]);
+      st_at(go, lin, r0 * oscale);
+      st_at(go + g.V, lin, r1 * oscale);
+      st_at(go + 2 * static_cast<size_t>(g.V), lin, r2 * oscale);
     }
     // (vi) the plane-(z+1) sources become the next iteration's plane-z sources
 #pragma unroll

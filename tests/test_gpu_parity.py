@@ -331,6 +331,28 @@ def test_smoothed_sweep_with_odd_inner_steps(dev, k2, batch):
     _check_run(imgs, O.SweepParams(**kw), D.SweepParams(batch=batch, **kw), 2, dev)
 
 
+@pytest.mark.parametrize("n_sq,amp", [(1, 3.0), (7, 2.5)], ids=["tiled-first-step", "marching"])
+def test_smoothed_sweep_from_given_velocities(dev, n_sq, amp):
+    """A smoothed sweep from nonzero velocities.  With one squaring step and
+    |v| up to 3 voxels the adjoint's reach exceeds one voxel (the tiled
+    adjoint); with seven it stays under one (the marching adjoint)."""
+    dims = (12, 10, 40)
+    imgs = blobs(3, dims, 128)
+    v0 = random_velocity(129, 3, dims, amp, corr_len=3.0)
+    kw = dict(metric="mse", lam=0.01, smooth_sigma=1.0, k2=2, n_sq=n_sq)
+    z = np.zeros(v0.shape)
+    r = O.sweep(imgs.astype(np.float64), v0.astype(np.float64), z, z, 0, O.initial_atlas(imgs),
+                O.SweepParams(**kw))
+    c = D.Cohort(g(imgs, dev), D.SweepParams(batch=2, **kw), v0=g(v0, dev))
+    losses = h(c.sweep())
+    inner = r["inner_losses"].ravel()
+    assert np.abs(losses[:-1] - inner).max() <= TOL_LOSS * np.abs(inner).max()
+    assert rel_l2(h(c.v), r["v"]) <= TOL_GRAD
+    assert rel_l2(h(c.m), r["m"]) <= TOL_GRAD
+    assert rel_l2(h(c.s), r["s"]) <= TOL_GRAD
+    assert rel_linf(h(c.atlas), r["atlas"]) <= TOL_WARP
+
+
 def test_blobs_4x32_mse_two_sweeps(dev):
     """The 4-subject 32^3 MSE workload (lambda 0.01, 7 squarings, K2 = 5)."""
     w = WORKLOADS["blobs-4x32^3-mse"]

@@ -701,19 +701,22 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
   // component base pointers (uniform across the block)
   const float* fc[3] = {f, f + g.V, f + 2 * static_cast<size_t>(g.V)};
   const float* gc[3] = {gi, gi + g.V, gi + 2 * static_cast<size_t>(g.V)};
-  float pu[2][3], pg[2][3];  // the plane being prefetched
+  // The plane being prefetched.  Every lane loads (lanes without a halo
+  // voxel from a clamped, valid position) and planes past the chunk are
+  // loaded clamped too: a conditional load would make the compiler merge
+  // register values right after it and so wait for it at once.
+  float pu[2][3], pg[2][3];
   auto load_plane = [&](int z) {
     const int zc = min(max(z, 0), g.d0 - 1);
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
-      if (puse[j]) {
-        const uint32_t lin = static_cast<uint32_t>(zc * g.plane + poff[j]);
+    for (int j = 0; j < 2; ++j) {
+      const uint32_t lin = static_cast<uint32_t>(zc * g.plane + poff[j]);
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          pu[j][c] = ld_at(fc[c], lin);
-          pg[j][c] = ld_at(gc[c], lin);
-        }
+      for (int c = 0; c < 3; ++c) {
+        pu[j][c] = ld_at(fc[c], lin);
+        pg[j][c] = ld_at(gc[c], lin);
       }
+    }
   };
   auto store_u = [&](int z) {
     const int su = (z + 3) % 3;
@@ -844,7 +847,7 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
         qg[j][c] = pg[j][c];
       }
     __syncthreads();
-    if (z + 2 <= id.z1) load_plane(z + 2);
+    load_plane(z + 2);
     // (ii) cells of the plane-(z+1) sources
     cells_of(z + 1, qu, nb, nok);
     // (iii) fill cell plane z

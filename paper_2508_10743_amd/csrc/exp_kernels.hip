@@ -244,16 +244,17 @@ __global__ __launch_bounds__(ENT) void k_exp_fwd(const float* __restrict__ src,
   float* o = dst + off;
   const int lx = threadIdx.x % ETX, ly = threadIdx.x / ETX;
   const HaloPos hp = halo_pos(g, id.oy, id.ox);
+  // the next plane in registers (planes past the chunk are loaded clamped)
+  const float* fc[3] = {f, f + g.V, f + 2 * static_cast<size_t>(g.V)};
   float pre[MNJ][3];
   auto load_plane = [&](int z) {
     const int zc = min(max(z, 0), g.d0 - 1);
 #pragma unroll
     for (int j = 0; j < MNJ; ++j)
       if (hp.use[j]) {
-        const int lin = zc * g.plane + hp.off[j];
-        pre[j][0] = f[lin];
-        pre[j][1] = f[g.V + lin];
-        pre[j][2] = f[2 * g.V + lin];
+        const uint32_t lin = static_cast<uint32_t>(zc * g.plane + hp.off[j]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c) pre[j][c] = ld_at(fc[c], lin);
       }
   };
   auto store_plane = [&](int z) {
@@ -279,7 +280,7 @@ __global__ __launch_bounds__(ENT) void k_exp_fwd(const float* __restrict__ src,
   for (int z = id.z0; z < id.z1; ++z) {
     store_plane(z + 1);
     __syncthreads();
-    if (z + 2 <= id.z1) load_plane(z + 2);
+    load_plane(z + 2);
     if (colv) {
       const int sz = z % 3;
       float u0 = ring[sz][0][own], u1 = ring[sz][1][own], u2 = ring[sz][2][own];
@@ -311,7 +312,7 @@ __global__ __launch_bounds__(ENT) void k_exp_fwd(const float* __restrict__ src,
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
           float cv[8];
-          corners_border(f + c * g.V, g, bc.base, cv);
+          corners_border(fc[c], g, bc.base, cv);
           r[c] = tri_value(cv, bc.t0, bc.t1, bc.t2);
         }
       }
@@ -320,10 +321,10 @@ __global__ __launch_bounds__(ENT) void k_exp_fwd(const float* __restrict__ src,
         r[1] *= scale;
         r[2] *= scale;
       }
-      const int lin = z * g.plane + x1 * g.d2 + x2;
-      o[lin] = u0 + r[0];
-      o[g.V + lin] = u1 + r[1];
-      o[2 * g.V + lin] = u2 + r[2];
+      const uint32_t lin = static_cast<uint32_t>(z * g.plane + x1 * g.d2 + x2);
+      st_at(o, lin, u0 + r[0]);
+      st_at(o + g.V, lin, u1 + r[1]);
+      st_at(o + 2 * static_cast<size_t>(g.V), lin, u2 + r[2]);
       if (REC) {
         mn0 = min(mn0, bc.i0 - z);
         mn1 = min(mn1, bc.i1 - x1);

@@ -702,30 +702,31 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
   // component base pointers (uniform across the block)
   const float* fc[3] = {f, f + g.V, f + 2 * static_cast<size_t>(g.V)};
   const float* gc[3] = {gi, gi + g.V, gi + 2 * static_cast<size_t>(g.V)};
-  // The plane being prefetched.  Every lane loads (lanes without a halo
-  // voxel from a clamped, valid position) and planes past the chunk are
-  // loaded clamped too: a conditional load would make the compiler merge
-  // register values right after it and so wait for it at once.
-  float pu[2][3], pg[2][3];
-  auto load_plane = [&](int z) {
+  // Planes in flight: two register buffers, loaded two planes ahead of use.
+  // Every lane loads (lanes without a halo voxel from a clamped, valid
+  // position) and planes past the chunk are loaded clamped too: a
+  // conditional load would make the compiler merge register values right
+  // after it and so wait for it at once.
+  float pu[2][3], pg[2][3], pu2[2][3], pg2[2][3];
+  auto load_plane = [&](int z, float (&lu)[2][3], float (&lg)[2][3]) {
     const int zc = min(max(z, 0), g.d0 - 1);
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       const uint32_t lin = static_cast<uint32_t>(zc * g.plane + poff[j]);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        pu[j][c] = ld_at(fc[c], lin);
-        pg[j][c] = ld_at(gc[c], lin);
+        lu[j][c] = ld_at(fc[c], lin);
+        lg[j][c] = ld_at(gc[c], lin);
       }
     }
   };
-  auto store_u = [&](int z) {
+  auto store_u = [&](int z, const float (&su_)[2][3]) {
     const int su = (z + 3) % 3;
 #pragma unroll
     for (int j = 0; j < 2; ++j)
       if (puse[j]) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) uring[su][c][pe[j]] = pu[j][c];
+        for (int c = 0; c < 3; ++c) uring[su][c][pe[j]] = su_[j][c];
       }
   };
   auto clear_cells = [&](int cplane) {
@@ -805,12 +806,12 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
   bool cok[2], nok[2];
   float cg[2][3], qu[2][3], qg[2][3];
 
-  // prologue: cell plane z0-1 from the sources of planes z0-1 and z0; plane
-  // z0+1 in flight
+  // prologue: cell plane z0-1 from the sources of planes z0-1 and z0; planes
+  // z0+1 and z0+2 in flight
   clear_cells(id.z0 - 1);
   clear_ovf(id.z0);
-  load_plane(id.z0 - 1);
-  store_u(id.z0 - 1);
+  load_plane(id.z0 - 1, pu, pg);
+  store_u(id.z0 - 1, pu);
 #pragma unroll
   for (int j = 0; j < 2; ++j)
 #pragma unroll
@@ -818,8 +819,8 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
       qu[j][c] = pu[j][c];
       qg[j][c] = pg[j][c];
     }
-  load_plane(id.z0);
-  store_u(id.z0);
+  load_plane(id.z0, pu, pg);
+  store_u(id.z0, pu);
   __syncthreads();
   cells_of(id.z0 - 1, qu, nb, nok);
 #pragma unroll
@@ -832,23 +833,25 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
 #pragma unroll
     for (int c = 0; c < 3; ++c) cg[j][c] = pg[j][c];
   }
-  load_plane(id.z0 + 1);
+  load_plane(id.z0 + 1, pu, pg);
+  load_plane(id.z0 + 2, pu2, pg2);
   __syncthreads();
 
-  for (int z = id.z0; z < id.z1; ++z) {
+  // one plane; (xu, xg) holds plane z+1 on entry and takes plane z+3
+  auto step = [&](int z, float (&xu)[2][3], float (&xg)[2][3]) {
     // (i) clear cell plane z (held z-2) and target plane z+1 (held z-1); stage u of plane z+1
     clear_cells(z);
     clear_ovf(z + 1);
-    store_u(z + 1);
+    store_u(z + 1, xu);
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        qu[j][c] = pu[j][c];
-        qg[j][c] = pg[j][c];
+        qu[j][c] = xu[j][c];
+        qg[j][c] = xg[j][c];
       }
     __syncthreads();
-    load_plane(z + 2);
+    load_plane(z + 3, xu, xg);
     // (ii) cells of the plane-(z+1) sources
     cells_of(z + 1, qu, nb, nok);
     // (iii) fill cell plane z
@@ -864,30 +867,41 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
       const int c0 = bc.i0 - z + 1, c1 = bc.i1 - id.oy + 1, c2 = bc.i2 - id.ox + 1;
       const bool in_ring =
           c0 >= 0 && c0 <= 1 && c1 >= 0 && c1 + 1 < MHY && c2 >= 0 && c2 + 1 < MHX;
-      // J^T g = grad of the trilinear interpolant of g . u at the sample:
-      // the corner values of g . u first, then one derivative evaluation
-      float h[8];
+      // J^T g = grad of the trilinear interpolant of g . u at the sample.
+      // Corners come from the staged ring; a cell outside it (not reached
+      // while every offset lies in [-1, 0]) reads them from memory.  The
+      // memory path combines three derivative evaluations instead of forming
+      // g . u at the corners first: its arithmetic then cannot be merged with
+      // the ring path's after the branch, which would make the ring path
+      // wait for memory loads (and with them for the planes in flight).
+      Tri t;
+      if (in_ring) {
+        const int sa = (bc.i0 + 3) % 3, sb = (bc.i0 + 4) % 3;
+        const int pb = c1 * MHX + c2;
+        float h[8];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        float cv[8];
-        if (in_ring) {
-          const int sa = (bc.i0 + 3) % 3, sb = (bc.i0 + 4) % 3;
-          const int pb = c1 * MHX + c2;
-          cv[0] = uring[sa][c][pb];
-          cv[1] = uring[sa][c][pb + 1];
-          cv[2] = uring[sa][c][pb + MHX];
-          cv[3] = uring[sa][c][pb + MHX + 1];
-          cv[4] = uring[sb][c][pb];
-          cv[5] = uring[sb][c][pb + 1];
-          cv[6] = uring[sb][c][pb + MHX];
-          cv[7] = uring[sb][c][pb + MHX + 1];
-        } else {
-          corners_border(fc[c], g, bc.base, cv);
+        for (int c = 0; c < 3; ++c) {
+          const float cv[8] = {uring[sa][c][pb],       uring[sa][c][pb + 1],
+                               uring[sa][c][pb + MHX], uring[sa][c][pb + MHX + 1],
+                               uring[sb][c][pb],       uring[sb][c][pb + 1],
+                               uring[sb][c][pb + MHX], uring[sb][c][pb + MHX + 1]};
+#pragma unroll
+          for (int k = 0; k < 8; ++k) h[k] = c == 0 ? cg[0][0] * cv[k] : h[k] + cg[0][c] * cv[k];
         }
+        t = tri_eval(h, bc.t0, bc.t1, bc.t2);
+      } else {
+        t.v = 0.0f;
+        t.d0 = t.d1 = t.d2 = 0.0f;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) h[k] = c == 0 ? cg[0][0] * cv[k] : h[k] + cg[0][c] * cv[k];
+        for (int c = 0; c < 3; ++c) {
+          float cv[8];
+          corners_border(fc[c], g, bc.base, cv);
+          const Tri tc = tri_eval(cv, bc.t0, bc.t1, bc.t2);
+          t.d0 += tc.d0 * cg[0][c];
+          t.d1 += tc.d1 * cg[0][c];
+          t.d2 += tc.d2 * cg[0][c];
+        }
       }
-      const Tri t = tri_eval(h, bc.t0, bc.t1, bc.t2);
       r0 = cg[0][0] + (bc.k0 ? 0.0f : t.d0 * js);
       r1 = cg[0][1] + (bc.k1 ? 0.0f : t.d1 * js);
       r2 = cg[0][2] + (bc.k2 ? 0.0f : t.d2 * js);
@@ -934,6 +948,11 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
       for (int c = 0; c < 3; ++c) cg[j][c] = qg[j][c];
     }
     __syncthreads();
+  };
+  // unrolled by two so that each prefetch buffer keeps its registers
+  for (int z = id.z0; z < id.z1; z += 2) {
+    step(z, pu, pg);
+    if (z + 1 < id.z1) step(z + 1, pu2, pg2);
   }
 }
 

@@ -698,6 +698,9 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
     pin[j] = py[j] >= 0 && py[j] < g.d1 && px[j] >= 0 && px[j] < g.d2;
     poff[j] = min(max(py[j], 0), g.d1 - 1) * g.d2 + min(max(px[j], 0), g.d2 - 1);
   }
+  // lanes without a halo voxel load their own voxel again (a cache line the
+  // wave reads anyway) rather than fetching rows of other tiles
+  if (!puse[1]) poff[1] = poff[0];
 
   // component base pointers (uniform across the block)
   const float* fc[3] = {f, f + g.V, f + 2 * static_cast<size_t>(g.V)};

@@ -244,31 +244,35 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
   }
   double racc = 0.0;
   const int nplanes = (tl.z1 - tl.z0) + 2 * R;
-  // the next plane's four factors are loaded into registers while the
-  // current plane is summed
+  // The next plane's four factors are loaded into registers while the
+  // current plane is summed.  Every load is unconditional, from a clamped
+  // (valid) position, and the zero padding outside the volume is applied
+  // when the values are staged: a load under a branch, or a select right
+  // after it, would make the compiler wait for it at once.
   constexpr int NE = (HY * HX + kNT - 1) / kNT;
   int eoff[NE];
+  bool ein[NE];
 #pragma unroll
   for (int k = 0; k < NE; ++k) {
     const int e = tid + k * kNT;
     const int hy = e / HX, hx = e - hy * HX;
     const int y = tl.yb - R + hy, x = tl.xb - R + hx;
-    eoff[k] = (e < HY * HX && y >= 0 && y < g.d1 && x >= 0 && x < g.d2) ? y * g.d2 + x : -1;
+    ein[k] = e < HY * HX && y >= 0 && y < g.d1 && x >= 0 && x < g.d2;
+    eoff[k] = min(max(y, 0), g.d1 - 1) * g.d2 + min(max(x, 0), g.d2 - 1);
   }
   float pre[NE][4];
+  bool pzin = false;  // the prefetched plane lies inside the volume
   auto load_plane = [&](int p) {
     const int zz = tl.z0 - R + p;
-    const bool zin = (zz >= 0) && (zz < g.d0);
+    pzin = (zz >= 0) && (zz < g.d0);
+    const int zc = min(max(zz, 0), g.d0 - 1);
 #pragma unroll
     for (int k = 0; k < NE; ++k) {
-      pre[k][0] = pre[k][1] = pre[k][2] = pre[k][3] = 0.0f;
-      if (zin && eoff[k] >= 0) {
-        const int idx = zz * g.plane + eoff[k];
-        pre[k][0] = F[idx];
-        pre[k][1] = F[g.V + idx];
-        pre[k][2] = F[2 * g.V + idx];
-        pre[k][3] = F[3 * g.V + idx];
-      }
+      const int idx = zc * g.plane + eoff[k];
+      pre[k][0] = F[idx];
+      pre[k][1] = F[g.V + idx];
+      pre[k][2] = F[2 * g.V + idx];
+      pre[k][3] = F[3 * g.V + idx];
     }
   };
   load_plane(0);
@@ -282,13 +286,29 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
         for (int k = 0; k < NE; ++k) {
           const int e = tid + k * kNT;
           if (e < HY * HX) {
-            sIn[0][e] = pre[k][0];
-            sIn[1][e] = pre[k][1];
-            sIn[2][e] = pre[k][2];
-            sIn[3][e] = pre[k][3];
+            const bool ok = pzin && ein[k];
+            sIn[0][e] = ok ? pre[k][0] : 0.0f;
+            sIn[1][e] = ok ? pre[k][1] : 0.0f;
+            sIn[2][e] = ok ? pre[k][2] : 0.0f;
+            sIn[3][e] = ok ? pre[k][3] : 0.0f;
           }
         }
-        if (p + 1 < nplanes) load_plane(p + 1);
+        // the output voxel's own values, issued before the next plane's
+        // factors so that waiting for them does not wait for those too
+        // (clamped indices: always valid, used only for live outputs)
+        const int zo = zz - R;
+        const int y = tl.yb + ly, x = tl.xb + lx;
+        const int idx = (min(max(zo, 0), g.d0 - 1) * g.d1 + min(y, g.d1 - 1)) * g.d2 +
+                        min(x, g.d2 - 1);
+        const float eJ = atlas[tl.chan * astr + idx];
+        const float eI = wimg[tl.chan * wstr + idx];
+        float eu[3] = {0.0f, 0.0f, 0.0f};
+        if (FUSED) {
+          const float* f = u + static_cast<size_t>(tl.chan) * 3 * g.V;
+#pragma unroll
+          for (int c = 0; c < 3; ++c) eu[c] = f[static_cast<size_t>(c) * g.V + idx];
+        }
+        load_plane(p + 1);  // past the chunk: clamped, never staged
         __syncthreads();
         // row sums along x, two neighbouring outputs per thread (sliding)
         for (int e = tid; e < HY * (kTX / 2); e += kNT) {
@@ -321,13 +341,10 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
           S[c] += P - ring[j][c];
           ring[j][c] = P;
         }
-        const int zo = zz - R;
-        const int y = tl.yb + ly, x = tl.xb + lx;
         if (zo >= tl.z0 && y < g.d1 && x < g.d2) {
-          const int idx = (zo * g.d1 + y) * g.d2 + x;
           const size_t vidx = static_cast<size_t>(tl.chan) * g.V + idx;
-          const double Jc = atlas[tl.chan * astr + idx];
-          const double Ic = wimg[tl.chan * wstr + idx];
+          const double Jc = eJ;
+          const double Ic = eI;
           const double gI = neg_inv_v * (Jc * S[0] - S[1] - Ic * S[2] + S[3]);
           if (!FUSED) {
             gw[vidx] = static_cast<float>(gI);
@@ -335,7 +352,7 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
             const size_t off = static_cast<size_t>(tl.chan) * 3 * g.V;
             const float* f = u + off;
             const float* Io = img + static_cast<size_t>(tl.chan) * g.V;
-            const Tri t = sample_zero(Io, g, zo, y, x, f[idx], f[g.V + idx], f[2 * g.V + idx]);
+            const Tri t = sample_zero(Io, g, zo, y, x, eu[0], eu[1], eu[2]);
             float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f;
             if (rw.on) {
               r0 = reg_at(f, g, idx, zo, y, x, rw, racc);

@@ -270,7 +270,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     print(f"# generating {w.name}", file=sys.stderr, flush=True)
-    images = torch.from_numpy(make_cohort(w)).to(dev)
+    # large cohorts are generated in a process pool (same images), sized to the
+    # CPU share of one GPU
+    workers = min(16, os.cpu_count() or 1) if w.n >= 32 else 1
+    images = torch.from_numpy(make_cohort(w, workers=workers)).to(dev)
     params = D.SweepParams(metric=w.metric, win=w.win, ncc_eps=w.ncc_eps, lam=w.lam,
                            smooth_sigma=w.smooth_sigma, n_sq=w.n_sq, k2=w.k2, lr=w.lr,
                            beta1=w.beta1, beta2=w.beta2, adam_eps=w.adam_eps, batch=args.batch)

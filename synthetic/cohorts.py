@@ -160,19 +160,12 @@ def eval_compartments(dims, y: np.ndarray, edge_sigma: float = 2.0) -> np.ndarra
 # cohorts
 
 
-def make_cohort(w: Workload, n: Optional[int] = None, dims=None, seed: Optional[int] = None):
-    """Return ``images`` ``[n, D0, D1, D2]`` FP32 for workload ``w``.
-
-    ``n``/``dims``/``seed`` override the workload's values (smaller test cases
-    with the same recipe).
-    """
-    n = w.n if n is None else n
-    dims = tuple(w.dims if dims is None else dims)
-    seed = w.seed if seed is None else seed
-    ss = np.random.SeedSequence(seed)
-    template_rng, *subject_ss = [np.random.default_rng(s) for s in ss.spawn(n + 1)]
+def _subject(w: Workload, n: int, dims, seed: int, i: int) -> np.ndarray:
+    """Subject ``i`` of the cohort: its own spawned seed, so that subjects can
+    be generated in any order or process with identical results."""
+    template_ss, *subject_ss = np.random.SeedSequence(seed).spawn(n + 1)
     if w.phantom == "blobs":
-        params = blob_template_params(template_rng, dims)
+        params = blob_template_params(np.random.default_rng(template_ss), dims)
         evaluate = lambda y: eval_blobs(params, y)  # noqa: E731
     elif w.phantom == "brain":
         evaluate = lambda y: eval_nested_ellipsoids(dims, y)  # noqa: E731
@@ -180,14 +173,36 @@ def make_cohort(w: Workload, n: Optional[int] = None, dims=None, seed: Optional[
         evaluate = lambda y: eval_compartments(dims, y)  # noqa: E731
     else:
         raise ValueError(f"unknown phantom {w.phantom!r}")
+    rng = np.random.default_rng(subject_ss[i])
     grid = np.stack(np.meshgrid(*[np.arange(d, dtype=np.float64) for d in dims], indexing="ij"))
+    disp = smooth_random_field(rng, dims, w.max_disp, w.corr_len)
+    img = evaluate(grid + disp)
+    if w.noise_sd > 0:
+        img += rng.normal(0.0, w.noise_sd, size=img.shape)
+    return img.astype(np.float32)
+
+
+def make_cohort(w: Workload, n: Optional[int] = None, dims=None, seed: Optional[int] = None,
+                workers: int = 1):
+    """Return ``images`` ``[n, D0, D1, D2]`` FP32 for workload ``w``.
+
+    ``n``/``dims``/``seed`` override the workload's values (smaller test cases
+    with the same recipe).  ``workers`` > 1 generates subjects in that many
+    processes (same images).
+    """
+    n = w.n if n is None else n
+    dims = tuple(w.dims if dims is None else dims)
+    seed = w.seed if seed is None else seed
     images = np.empty((n,) + dims, dtype=np.float32)
-    for i, rng in enumerate(subject_ss):
-        disp = smooth_random_field(rng, dims, w.max_disp, w.corr_len)
-        img = evaluate(grid + disp)
-        if w.noise_sd > 0:
-            img += rng.normal(0.0, w.noise_sd, size=img.shape)
-        images[i] = img.astype(np.float32)
+    if workers > 1 and n > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(workers, n)) as ex:
+            futs = [ex.submit(_subject, w, n, dims, seed, i) for i in range(n)]
+            for i, f in enumerate(futs):
+                images[i] = f.result()
+    else:
+        for i in range(n):
+            images[i] = _subject(w, n, dims, seed, i)
     return images
 
 

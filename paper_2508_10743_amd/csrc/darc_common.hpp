@@ -107,21 +107,16 @@ __device__ __forceinline__ void cell_zero(int x, float u, int& i, float& t) {
 // [0, D-1] (the sample then does not move with the position).
 __device__ __forceinline__ void cell_border(int x, float u, int D, int& i, float& t,
                                             bool& clamped) {
+  // selects rather than branches: the same result without divergent control
+  // flow in the callers' loops
   const float f = floorf(u);
-  int ii = x + static_cast<int>(f);
-  float tt = u - f;
-  clamped = false;
-  if (ii < 0) {
-    clamped = true;
-    ii = 0;
-    tt = 0.0f;
-  } else if (ii >= D - 1) {
-    clamped = (ii > D - 1) || (tt > 0.0f);
-    ii = D - 2;
-    tt = 1.0f;
-  }
-  i = ii;
-  t = tt;
+  const int ii = x + static_cast<int>(f);
+  const float tt = u - f;
+  const bool lo = ii < 0;
+  const bool hi = ii >= D - 1;
+  clamped = lo || (hi && (ii > D - 1 || tt > 0.0f));
+  i = lo ? 0 : (hi ? D - 2 : ii);
+  t = lo ? 0.0f : (hi ? 1.0f : tt);
 }
 
 __device__ __forceinline__ float lerp(float a, float b, float t) { return a + t * (b - a); }

@@ -293,7 +293,8 @@ __global__ __launch_bounds__(ENT) void k_exp_fwd(const float* __restrict__ src,
       const int c0 = bc.i0 - z + 1, c1 = bc.i1 - id.oy + 1, c2 = bc.i2 - id.ox + 1;
       float r[3];
       if (c0 >= 0 && c0 <= 1 && c1 >= 0 && c1 + 1 < MHY && c2 >= 0 && c2 + 1 < MHX) {
-        const int sa = (bc.i0 + 3) % 3, sb = (bc.i0 + 4) % 3;
+        // ring slots of planes i0 and i0 + 1, i0 in {z - 1, z}: uniform choices
+        const int sa = c0 ? sz : (z + 2) % 3, sb = c0 ? (z + 1) % 3 : sz;
         const int pb = c1 * MHX + c2;
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
@@ -768,10 +769,13 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
     }
   };
   // bin one source into its cell (plane bc.i0, which must be the plane being filled)
-  auto bin_one = [&](const BorderCell& bc, float g0, float g1, float g2) {
-    if (bc.i0 < id.z0 - 1 || bc.i0 > id.z1 - 1) return;  // cell plane not gathered here
+  // Every call site bins into the cell plane being filled, which lies in
+  // [z0 - 1, z1 - 1].  The cell of a tile voxel (halo = false) always lies in
+  // the tile's cell region (offsets in [-1, 0], and border clamping keeps a
+  // cell inside the volume); a halo voxel's cell may not.
+  auto bin_one = [&](const BorderCell& bc, float g0, float g1, float g2, bool halo) {
     const int c1 = bc.i1 - id.oy + 1, c2 = bc.i2 - id.ox + 1;
-    if (c1 < 0 || c1 >= MCY || c2 < 0 || c2 >= MCX) return;
+    if (halo && (c1 < 0 || c1 >= MCY || c2 < 0 || c2 >= MCX)) return;
     const int ci = c1 * MCX + c2;
     const int cs = bc.i0 & 1;
     const int slot = atomicAdd(&bcnt[cs][ci], 1);
@@ -828,11 +832,11 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
   cells_of(id.z0 - 1, qu, nb, nok);
 #pragma unroll
   for (int j = 0; j < 2; ++j)
-    if (nok[j] && nb[j].i0 == id.z0 - 1) bin_one(nb[j], qg[j][0], qg[j][1], qg[j][2]);
+    if (nok[j] && nb[j].i0 == id.z0 - 1) bin_one(nb[j], qg[j][0], qg[j][1], qg[j][2], j == 1);
   cells_of(id.z0, pu, cb, cok);
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
-    if (cok[j] && cb[j].i0 == id.z0 - 1) bin_one(cb[j], pg[j][0], pg[j][1], pg[j][2]);
+    if (cok[j] && cb[j].i0 == id.z0 - 1) bin_one(cb[j], pg[j][0], pg[j][1], pg[j][2], j == 1);
 #pragma unroll
     for (int c = 0; c < 3; ++c) cg[j][c] = pg[j][c];
   }
@@ -860,11 +864,12 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
     // (iii) fill cell plane z
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
-      if (cok[j] && cb[j].i0 == z) bin_one(cb[j], cg[j][0], cg[j][1], cg[j][2]);
-      if (nok[j] && nb[j].i0 == z) bin_one(nb[j], qg[j][0], qg[j][1], qg[j][2]);
+      if (cok[j] && cb[j].i0 == z) bin_one(cb[j], cg[j][0], cg[j][1], cg[j][2], j == 1);
+      if (nok[j] && nb[j].i0 == z) bin_one(nb[j], qg[j][0], qg[j][1], qg[j][2], j == 1);
     }
     // (iv) direct term of the plane-z targets
     float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f;
+    const int szm = (z + 2) % 3, szc = z % 3, szp = (z + 1) % 3;  // slots of z-1, z, z+1
     if (colv) {
       const BorderCell& bc = cb[0];
       const int c0 = bc.i0 - z + 1, c1 = bc.i1 - id.oy + 1, c2 = bc.i2 - id.ox + 1;
@@ -879,7 +884,8 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
       // wait for memory loads (and with them for the planes in flight).
       Tri t;
       if (in_ring) {
-        const int sa = (bc.i0 + 3) % 3, sb = (bc.i0 + 4) % 3;
+        // ring slots of planes i0 and i0 + 1, i0 in {z - 1, z}: uniform choices
+        const int sa = c0 ? szc : szm, sb = c0 ? szp : szc;
         const int pb = c1 * MHX + c2;
         float h[8];
 #pragma unroll

@@ -295,10 +295,12 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
         }
         // the output voxel's own values, issued before the next plane's
         // factors so that waiting for them does not wait for those too
-        // (clamped indices: always valid, used only for live outputs)
+        // (clamped indices: always valid, used only for live outputs; the
+        // ramp-up planes before the chunk read its first output plane, which
+        // is needed soon, rather than the previous chunk's planes)
         const int zo = zz - R;
         const int y = tl.yb + ly, x = tl.xb + lx;
-        const int idx = (min(max(zo, 0), g.d0 - 1) * g.d1 + min(y, g.d1 - 1)) * g.d2 +
+        const int idx = (min(max(zo, tl.z0), g.d0 - 1) * g.d1 + min(y, g.d1 - 1)) * g.d2 +
                         min(x, g.d2 - 1);
         const float eJ = atlas[tl.chan * astr + idx];
         const float eI = wimg[tl.chan * wstr + idx];

@@ -13,10 +13,11 @@
 // neighbour) and x1 (next c1 channels), which is how the decoder reads its
 // upsampled and skip tensors without materialising either.
 //
-// One wave computes a 16-voxel x (16 * NT16) tile with
+// One wave computes MT 16-voxel row tiles x (16 * NT16) channels with
 // v_mfma_f32_16x16x32_bf16: per 32-wide K step, lane l supplies the A row
-// l % 16 (its voxel) and B column l % 16 at K entries 8 (l / 16) .. + 7, and
-// holds output rows 4 (l / 16) .. + 3 of column l % 16.  FP32 accumulation;
+// l % 16 (its voxel of each row tile) and B column l % 16 at K entries
+// 8 (l / 16) .. + 7 (loaded once and used by every row tile), and holds
+// output rows 4 (l / 16) .. + 3 of column l % 16.  FP32 accumulation;
 // bias, leaky ReLU and the BF16 rounding (to nearest even) in the epilogue.
 #include "darc_kernels.hpp"
 
@@ -65,7 +66,7 @@ __device__ __forceinline__ const uint16_t* input_at(const ConvGeom& cg, const ui
                (ch - cg.c0));
 }
 
-template <int NT16>
+template <int NT16, int MT>
 __global__ __launch_bounds__(CNT) void k_conv3d(const uint16_t* __restrict__ x0,
                                                 const uint16_t* __restrict__ x1,
                                                 const uint16_t* __restrict__ w,
@@ -74,65 +75,83 @@ __global__ __launch_bounds__(CNT) void k_conv3d(const uint16_t* __restrict__ x0,
                                                 float* __restrict__ y32, ConvGeom cg) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int r = lane & 15, kg = lane >> 4;
-  const long long m = static_cast<long long>(blockIdx.x) * CROWS + wave * 16 + r;
-  const bool mv = m < cg.nvox;
-  // output coordinates of this lane's A row
-  int s = 0, o0 = 0, o1 = 0, o2 = 0;
-  if (mv) {
-    const long long ov = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
-    s = static_cast<int>(m / ov);
-    int rem = static_cast<int>(m - static_cast<long long>(s) * ov);
-    o2 = rem % cg.o2;
-    rem /= cg.o2;
-    o1 = rem % cg.o1;
-    o0 = rem / cg.o1;
+  // this wave's MT consecutive 16-voxel row tiles
+  const long long mbase = static_cast<long long>(blockIdx.x) * CROWS * MT + wave * 16 * MT;
+  const long long ov = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
+  // output coordinates of this lane's A row in each tile
+  int s[MT], o0[MT], o1[MT], o2[MT];
+  bool mv[MT];
+#pragma unroll
+  for (int q = 0; q < MT; ++q) {
+    const long long m = mbase + q * 16 + r;
+    mv[q] = m < cg.nvox;
+    s[q] = o0[q] = o1[q] = o2[q] = 0;
+    if (mv[q]) {
+      s[q] = static_cast<int>(m / ov);
+      int rem = static_cast<int>(m - static_cast<long long>(s[q]) * ov);
+      o2[q] = rem % cg.o2;
+      rem /= cg.o2;
+      o1[q] = rem % cg.o1;
+      o0[q] = rem / cg.o1;
+    }
   }
   const int nco0 = blockIdx.y * 16 * NT16;
-  f32x4 acc[NT16];
+  f32x4 acc[MT][NT16];
 #pragma unroll
-  for (int t = 0; t < NT16; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int q = 0; q < MT; ++q)
+#pragma unroll
+    for (int t = 0; t < NT16; ++t) acc[q][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   const int cvec = (cg.c0 + cg.c1) >> 3;
   for (int kc = 0; kc < cg.kpad; kc += 32) {
-    // A fragment: 8 channels of one tap at this lane's voxel
-    const int kv = (kc >> 3) + kg;
-    const int tap = kv / cvec, v = kv - tap * cvec;
-    uint4 araw = make_uint4(0u, 0u, 0u, 0u);
-    if (mv) {
-      const uint16_t* src = input_at(cg, x0, x1, s, o0, o1, o2, tap, v * 8);
-      if (src) araw = *reinterpret_cast<const uint4*>(src);
-    }
-    const bf16x8 afrag = __builtin_bit_cast(bf16x8, araw);
+    // B fragments (weights) of this K step, shared by the wave's row tiles
+    bf16x8 bfrag[NT16];
 #pragma unroll
     for (int t = 0; t < NT16; ++t) {
       const int co = nco0 + t * 16 + r;
       uint4 braw = make_uint4(0u, 0u, 0u, 0u);
       if (co < cg.cout)
         braw = *reinterpret_cast<const uint4*>(w + static_cast<long long>(co) * cg.kpad + kc + kg * 8);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, __builtin_bit_cast(bf16x8, braw),
-                                                       acc[t], 0, 0, 0);
+      bfrag[t] = __builtin_bit_cast(bf16x8, braw);
+    }
+    // A fragments: 8 channels of one tap at this lane's voxel of each tile
+    const int kv = (kc >> 3) + kg;
+    const int tap = kv / cvec, v = kv - tap * cvec;
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+      uint4 araw = make_uint4(0u, 0u, 0u, 0u);
+      if (mv[q]) {
+        const uint16_t* src = input_at(cg, x0, x1, s[q], o0[q], o1[q], o2[q], tap, v * 8);
+        if (src) araw = *reinterpret_cast<const uint4*>(src);
+      }
+      const bf16x8 afrag = __builtin_bit_cast(bf16x8, araw);
+#pragma unroll
+      for (int t = 0; t < NT16; ++t)
+        acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[t], acc[q][t], 0, 0, 0);
     }
   }
   // epilogue: lane holds rows 4 kg .. 4 kg + 3 of column r of each N sub-tile
-  const long long ov = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
 #pragma unroll
   for (int t = 0; t < NT16; ++t) {
     const int co = nco0 + t * 16 + r;
     if (co >= cg.cout) continue;
     const float bb = bias ? bias[co] : 0.0f;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const long long mo = static_cast<long long>(blockIdx.x) * CROWS + wave * 16 + kg * 4 + i;
-      if (mo >= cg.nvox) continue;
-      float val = acc[t][i] + bb;
-      if (cg.act) val = val > 0.0f ? val : cg.slope * val;
-      if (y16) {
-        y16[mo * cg.cout + co] = to_bf16(val);
-      } else if (cg.ycl32) {
-        float* d = y32 + mo * cg.cout + co;
-        *d = cg.accum ? *d + val : val;
-      } else {
-        const long long so = mo / ov;
-        y32[(so * cg.cout + co) * ov + (mo - so * ov)] = val;
+    for (int q = 0; q < MT; ++q) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const long long mo = mbase + q * 16 + kg * 4 + i;
+        if (mo >= cg.nvox) continue;
+        float val = acc[q][t][i] + bb;
+        if (cg.act) val = val > 0.0f ? val : cg.slope * val;
+        if (y16) {
+          y16[mo * cg.cout + co] = to_bf16(val);
+        } else if (cg.ycl32) {
+          float* d = y32 + mo * cg.cout + co;
+          *d = cg.accum ? *d + val : val;
+        } else {
+          const long long so = mo / ov;
+          y32[(so * cg.cout + co) * ov + (mo - so * ov)] = val;
+        }
       }
     }
   }
@@ -380,16 +399,22 @@ int conv_kpad(int cin, int ntaps) {
 
 void launch_conv3d(const uint16_t* x0, const uint16_t* x1, const uint16_t* w, const float* bias,
                    uint16_t* y16, float* y32, const ConvGeom& cg, hipStream_t st) {
-  const uint32_t gx = static_cast<uint32_t>((cg.nvox + CROWS - 1) / CROWS);
+  // row tiles per wave (MT) share each K step's weight fragments
+  auto gx = [&](int mt) {
+    return static_cast<uint32_t>((cg.nvox + static_cast<long long>(CROWS) * mt - 1) /
+                                 (static_cast<long long>(CROWS) * mt));
+  };
   prof_begin(st, KC_MISC);
   if (cg.cout <= 16) {
-    hipLaunchKernelGGL(k_conv3d<1>, dim3(gx, 1), dim3(CNT), 0, st, x0, x1, w, bias, y16, y32, cg);
+    hipLaunchKernelGGL((k_conv3d<1, 4>), dim3(gx(4), 1), dim3(CNT), 0, st, x0, x1, w, bias, y16,
+                       y32, cg);
   } else if (cg.cout <= 32) {
-    hipLaunchKernelGGL(k_conv3d<2>, dim3(gx, 1), dim3(CNT), 0, st, x0, x1, w, bias, y16, y32, cg);
+    hipLaunchKernelGGL((k_conv3d<2, 2>), dim3(gx(2), 1), dim3(CNT), 0, st, x0, x1, w, bias, y16,
+                       y32, cg);
   } else {
     const uint32_t gy = static_cast<uint32_t>((cg.cout + 63) / 64);
-    hipLaunchKernelGGL(k_conv3d<4>, dim3(gx, gy), dim3(CNT), 0, st, x0, x1, w, bias, y16, y32,
-                       cg);
+    hipLaunchKernelGGL((k_conv3d<4, 2>), dim3(gx(2), gy), dim3(CNT), 0, st, x0, x1, w, bias, y16,
+                       y32, cg);
   }
   prof_end(st, KC_MISC);
 }

@@ -83,8 +83,7 @@ __device__ __forceinline__ int wave_max(int x) {
 // scatter (zeroed before).  Tiles are 32 (d2) x 8 (d1) x 8 (d0).
 __device__ __forceinline__ void write_record(int mn0, int mn1, int mn2, int mx0, int mx1, int mx2,
                                              int (*red)[ENT / 64], int* __restrict__ boxes,
-                                             int* __restrict__ reach, int s, int tile,
-                                             int ntiles) {
+                                             int s, int tile, int ntiles, int (&rmax)[6]) {
   mn0 = wave_min(mn0);
   mn1 = wave_min(mn1);
   mn2 = wave_min(mn2);
@@ -101,6 +100,10 @@ __device__ __forceinline__ void write_record(int mn0, int mn1, int mn2, int mx0,
     red[5][w] = mx2;
   }
   __syncthreads();
+  // thread 0 writes the box and folds the reaches into its running maxima
+  // (flush_reach issues them once per block): nothing here waits for memory,
+  // and no barrier follows, since `red` is rewritten only after the caller's
+  // next barrier
   if (threadIdx.x == 0) {
     int r[6];
     for (int k = 0; k < 6; ++k) r[k] = red[k][0];
@@ -109,19 +112,21 @@ __device__ __forceinline__ void write_record(int mn0, int mn1, int mn2, int mx0,
       for (int k = 3; k < 6; ++k) r[k] = max(r[k], red[k][i]);
     }
     int* bx = boxes + (static_cast<size_t>(s) * ntiles + tile) * 8;
-    int* rc = reach + s * 8;
     for (int d = 0; d < 3; ++d) {
       bx[d] = r[d];
       bx[3 + d] = r[3 + d];
-      // the reaches only grow and saturate early: skip the atomic (which
-      // every block of the subject would aim at the same word) unless this
-      // record can raise it; a stale read only costs a redundant atomic
-      const int lo = max(0, -r[d]), hi = max(0, r[3 + d] + 1);
-      if (lo > *reinterpret_cast<volatile int*>(rc + d)) atomicMax(rc + d, lo);
-      if (hi > *reinterpret_cast<volatile int*>(rc + 3 + d)) atomicMax(rc + 3 + d, hi);
+      rmax[d] = max(rmax[d], max(0, -r[d]));
+      rmax[3 + d] = max(rmax[3 + d], max(0, r[3 + d] + 1));
     }
   }
-  __syncthreads();
+}
+
+// The block's reaches into the subject's (atomics only where they can raise it).
+__device__ __forceinline__ void flush_reach(const int (&rmax)[6], int* __restrict__ reach, int s) {
+  if (threadIdx.x == 0) {
+    for (int k = 0; k < 6; ++k)
+      if (rmax[k] > 0) atomicMax(reach + s * 8 + k, rmax[k]);
+  }
 }
 
 // Records only (for an adjoint whose forward pass did not record them).
@@ -156,7 +161,9 @@ __global__ __launch_bounds__(ENT) void k_exp_rec(const float* __restrict__ src, 
       mx2 = max(mx2, bc.i2 - x2);
     }
   }
-  write_record(mn0, mn1, mn2, mx0, mx1, mx2, red, boxes, reach, id.s, id.tile, tg.ntiles);
+  int rmax[6] = {0, 0, 0, 0, 0, 0};
+  write_record(mn0, mn1, mn2, mx0, mx1, mx2, red, boxes, id.s, id.tile, tg.ntiles, rmax);
+  flush_reach(rmax, reach, id.s);
 }
 
 // ---------------------------------------------------------------------------
@@ -277,6 +284,7 @@ __global__ __launch_bounds__(ENT) void k_exp_fwd(const float* __restrict__ src,
   const bool colv = (x2 < g.d2) && (x1 < g.d1);
   const int own = (ly + 1) * MHX + lx + 1;
   int mn0 = INT_MAX, mn1 = INT_MAX, mn2 = INT_MAX, mx0 = INT_MIN, mx1 = INT_MIN, mx2 = INT_MIN;
+  int rmax[6] = {0, 0, 0, 0, 0, 0};
   for (int z = id.z0; z < id.z1; ++z) {
     store_plane(z + 1);
     __syncthreads();
@@ -337,13 +345,14 @@ __global__ __launch_bounds__(ENT) void k_exp_fwd(const float* __restrict__ src,
     }
     if (REC && ((z + 1) % ETZ == 0 || z + 1 == id.z1)) {
       const int tile = ((z / ETZ) * m.rec.nty + id.ty) * m.rec.ntx + id.tx;
-      write_record(mn0, mn1, mn2, mx0, mx1, mx2, red, boxes, reach, id.s, tile, m.rec.ntiles);
+      write_record(mn0, mn1, mn2, mx0, mx1, mx2, red, boxes, id.s, tile, m.rec.ntiles, rmax);
       mn0 = mn1 = mn2 = INT_MAX;
       mx0 = mx1 = mx2 = INT_MIN;
     } else {
       __syncthreads();
     }
   }
+  if (REC) flush_reach(rmax, reach, id.s);
 }
 
 // Adjoint tiles: 4 (d0) x 4 (d1) x 32 (d2) output voxels, two per thread.

@@ -177,68 +177,114 @@ __device__ __forceinline__ float from_bf16(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
 
-// dW tile 16 (co) x 16 (k) of one wave over a chunk of output voxels:
-// C[co][k] = sum_v dz[v][co] X(v, k) with A = dz^T (lane: row co, 8
-// consecutive voxels) and B = X (lane: column k, the same 8 voxels).
+// dW tiles 16 (co) x 16 NK (k) of one wave over a chunk of output voxels:
+// C[co][k] = sum_v dz[v][co] X(v, k) with the 32 voxels of a K step as the
+// MFMA reduction.  The reduction runs over voxels while both operands are
+// stored channels-last, so each K step is transposed through a small LDS
+// tile of the wave: lane l loads 8 channels of voxel l % 32 (one 16-byte
+// read of dz, and of X at each column group's tap: a group of 8 consecutive
+// k is one tap and 8 channels), writes them as [channel][voxel], and then
+// reads its A row / B column at 8 consecutive voxels as one 16-byte read.
 constexpr int WCH = 1024;  // voxels per wave
+constexpr int WNK = 4;     // 16-column k tiles per wave
 __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ dz, int cz,
                                                    const uint16_t* __restrict__ x0,
                                                    const uint16_t* __restrict__ x1, ConvGeom cg,
                                                    float* __restrict__ dw) {
+  __shared__ __align__(16) uint16_t at[16 * 32];       // dz^T: [co][voxel]
+  __shared__ __align__(16) uint16_t bt[WNK][16 * 32];  // X^T:  [k][voxel]
   const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
-  const int cin = cg.c0 + cg.c1;
-  const int kcol = blockIdx.y * 16 + r;   // this lane's B column
-  const int corow = blockIdx.z * 16 + r;  // this lane's A row
-  const int tap = kcol / cin, ci = kcol - tap * cin;
+  const int vl = lane & 31, h = lane >> 5;  // staged voxel, channel half
+  const int cvec = (cg.c0 + cg.c1) >> 3;
+  const int co0 = blockIdx.z * 16;
+  const int kb = blockIdx.y * 16 * WNK;  // first k column of the wave
+  // column groups this lane stages: (tap, channel) of k = kb + 16 t + 8 h
+  int gtap[WNK], gch[WNK];
+#pragma unroll
+  for (int t = 0; t < WNK; ++t) {
+    const int kv = (kb + 16 * t) / 8 + h;
+    gtap[t] = kv / cvec;
+    gch[t] = (kv - gtap[t] * cvec) * 8;
+  }
+  // coordinates of the staged voxel, advanced by 32 voxels per K step
+  const long long vstart = static_cast<long long>(blockIdx.x) * WCH + vl;
   const long long ov = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
-  f32x4 acc = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  int s = 0, o0 = 0, o1 = 0, o2 = 0;
+  if (vstart < cg.nvox) {
+    s = static_cast<int>(vstart / ov);
+    int rem = static_cast<int>(vstart - s * ov);
+    o2 = rem % cg.o2;
+    rem /= cg.o2;
+    o1 = rem % cg.o1;
+    o0 = rem / cg.o1;
+  }
+  f32x4 acc[WNK];
+#pragma unroll
+  for (int t = 0; t < WNK; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int step = 0; step < WCH; step += 32) {
     const long long vb = static_cast<long long>(blockIdx.x) * WCH + step;
-    if (vb >= cg.nvox) break;  // uniform across the wave: every lane keeps its operands
-    const long long v0 = vb + 8 * g;
-    int s = static_cast<int>(v0 / ov);
-    int rem = static_cast<int>(v0 - s * ov);
-    int o2 = rem % cg.o2;
-    rem /= cg.o2;
-    int o1 = rem % cg.o1, o0 = rem / cg.o1;
-    uint16_t av[8], bv[8];
+    if (vb >= cg.nvox) break;  // uniform across the wave
+    const long long v = vb + vl;
+    const bool live = v < cg.nvox;
+    // stage dz^T and X^T of these 32 voxels
+    uint4 araw = make_uint4(0u, 0u, 0u, 0u);
+    if (live && co0 + 8 * h < cz)
+      araw = *reinterpret_cast<const uint4*>(dz + v * cz + co0 + 8 * h);
+    uint4 braw[WNK];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const long long v = v0 + j;
-      av[j] = 0;
-      bv[j] = 0;
-      if (v < cg.nvox) {
-        if (corow < cz) av[j] = dz[v * cz + corow];
-        const uint16_t* src = input_at(cg, x0, x1, s, o0, o1, o2, tap, ci);
-        if (src) bv[j] = *src;
+    for (int t = 0; t < WNK; ++t) {
+      braw[t] = make_uint4(0u, 0u, 0u, 0u);
+      if (live) {
+        const uint16_t* src = input_at(cg, x0, x1, s, o0, o1, o2, gtap[t], gch[t]);
+        if (src) braw[t] = *reinterpret_cast<const uint4*>(src);
       }
-      if (++o2 == cg.o2) {
-        o2 = 0;
-        if (++o1 == cg.o1) {
-          o1 = 0;
-          if (++o0 == cg.o0) {
-            o0 = 0;
-            ++s;
-          }
+    }
+    const uint32_t aw[4] = {araw.x, araw.y, araw.z, araw.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      at[(8 * h + 2 * j) * 32 + vl] = static_cast<uint16_t>(aw[j]);
+      at[(8 * h + 2 * j + 1) * 32 + vl] = static_cast<uint16_t>(aw[j] >> 16);
+    }
+#pragma unroll
+    for (int t = 0; t < WNK; ++t) {
+      const uint32_t bw[4] = {braw[t].x, braw[t].y, braw[t].z, braw[t].w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        bt[t][(8 * h + 2 * j) * 32 + vl] = static_cast<uint16_t>(bw[j]);
+        bt[t][(8 * h + 2 * j + 1) * 32 + vl] = static_cast<uint16_t>(bw[j] >> 16);
+      }
+    }
+    // one wave: its LDS operations complete in order, so the reads below
+    // see the writes above, and the next step's writes follow these reads
+    const bf16x8 afrag = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&at[r * 32 + 8 * g]));
+#pragma unroll
+    for (int t = 0; t < WNK; ++t) {
+      const bf16x8 bfrag =
+          __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&bt[t][r * 32 + 8 * g]));
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, acc[t], 0, 0, 0);
+    }
+    // advance the staged voxel by 32
+    o2 += 32;
+    while (o2 >= cg.o2) {
+      o2 -= cg.o2;
+      if (++o1 == cg.o1) {
+        o1 = 0;
+        if (++o0 == cg.o0) {
+          o0 = 0;
+          ++s;
         }
       }
     }
-    uint4 ar, br;
-    ar.x = av[0] | (static_cast<uint32_t>(av[1]) << 16);
-    ar.y = av[2] | (static_cast<uint32_t>(av[3]) << 16);
-    ar.z = av[4] | (static_cast<uint32_t>(av[5]) << 16);
-    ar.w = av[6] | (static_cast<uint32_t>(av[7]) << 16);
-    br.x = bv[0] | (static_cast<uint32_t>(bv[1]) << 16);
-    br.y = bv[2] | (static_cast<uint32_t>(bv[3]) << 16);
-    br.z = bv[4] | (static_cast<uint32_t>(bv[5]) << 16);
-    br.w = bv[6] | (static_cast<uint32_t>(bv[7]) << 16);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, ar),
-                                                  __builtin_bit_cast(bf16x8, br), acc, 0, 0, 0);
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int co = blockIdx.z * 16 + 4 * g + i;
-    if (co < cg.cout && kcol < cg.kpad) atomicAdd(dw + static_cast<long long>(co) * cg.kpad + kcol, acc[i]);
+  for (int t = 0; t < WNK; ++t) {
+    const int kcol = kb + 16 * t + r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = co0 + 4 * g + i;
+      if (co < cg.cout && kcol < cg.kpad)
+        atomicAdd(dw + static_cast<long long>(co) * cg.kpad + kcol, acc[t][i]);
+    }
   }
 }
 
@@ -352,7 +398,8 @@ void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uin
                        const ConvGeom& cg, float* dw, float* db, hipStream_t st) {
   prof_begin(st, KC_MISC);
   const dim3 grid(static_cast<uint32_t>((cg.nvox + WCH - 1) / WCH),
-                  static_cast<uint32_t>(cg.kpad / 16), static_cast<uint32_t>((cg.cout + 15) / 16));
+                  static_cast<uint32_t>((cg.kpad + 16 * WNK - 1) / (16 * WNK)),
+                  static_cast<uint32_t>((cg.cout + 15) / 16));
   hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(64), 0, st, dz, cz, x0, x1, cg, dw);
   if (db)
     hipLaunchKernelGGL(k_bias_grad, dim3(static_cast<uint32_t>((cg.nvox + 4095) / 4096)),

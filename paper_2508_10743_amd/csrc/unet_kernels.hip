@@ -190,7 +190,8 @@ constexpr int WNK = 4;     // 16-column k tiles per wave
 __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ dz, int cz,
                                                    const uint16_t* __restrict__ x0,
                                                    const uint16_t* __restrict__ x1, ConvGeom cg,
-                                                   float* __restrict__ dw) {
+                                                   float* __restrict__ dw,
+                                                   float* __restrict__ db) {
   __shared__ __align__(16) uint16_t at[16 * 32];       // dz^T: [co][voxel]
   __shared__ __align__(16) uint16_t bt[WNK][16 * 32];  // X^T:  [k][voxel]
   const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
@@ -221,6 +222,9 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
   f32x4 acc[WNK];
 #pragma unroll
   for (int t = 0; t < WNK; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  // the bias gradient sum_v dz[v][co], from the staged dz of the first k tile
+  const bool bias = db != nullptr && blockIdx.y == 0;
+  float bacc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   for (int step = 0; step < WCH; step += 32) {
     const long long vb = static_cast<long long>(blockIdx.x) * WCH + step;
     if (vb >= cg.nvox) break;  // uniform across the wave
@@ -244,6 +248,10 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
     for (int j = 0; j < 4; ++j) {
       at[(8 * h + 2 * j) * 32 + vl] = static_cast<uint16_t>(aw[j]);
       at[(8 * h + 2 * j + 1) * 32 + vl] = static_cast<uint16_t>(aw[j] >> 16);
+      if (bias) {
+        bacc[2 * j] += __uint_as_float(aw[j] << 16);
+        bacc[2 * j + 1] += __uint_as_float(aw[j] & 0xFFFF0000u);
+      }
     }
 #pragma unroll
     for (int t = 0; t < WNK; ++t) {
@@ -286,16 +294,21 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
         atomicAdd(dw + static_cast<long long>(co) * cg.kpad + kcol, acc[t][i]);
     }
   }
-}
-
-__global__ __launch_bounds__(kBlock) void k_bias_grad(const uint16_t* __restrict__ dz, int cz,
-                                                      int cout, long long nvox,
-                                                      float* __restrict__ db) {
-  const int c = threadIdx.x % cz, lane_v = threadIdx.x / cz, per = kBlock / cz;
-  const long long v0 = static_cast<long long>(blockIdx.x) * 4096;
-  float acc = 0.0f;
-  for (long long v = v0 + lane_v; v < v0 + 4096 && v < nvox; v += per) acc += from_bf16(dz[v * cz + c]);
-  if (c < cout) atomicAdd(db + c, acc);
+  if (bias) {
+    // sum over the 32 staged voxels of each channel half, one atomic per channel
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+#pragma unroll
+      for (int m = 16; m >= 1; m >>= 1) bacc[j] += __shfl_xor(bacc[j], m, 64);
+    }
+    if (vl == 0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int co = co0 + 8 * h + j;
+        if (co < cg.cout) atomicAdd(db + co, bacc[j]);
+      }
+    }
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_pack_wt(const float* __restrict__ w, int cin, int cout,
@@ -379,11 +392,13 @@ __global__ __launch_bounds__(kBlock) void k_vec_mse(const float* __restrict__ p,
                                                     double inv, double* __restrict__ loss,
                                                     float* __restrict__ g) {
   __shared__ double red[kBlock / 64];
-  const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
+  // grid-stride over a bounded grid: one loss atomic per block
   double acc = 0.0;
-  if (i < count) {
+  const long long stride = static_cast<long long>(gridDim.x) * kBlock;
+  for (long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x; i < count;
+       i += stride) {
     const double d = static_cast<double>(p[i]) - static_cast<double>(t[i]);
-    acc = d * d * inv;
+    acc += d * d * inv;
     g[i] = static_cast<float>(2.0 * d * inv);
   }
   const double tot = block_sum<kBlock>(acc, red);
@@ -400,10 +415,7 @@ void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uin
   const dim3 grid(static_cast<uint32_t>((cg.nvox + WCH - 1) / WCH),
                   static_cast<uint32_t>((cg.kpad + 16 * WNK - 1) / (16 * WNK)),
                   static_cast<uint32_t>((cg.cout + 15) / 16));
-  hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(64), 0, st, dz, cz, x0, x1, cg, dw);
-  if (db)
-    hipLaunchKernelGGL(k_bias_grad, dim3(static_cast<uint32_t>((cg.nvox + 4095) / 4096)),
-                       dim3(kBlock), 0, st, dz, cz, cg.cout, cg.nvox, db);
+  hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(64), 0, st, dz, cz, x0, x1, cg, dw, db);
   prof_end(st, KC_MISC);
 }
 
@@ -435,7 +447,8 @@ void launch_to_bf16(const float* in, uint16_t* out, long long count, hipStream_t
 
 void launch_vec_mse(const float* p, const float* t, long long count, double* loss, float* g,
                     hipStream_t st) {
-  hipLaunchKernelGGL(k_vec_mse, dim3(grid_1d(count)), dim3(kBlock), 0, st, p, t, count,
+  const uint32_t blocks = grid_1d(count) < 2048u ? grid_1d(count) : 2048u;
+  hipLaunchKernelGGL(k_vec_mse, dim3(blocks), dim3(kBlock), 0, st, p, t, count,
                      1.0 / static_cast<double>(count), loss, g);
 }
 

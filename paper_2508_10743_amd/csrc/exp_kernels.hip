@@ -1017,6 +1017,9 @@ size_t exp_aux_bytes(const Geom& g, int n, int n_sq) {
 int march_tz(const TileGeom& tg, int n) {
   const int tuned = tuned_tz(TUNE_EXP, tg.g, n);
   if (tuned > 0) return tuned;
+  // long chunks amortise the ramp-up planes, short ones keep each block's
+  // planes in flight within L2 (64 planes measured no faster than 32 and
+  // fetched more from HBM); shorter still for small cohorts
   int tz = 32;
   while (tz > ETZ && static_cast<long long>(tg.ntx) * tg.nty * ((tg.g.d0 + tz - 1) / tz) * n < 4096)
     tz /= 2;

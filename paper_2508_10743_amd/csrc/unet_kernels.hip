@@ -66,7 +66,9 @@ __device__ __forceinline__ const uint16_t* input_at(const ConvGeom& cg, const ui
                (ch - cg.c0));
 }
 
-template <int NT16, int MT>
+// X0: how x0 is read (0: full resolution; 1: half resolution, nearest
+// upsampled; 2: half resolution, zero-dilated), fixed per launch.
+template <int NT16, int MT, int X0>
 __global__ __launch_bounds__(CNT) void k_conv3d(const uint16_t* __restrict__ x0,
                                                 const uint16_t* __restrict__ x1,
                                                 const uint16_t* __restrict__ w,
@@ -78,22 +80,37 @@ __global__ __launch_bounds__(CNT) void k_conv3d(const uint16_t* __restrict__ x0,
   // this wave's MT consecutive 16-voxel row tiles
   const long long mbase = static_cast<long long>(blockIdx.x) * CROWS * MT + wave * 16 * MT;
   const long long ov = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
-  // output coordinates of this lane's A row in each tile
-  int s[MT], o0[MT], o1[MT], o2[MT];
+  constexpr bool half = X0 != 0;  // x0 is stored at half resolution
+  const int h0 = half ? cg.i0 / 2 : cg.i0, h1 = half ? cg.i1 / 2 : cg.i1;
+  const int h2 = half ? cg.i2 / 2 : cg.i2;
+  // per row tile: this lane's voxel as input position of tap (0, 0, 0)
+  // (output position * stride - 1), the subject's base pointers, and the
+  // x1 voxel offset of that position within the subject
+  int q0[MT], q1[MT], q2[MT], lb1[MT];
+  const uint16_t* t0[MT];
+  const uint16_t* t1[MT];
   bool mv[MT];
+  const long long vin0 = static_cast<long long>(h0) * h1 * h2;
+  const long long vin1 = static_cast<long long>(cg.i0) * cg.i1 * cg.i2;
 #pragma unroll
   for (int q = 0; q < MT; ++q) {
     const long long m = mbase + q * 16 + r;
     mv[q] = m < cg.nvox;
-    s[q] = o0[q] = o1[q] = o2[q] = 0;
+    int ss = 0, a0 = 0, a1 = 0, a2 = 0;
     if (mv[q]) {
-      s[q] = static_cast<int>(m / ov);
-      int rem = static_cast<int>(m - static_cast<long long>(s[q]) * ov);
-      o2[q] = rem % cg.o2;
+      ss = static_cast<int>(m / ov);
+      int rem = static_cast<int>(m - static_cast<long long>(ss) * ov);
+      a2 = rem % cg.o2;
       rem /= cg.o2;
-      o1[q] = rem % cg.o1;
-      o0[q] = rem / cg.o1;
+      a1 = rem % cg.o1;
+      a0 = rem / cg.o1;
     }
+    q0[q] = a0 * cg.stride - 1;
+    q1[q] = a1 * cg.stride - 1;
+    q2[q] = a2 * cg.stride - 1;
+    lb1[q] = (q0[q] * cg.i1 + q1[q]) * cg.i2 + q2[q];
+    t0[q] = x0 + ss * vin0 * cg.c0;
+    t1[q] = x1 + ss * vin1 * cg.c1 - cg.c0;  // x1 channels follow the c0 of x0
   }
   const int nco0 = blockIdx.y * 16 * NT16;
   f32x4 acc[MT][NT16];
@@ -102,6 +119,15 @@ __global__ __launch_bounds__(CNT) void k_conv3d(const uint16_t* __restrict__ x0,
 #pragma unroll
     for (int t = 0; t < NT16; ++t) acc[q][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   const int cvec = (cg.c0 + cg.c1) >> 3;
+  // this lane's 8-wide K group: tap and channel group, advanced by 4 groups
+  // per K step without divisions; (ta, tb, tc) is the tap's offset + 1
+  int tap = kg / cvec, v = kg - tap * cvec;
+  int ta = 1, tb = 1, tc = 1;
+  if (cg.ntaps == 27) {
+    ta = tap / 9;
+    tb = (tap / 3) % 3;
+    tc = tap % 3;
+  }
   for (int kc = 0; kc < cg.kpad; kc += 32) {
     // B fragments (weights) of this K step, shared by the wave's row tiles
     bf16x8 bfrag[NT16];
@@ -113,20 +139,56 @@ __global__ __launch_bounds__(CNT) void k_conv3d(const uint16_t* __restrict__ x0,
         braw = *reinterpret_cast<const uint4*>(w + static_cast<long long>(co) * cg.kpad + kc + kg * 8);
       bfrag[t] = __builtin_bit_cast(bf16x8, braw);
     }
-    // A fragments: 8 channels of one tap at this lane's voxel of each tile
-    const int kv = (kc >> 3) + kg;
-    const int tap = kv / cvec, v = kv - tap * cvec;
+    // A fragments: 8 channels of this lane's tap at its voxel of each tile.
+    // Every load is issued (from x0 itself where the input is zero) before
+    // the products; the zero padding is applied to the loaded values.
+    const int ch = v * 8;
+    const bool from0 = ch < cg.c0;
+    const bool tap_ok = tap < cg.ntaps;
+    const int toff1 = (ta * cg.i1 + tb) * cg.i2 + tc;
+    uint4 araw[MT];
+    bool in[MT];
 #pragma unroll
     for (int q = 0; q < MT; ++q) {
-      uint4 araw = make_uint4(0u, 0u, 0u, 0u);
-      if (mv[q]) {
-        const uint16_t* src = input_at(cg, x0, x1, s[q], o0[q], o1[q], o2[q], tap, v * 8);
-        if (src) araw = *reinterpret_cast<const uint4*>(src);
+      const int p0 = q0[q] + ta, p1 = q1[q] + tb, p2 = q2[q] + tc;
+      bool ok = tap_ok && mv[q] && static_cast<unsigned>(p0) < static_cast<unsigned>(cg.i0) &&
+                static_cast<unsigned>(p1) < static_cast<unsigned>(cg.i1) &&
+                static_cast<unsigned>(p2) < static_cast<unsigned>(cg.i2);
+      const uint16_t* src;
+      if (!half) {
+        // both inputs at full resolution: same voxel offset, own base and stride
+        src = (from0 ? t0[q] : t1[q]) +
+              static_cast<long long>(lb1[q] + toff1) * (from0 ? cg.c0 : cg.c1) + ch;
+      } else if (from0) {
+        if (X0 == 2) ok = ok && !((p0 | p1 | p2) & 1);
+        src = t0[q] + static_cast<long long>(((p0 >> 1) * h1 + (p1 >> 1)) * h2 + (p2 >> 1)) * cg.c0 +
+              ch;
+      } else {
+        src = t1[q] + static_cast<long long>(lb1[q] + toff1) * cg.c1 + ch;
       }
-      const bf16x8 afrag = __builtin_bit_cast(bf16x8, araw);
+      in[q] = ok;
+      araw[q] = *reinterpret_cast<const uint4*>(ok ? src : x0);
+    }
+#pragma unroll
+    for (int q = 0; q < MT; ++q) {
+      const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+      const bf16x8 afrag = __builtin_bit_cast(bf16x8, in[q] ? araw[q] : z);
 #pragma unroll
       for (int t = 0; t < NT16; ++t)
         acc[q][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[t], acc[q][t], 0, 0, 0);
+    }
+    // next K step: 4 groups further
+    v += 4;
+    while (v >= cvec) {
+      v -= cvec;
+      ++tap;
+      if (cg.ntaps == 27 && ++tc == 3) {
+        tc = 0;
+        if (++tb == 3) {
+          tb = 0;
+          ++ta;
+        }
+      }
     }
   }
   // epilogue: lane holds rows 4 kg .. 4 kg + 3 of column r of each N sub-tile
@@ -457,6 +519,22 @@ int conv_kpad(int cin, int ntaps) {
   return (ntaps * cv * 8 + 31) / 32 * 32;
 }
 
+namespace {
+template <int NT16, int MT>
+void conv3d_x0(int mode, dim3 grid, const uint16_t* x0, const uint16_t* x1, const uint16_t* w,
+               const float* bias, uint16_t* y16, float* y32, const ConvGeom& cg, hipStream_t st) {
+  if (mode == 0)
+    hipLaunchKernelGGL((k_conv3d<NT16, MT, 0>), grid, dim3(CNT), 0, st, x0, x1, w, bias, y16, y32,
+                       cg);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_conv3d<NT16, MT, 1>), grid, dim3(CNT), 0, st, x0, x1, w, bias, y16, y32,
+                       cg);
+  else
+    hipLaunchKernelGGL((k_conv3d<NT16, MT, 2>), grid, dim3(CNT), 0, st, x0, x1, w, bias, y16, y32,
+                       cg);
+}
+}  // namespace
+
 void launch_conv3d(const uint16_t* x0, const uint16_t* x1, const uint16_t* w, const float* bias,
                    uint16_t* y16, float* y32, const ConvGeom& cg, hipStream_t st) {
   // row tiles per wave (MT) share each K step's weight fragments
@@ -465,16 +543,14 @@ void launch_conv3d(const uint16_t* x0, const uint16_t* x1, const uint16_t* w, co
                                  (static_cast<long long>(CROWS) * mt));
   };
   prof_begin(st, KC_MISC);
+  const int mode = cg.dil0 ? 2 : (cg.up0 ? 1 : 0);
   if (cg.cout <= 16) {
-    hipLaunchKernelGGL((k_conv3d<1, 4>), dim3(gx(4), 1), dim3(CNT), 0, st, x0, x1, w, bias, y16,
-                       y32, cg);
+    conv3d_x0<1, 4>(mode, dim3(gx(4), 1), x0, x1, w, bias, y16, y32, cg, st);
   } else if (cg.cout <= 32) {
-    hipLaunchKernelGGL((k_conv3d<2, 2>), dim3(gx(2), 1), dim3(CNT), 0, st, x0, x1, w, bias, y16,
-                       y32, cg);
+    conv3d_x0<2, 2>(mode, dim3(gx(2), 1), x0, x1, w, bias, y16, y32, cg, st);
   } else {
     const uint32_t gy = static_cast<uint32_t>((cg.cout + 63) / 64);
-    hipLaunchKernelGGL((k_conv3d<4, 2>), dim3(gx(2), gy), dim3(CNT), 0, st, x0, x1, w, bias, y16,
-                       y32, cg);
+    conv3d_x0<4, 2>(mode, dim3(gx(2), gy), x0, x1, w, bias, y16, y32, cg, st);
   }
   prof_end(st, KC_MISC);
 }

@@ -249,6 +249,24 @@ def test_adam_step(dev):
     assert rel_linf(h(sd), rs) <= 1e-6
 
 
+@pytest.mark.parametrize("offset", [0, 1, 3])
+def test_adam_step_alignment_and_tail(dev, offset):
+    """The Adam step on arrays at any element offset (not 16-byte aligned)
+    and of odd length; elements outside the given range stay untouched."""
+    n = 4099
+    v, m = random_volume(131, (n + 3,), -1, 1), random_volume(132, (n + 3,), -0.1, 0.1)
+    s, gr = random_volume(133, (n + 3,), 0.0, 0.01), random_volume(134, (n + 3,), -1, 1)
+    sl = slice(offset, offset + n)
+    rv, rm, rs = O.adam_step(v[sl], m[sl], s[sl], gr[sl], 3)
+    vd, md, sd, gd = g(v, dev), g(m, dev), g(s, dev), g(gr, dev)
+    D.adam_step(vd[sl], md[sl], sd[sl], gd[sl], 3)
+    assert rel_linf(h(vd)[sl], rv) <= 1e-6
+    assert rel_linf(h(md)[sl], rm) <= 1e-6
+    assert rel_linf(h(sd)[sl], rs) <= 1e-6
+    # elements outside the slice are untouched
+    assert np.array_equal(h(vd)[:offset], v[:offset]) and np.array_equal(h(vd)[offset + n:], v[offset + n:])
+
+
 def test_center_and_atlas(dev):
     u = random_velocity(121, 5, DIMS, 2.0)
     ud = g(u, dev)

@@ -249,6 +249,7 @@ __device__ __forceinline__ float from_bf16(uint16_t h) {
 // reads its A row / B column at 8 consecutive voxels as one 16-byte read.
 constexpr int WCH = 1024;  // voxels per wave
 constexpr int WNK = 4;     // 16-column k tiles per wave
+template <int X0>
 __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ dz, int cz,
                                                    const uint16_t* __restrict__ x0,
                                                    const uint16_t* __restrict__ x1, ConvGeom cg,
@@ -256,18 +257,34 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
                                                    float* __restrict__ db) {
   __shared__ __align__(16) uint16_t at[16 * 32];       // dz^T: [co][voxel]
   __shared__ __align__(16) uint16_t bt[WNK][16 * 32];  // X^T:  [k][voxel]
+  constexpr bool half = X0 != 0;  // x0 is stored at half resolution
   const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
   const int vl = lane & 31, h = lane >> 5;  // staged voxel, channel half
   const int cvec = (cg.c0 + cg.c1) >> 3;
   const int co0 = blockIdx.z * 16;
   const int kb = blockIdx.y * 16 * WNK;  // first k column of the wave
-  // column groups this lane stages: (tap, channel) of k = kb + 16 t + 8 h
-  int gtap[WNK], gch[WNK];
+  const int h0 = half ? cg.i0 / 2 : cg.i0, h1 = half ? cg.i1 / 2 : cg.i1;
+  const int h2 = half ? cg.i2 / 2 : cg.i2;
+  const long long vin0 = static_cast<long long>(h0) * h1 * h2;
+  const long long vin1 = static_cast<long long>(cg.i0) * cg.i1 * cg.i2;
+  // column groups this lane stages: (tap, channel) of k = kb + 16 t + 8 h,
+  // as tap offset + 1 per axis and, for full-resolution reads, the tap's
+  // voxel offset
+  int gta[WNK], gtb[WNK], gtc[WNK], gch[WNK], gto[WNK];
+  bool gok[WNK];
 #pragma unroll
   for (int t = 0; t < WNK; ++t) {
     const int kv = (kb + 16 * t) / 8 + h;
-    gtap[t] = kv / cvec;
-    gch[t] = (kv - gtap[t] * cvec) * 8;
+    const int tap = kv / cvec;
+    gch[t] = (kv - tap * cvec) * 8;
+    gok[t] = tap < cg.ntaps;
+    gta[t] = gtb[t] = gtc[t] = 1;
+    if (cg.ntaps == 27) {
+      gta[t] = tap / 9;
+      gtb[t] = (tap / 3) % 3;
+      gtc[t] = tap % 3;
+    }
+    gto[t] = (gta[t] * cg.i1 + gtb[t]) * cg.i2 + gtc[t];
   }
   // coordinates of the staged voxel, advanced by 32 voxels per K step
   const long long vstart = static_cast<long long>(blockIdx.x) * WCH + vl;
@@ -292,19 +309,41 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
     if (vb >= cg.nvox) break;  // uniform across the wave
     const long long v = vb + vl;
     const bool live = v < cg.nvox;
-    // stage dz^T and X^T of these 32 voxels
+    // stage dz^T and X^T of these 32 voxels: every load issued (from x0
+    // itself where the input is zero), the zero padding applied afterwards
     uint4 araw = make_uint4(0u, 0u, 0u, 0u);
     if (live && co0 + 8 * h < cz)
       araw = *reinterpret_cast<const uint4*>(dz + v * cz + co0 + 8 * h);
+    const int q0 = o0 * cg.stride - 1, q1 = o1 * cg.stride - 1, q2 = o2 * cg.stride - 1;
+    const int lb = (q0 * cg.i1 + q1) * cg.i2 + q2;
+    const uint16_t* t0 = x0 + s * vin0 * cg.c0;
+    const uint16_t* t1 = x1 + s * vin1 * cg.c1 - cg.c0;  // x1 channels follow the c0 of x0
     uint4 braw[WNK];
+    bool bin[WNK];
 #pragma unroll
     for (int t = 0; t < WNK; ++t) {
-      braw[t] = make_uint4(0u, 0u, 0u, 0u);
-      if (live) {
-        const uint16_t* src = input_at(cg, x0, x1, s, o0, o1, o2, gtap[t], gch[t]);
-        if (src) braw[t] = *reinterpret_cast<const uint4*>(src);
+      const int p0 = q0 + gta[t], p1 = q1 + gtb[t], p2 = q2 + gtc[t];
+      bool ok = live && gok[t] && static_cast<unsigned>(p0) < static_cast<unsigned>(cg.i0) &&
+                static_cast<unsigned>(p1) < static_cast<unsigned>(cg.i1) &&
+                static_cast<unsigned>(p2) < static_cast<unsigned>(cg.i2);
+      const bool from0 = gch[t] < cg.c0;
+      const uint16_t* src;
+      if (!half) {
+        src = (from0 ? t0 : t1) + static_cast<long long>(lb + gto[t]) * (from0 ? cg.c0 : cg.c1) +
+              gch[t];
+      } else if (from0) {
+        if (X0 == 2) ok = ok && !((p0 | p1 | p2) & 1);
+        src = t0 + static_cast<long long>(((p0 >> 1) * h1 + (p1 >> 1)) * h2 + (p2 >> 1)) * cg.c0 +
+              gch[t];
+      } else {
+        src = t1 + static_cast<long long>(lb + gto[t]) * cg.c1 + gch[t];
       }
+      bin[t] = ok;
+      braw[t] = *reinterpret_cast<const uint4*>(ok ? src : x0);
     }
+#pragma unroll
+    for (int t = 0; t < WNK; ++t)
+      if (!bin[t]) braw[t] = make_uint4(0u, 0u, 0u, 0u);
     const uint32_t aw[4] = {araw.x, araw.y, araw.z, araw.w};
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
@@ -477,7 +516,12 @@ void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uin
   const dim3 grid(static_cast<uint32_t>((cg.nvox + WCH - 1) / WCH),
                   static_cast<uint32_t>((cg.kpad + 16 * WNK - 1) / (16 * WNK)),
                   static_cast<uint32_t>((cg.cout + 15) / 16));
-  hipLaunchKernelGGL(k_conv_wgrad, grid, dim3(64), 0, st, dz, cz, x0, x1, cg, dw, db);
+  if (cg.dil0)
+    hipLaunchKernelGGL((k_conv_wgrad<2>), grid, dim3(64), 0, st, dz, cz, x0, x1, cg, dw, db);
+  else if (cg.up0)
+    hipLaunchKernelGGL((k_conv_wgrad<1>), grid, dim3(64), 0, st, dz, cz, x0, x1, cg, dw, db);
+  else
+    hipLaunchKernelGGL((k_conv_wgrad<0>), grid, dim3(64), 0, st, dz, cz, x0, x1, cg, dw, db);
   prof_end(st, KC_MISC);
 }
 

@@ -39,33 +39,6 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
   return static_cast<uint16_t>(u >> 16);
 }
 
-// Address of input channel ch (8-aligned for vector reads) at tap `tap` of
-// output voxel (s, o0, o1, o2), or nullptr where the input is zero (padding,
-// taps beyond the kernel, odd positions of a dilated x0).
-__device__ __forceinline__ const uint16_t* input_at(const ConvGeom& cg, const uint16_t* x0,
-                                                    const uint16_t* x1, int s, int o0, int o1,
-                                                    int o2, int tap, int ch) {
-  if (tap >= cg.ntaps) return nullptr;
-  int a = 1, b = 1, c = 1;
-  if (cg.ntaps == 27) {
-    a = tap / 9;
-    b = (tap / 3) % 3;
-    c = tap % 3;
-  }
-  const int p0 = o0 * cg.stride + a - 1, p1 = o1 * cg.stride + b - 1, p2 = o2 * cg.stride + c - 1;
-  if (p0 < 0 || p0 >= cg.i0 || p1 < 0 || p1 >= cg.i1 || p2 < 0 || p2 >= cg.i2) return nullptr;
-  if (ch < cg.c0) {
-    if (cg.dil0 && ((p0 | p1 | p2) & 1)) return nullptr;
-    const bool half = cg.up0 || cg.dil0;
-    const int h1 = half ? cg.i1 / 2 : cg.i1, h2 = half ? cg.i2 / 2 : cg.i2;
-    const int h0 = half ? cg.i0 / 2 : cg.i0;
-    const int q0 = half ? p0 >> 1 : p0, q1 = half ? p1 >> 1 : p1, q2 = half ? p2 >> 1 : p2;
-    return x0 + ((((static_cast<long long>(s) * h0 + q0) * h1 + q1) * h2 + q2) * cg.c0 + ch);
-  }
-  return x1 + ((((static_cast<long long>(s) * cg.i0 + p0) * cg.i1 + p1) * cg.i2 + p2) * cg.c1 +
-               (ch - cg.c0));
-}
-
 // X0: how x0 is read (0: full resolution; 1: half resolution, nearest
 // upsampled; 2: half resolution, zero-dilated), fixed per launch.
 template <int NT16, int MT, int X0>

@@ -276,6 +276,21 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
     }
   };
   load_plane(0);
+  // Output voxel (clamped: always valid, used only for live outputs; the
+  // ramp-up planes before the chunk read its first output plane).  With the
+  // warp adjoint fused, u at the output voxel is loaded one plane ahead, so
+  // that the image corners around x + u go out before the next plane's
+  // factors and arrive while the plane is summed.
+  const int oy = min(tl.yb + ly, g.d1 - 1), ox = min(tl.xb + lx, g.d2 - 1);
+  auto out_idx = [&](int zo) { return (min(max(zo, tl.z0), g.d0 - 1) * g.d1 + oy) * g.d2 + ox; };
+  const float* uf = u + static_cast<size_t>(tl.chan) * 3 * g.V;
+  const float* Io = img + static_cast<size_t>(tl.chan) * g.V;
+  float nu[3] = {0.0f, 0.0f, 0.0f};
+  if (FUSED) {
+    const int i = out_idx(tl.z0 - 2 * R);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) nu[c] = uf[static_cast<size_t>(c) * g.V + i];
+  }
   for (int base = 0; base < nplanes; base += W) {
 #pragma unroll
     for (int j = 0; j < W; ++j) {
@@ -295,20 +310,43 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
         }
         // the output voxel's own values, issued before the next plane's
         // factors so that waiting for them does not wait for those too
-        // (clamped indices: always valid, used only for live outputs; the
-        // ramp-up planes before the chunk read its first output plane, which
-        // is needed soon, rather than the previous chunk's planes)
         const int zo = zz - R;
         const int y = tl.yb + ly, x = tl.xb + lx;
-        const int idx = (min(max(zo, tl.z0), g.d0 - 1) * g.d1 + min(y, g.d1 - 1)) * g.d2 +
-                        min(x, g.d2 - 1);
+        const int idx = out_idx(zo);
         const float eJ = atlas[tl.chan * astr + idx];
         const float eI = wimg[tl.chan * wstr + idx];
-        float eu[3] = {0.0f, 0.0f, 0.0f};
+        // fused: the image corners around x + u (zero padding applied when
+        // they are used), then u of the next plane's output voxel
+        float cr[8], ct[3];
+        unsigned cmask = 0u;
         if (FUSED) {
-          const float* f = u + static_cast<size_t>(tl.chan) * 3 * g.V;
+          const int zc = min(max(zo, tl.z0), g.d0 - 1);
+          int ci[3];
+          cell_zero(zc, sane(nu[0]), ci[0], ct[0]);
+          cell_zero(oy, sane(nu[1]), ci[1], ct[1]);
+          cell_zero(ox, sane(nu[2]), ci[2], ct[2]);
+          const int dims[3] = {g.d0, g.d1, g.d2};
+          int lo[3], hi[3];
+          unsigned inl = 0u, inh = 0u;
 #pragma unroll
-          for (int c = 0; c < 3; ++c) eu[c] = f[static_cast<size_t>(c) * g.V + idx];
+          for (int d = 0; d < 3; ++d) {
+            lo[d] = min(max(ci[d], 0), dims[d] - 1);
+            hi[d] = min(max(ci[d] + 1, 0), dims[d] - 1);
+            inl |= static_cast<unsigned>(ci[d] >= 0 && ci[d] < dims[d]) << d;
+            inh |= static_cast<unsigned>(ci[d] + 1 >= 0 && ci[d] + 1 < dims[d]) << d;
+          }
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            const int ka = k >> 2, kb = (k >> 1) & 1, kc = k & 1;
+            const int j0 = ka ? hi[0] : lo[0], j1 = kb ? hi[1] : lo[1], j2 = kc ? hi[2] : lo[2];
+            cr[k] = Io[(j0 * g.d1 + j1) * g.d2 + j2];
+            const bool ok = ((ka ? inh : inl) & 1u) && ((kb ? inh : inl) & 2u) &&
+                            ((kc ? inh : inl) & 4u);
+            cmask |= static_cast<unsigned>(ok) << k;
+          }
+          const int in = out_idx(zo + 1);
+#pragma unroll
+          for (int c = 0; c < 3; ++c) nu[c] = uf[static_cast<size_t>(c) * g.V + in];
         }
         load_plane(p + 1);  // past the chunk: clamped, never staged
         __syncthreads();
@@ -352,9 +390,11 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
             gw[vidx] = static_cast<float>(gI);
           } else {
             const size_t off = static_cast<size_t>(tl.chan) * 3 * g.V;
-            const float* f = u + off;
-            const float* Io = img + static_cast<size_t>(tl.chan) * g.V;
-            const Tri t = sample_zero(Io, g, zo, y, x, eu[0], eu[1], eu[2]);
+            const float* f = uf;
+            float cv[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) cv[k] = ((cmask >> k) & 1u) ? cr[k] : 0.0f;
+            const Tri t = tri_eval(cv, ct[0], ct[1], ct[2]);
             float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f;
             if (rw.on) {
               r0 = reg_at(f, g, idx, zo, y, x, rw, racc);

@@ -425,15 +425,19 @@ struct GaussW {
   float w[17];
 };
 
-// A Gaussian block owns 32 x 32 outputs of a plane: thread (lx, r) holds the
-// kGR consecutive rows r*kGR.. of column lx, so each staged value is reused by
-// four outputs along d1 from registers, and the pass along d2 produces four
-// adjacent outputs from one run of 16-byte LDS reads.
-constexpr int kGX = 32, kGY = 32, kGR = kGY * kGX / kNT;
+// A Gaussian block owns 32 x (8 GR) outputs of a plane: thread (lx, r) holds
+// the GR consecutive rows r*GR.. of column lx, so each staged value is reused
+// by GR outputs along d1 from registers, and the pass along d2 produces four
+// adjacent outputs from one run of 16-byte LDS reads.  GR = 4 (32 x 32
+// tiles); 2 for the widest radii, whose ring of (2R + 1) x GR plane sums
+// would not stay in registers.
+constexpr int kGX = 32;
+constexpr int gauss_rows(int R) { return R <= 6 ? 4 : 2; }
 
 template <int R>
 __global__ __launch_bounds__(kNT) void k_gauss(const float* __restrict__ in,
                                                float* __restrict__ out, MarchGeom mg, GaussW gw) {
+  constexpr int kGR = gauss_rows(R), kGY = kNT * kGR / kGX;
   constexpr int W2 = 2 * R + 1, HX = kGX + 2 * R, HY = kGY + 2 * R;
   constexpr int NV = (4 + 2 * R + 3) / 4;  // 16-byte reads per four d2-outputs
   constexpr int SX = kGX - 4 + 4 * NV;     // LDS row stride: >= HX, a multiple of 4
@@ -595,7 +599,7 @@ bool lncc_bwd_dispatch(const float* fields, const float* w, const float* atlas, 
 template <int R>
 void gauss_r(const float* in, float* out, const GaussW& gw, const Geom& g, int nchan,
              hipStream_t st) {
-  const MarchGeom mg = make_march(g, nchan, R, kGX, kGY);
+  const MarchGeom mg = make_march(g, nchan, R, kGX, kNT * gauss_rows(R) / kGX);
   hipLaunchKernelGGL((k_gauss<R>), dim3(mg.total), dim3(kNT), 0, st, in, out, mg, gw);
 }
 

@@ -232,6 +232,26 @@ __device__ __forceinline__ void st_at(float* __restrict__ base, uint32_t i, floa
   *reinterpret_cast<float*>(reinterpret_cast<char*>(base) + (i << 2)) = v;
 }
 
+// Stores that a lane may skip without a branch: a raw buffer resource over
+// one array of at most 2^31 bytes (one component of a capped volume), and a
+// lane that must not write passes a byte offset of 2^31 or more, which the
+// buffer range check discards.  Every lane then issues the same store
+// instructions, so the in-order memory counter of the wave stays exact at
+// later waits.
+struct MaskedOut {
+  __amdgpu_buffer_rsrc_t r;
+};
+__device__ __forceinline__ MaskedOut masked_out(float* base, uint32_t count) {
+  constexpr int kRawWord3 = 0x00020000;  // untyped 32-bit access (gfx9 family)
+  MaskedOut m;
+  m.r = __builtin_amdgcn_make_buffer_rsrc(base, 0, static_cast<int>(count << 2), kRawWord3);
+  return m;
+}
+__device__ __forceinline__ void store_masked(const MaskedOut& m, uint32_t i, float v, bool on) {
+  const uint32_t off = on ? (i << 2) : 0x80000000u;
+  __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), m.r, off, 0, 0);
+}
+
 // The 8 corners of one field component at a border cell (always in range).
 __device__ __forceinline__ void corners_border(const float* __restrict__ f, const Geom& g,
                                                int base, float (&c)[8]) {

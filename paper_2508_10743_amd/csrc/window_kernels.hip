@@ -124,26 +124,61 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
     for (int j = 0; j < W; ++j) ring[j][c] = 0.0;
   }
   double acc = 0.0;
+  // planes walked: the chunk and R on either side, padded to a multiple of W
+  // so that the unrolled body has no branch around its loads and stores
+  // (padding planes stage clamped values and store nothing)
   const int nplanes = (tl.z1 - tl.z0) + 2 * R;
-  for (int base = 0; base < nplanes; base += W) {
+  const int npad = (nplanes + W - 1) / W * W;
+  // Staged positions of this thread (NPRE per plane): the next plane is
+  // loaded into registers while the current one is summed.  Loads are
+  // unconditional from clamped positions; out-of-volume values become zeros
+  // when staged.
+  constexpr int NPRE = (HY * HX + kNT - 1) / kNT;
+  uint32_t poff[NPRE];
+  bool pin[NPRE];
+#pragma unroll
+  for (int j = 0; j < NPRE; ++j) {
+    const int e = min(tid + j * kNT, HY * HX - 1);
+    const int hy = e / HX, hx = e - hy * HX;
+    const int y = tl.yb - R + hy, x = tl.xb - R + hx;
+    pin[j] = y >= 0 && y < g.d1 && x >= 0 && x < g.d2;
+    poff[j] = static_cast<uint32_t>(min(max(y, 0), g.d1 - 1) * g.d2 + min(max(x, 0), g.d2 - 1));
+  }
+  float pI[NPRE], pJ[NPRE];
+  auto load_plane = [&](int p) {
+    const int zc = min(max(tl.z0 - R + p, 0), g.d0 - 1);
+#pragma unroll
+    for (int j = 0; j < NPRE; ++j) {
+      const uint32_t lin = static_cast<uint32_t>(zc) * static_cast<uint32_t>(g.plane) + poff[j];
+      pI[j] = ld_at(I, lin);
+      pJ[j] = ld_at(Jm, lin);
+    }
+  };
+  // the four factor fields of this subject (stores masked per lane)
+  MaskedOut fo[4];
+  if (FIELDS) {
+    float* F = fields + static_cast<size_t>(tl.chan) * 4 * g.V;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) fo[k] = masked_out(F + static_cast<size_t>(k) * g.V, g.V);
+  }
+  load_plane(0);
+  for (int base = 0; base < npad; base += W) {
 #pragma unroll
     for (int j = 0; j < W; ++j) {
       const int p = base + j;
-      if (p < nplanes) {
+      {
         const int zz = tl.z0 - R + p;
         const bool zin = (zz >= 0) && (zz < g.d0);
-        for (int e = tid; e < HY * HX; e += kNT) {
-          const int hy = e / HX, hx = e - hy * HX;
-          const int y = tl.yb - R + hy, x = tl.xb - R + hx;
-          double vi = 0.0, vj = 0.0;
-          if (zin && y >= 0 && y < g.d1 && x >= 0 && x < g.d2) {
-            const int idx = (zz * g.d1 + y) * g.d2 + x;
-            vi = I[idx];
-            vj = Jm[idx];
+#pragma unroll
+        for (int k = 0; k < NPRE; ++k) {
+          const int e = tid + k * kNT;
+          if (k + 1 < NPRE || e < HY * HX) {
+            const bool in = zin && pin[k];
+            sI[e] = in ? static_cast<double>(pI[k]) : 0.0;
+            sJ[e] = in ? static_cast<double>(pJ[k]) : 0.0;
           }
-          sI[e] = vi;
-          sJ[e] = vj;
         }
+        load_plane(p + 1);
         __syncthreads();
         // row sums along x, two neighbouring outputs per thread: the second
         // slides the first by one (add the entering tap, drop the leaving one)
@@ -187,7 +222,9 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
         }
         const int zo = zz - R;
         const int y = tl.yb + ly, x = tl.xb + lx;
-        if (zo >= tl.z0 && y < g.d1 && x < g.d2) {
+        const bool out = zo >= tl.z0 && zo < tl.z1 && y < g.d1 && x < g.d2;
+        float fv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (out) {
           const double cross = S[4] - S[0] * S[1] * kInvN;
           const double ivar = S[2] - S[0] * S[0] * kInvN;
           const double jvar = S[3] - S[1] * S[1] * kInvN;
@@ -197,13 +234,16 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
           if (FIELDS) {
             const double alpha = 2.0 * cross / den;
             const double beta = 2.0 * cross * cross * jvar / (den * den);
-            const int idx = (zo * g.d1 + y) * g.d2 + x;
-            float* F = fields + static_cast<size_t>(tl.chan) * 4 * g.V;
-            F[idx] = static_cast<float>(alpha);
-            F[g.V + idx] = static_cast<float>(alpha * S[1] * kInvN);
-            F[2 * g.V + idx] = static_cast<float>(beta);
-            F[3 * g.V + idx] = static_cast<float>(beta * S[0] * kInvN);
+            fv[0] = static_cast<float>(alpha);
+            fv[1] = static_cast<float>(alpha * S[1] * kInvN);
+            fv[2] = static_cast<float>(beta);
+            fv[3] = static_cast<float>(beta * S[0] * kInvN);
           }
+        }
+        if (FIELDS) {
+          const uint32_t idx = static_cast<uint32_t>((zo * g.d1 + y) * g.d2 + x);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) store_masked(fo[k], idx, fv[k], out);
         }
         __syncthreads();
       }

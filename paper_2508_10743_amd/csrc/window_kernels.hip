@@ -49,14 +49,16 @@ MarchGeom make_march(const Geom& g, int nchan, int halo, int tx = kTX, int ty = 
   mg.g = g;
   mg.ntx = (g.d2 + tx - 1) / tx;
   mg.nty = (g.d1 + ty - 1) / ty;
-  // long chunks amortise the 2*halo planes of ramp-up; shorter ones give
-  // enough blocks for small cohorts
+  // long chunks amortise the 2*halo planes of ramp-up (d0 split into equal
+  // chunks of at most 96 planes); shorter ones give enough blocks for small
+  // cohorts
   int tz = tuned_tz(TUNE_WINDOW, g, nchan);
   if (tz <= 0) {
-    tz = 64;
+    const int nzc = (g.d0 + 95) / 96;
+    tz = (g.d0 + nzc - 1) / nzc;
     while (tz > 8 && tz > 2 * halo &&
            static_cast<long long>(mg.ntx) * mg.nty * ((g.d0 + tz - 1) / tz) * nchan < 2048)
-      tz /= 2;
+      tz = (tz + 1) / 2;
   }
   mg.tz = tz;
   mg.nz = (g.d0 + tz - 1) / tz;

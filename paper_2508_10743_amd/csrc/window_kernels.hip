@@ -107,8 +107,9 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
                                                   long long wstr, long long astr) {
   constexpr int R = W / 2, HX = kTX + 2 * R, HY = kTY + 2 * R;
   constexpr double kInvN = 1.0 / (W * W * W);
-  __shared__ __attribute__((aligned(16))) double sI[HY * HX];
-  __shared__ __attribute__((aligned(16))) double sJ[HY * HX];
+  // staged planes in FP32 (the inputs' own precision), widened at the taps
+  __shared__ __attribute__((aligned(16))) float sI[HY * HX];
+  __shared__ __attribute__((aligned(16))) float sJ[HY * HX];
   __shared__ double sr[5][HY * kTX];
   __shared__ double sc[5][kTY * kTX];
   __shared__ double red[kNT / 64];
@@ -176,8 +177,8 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
           const int e = tid + k * kNT;
           if (k + 1 < NPRE || e < HY * HX) {
             const bool in = zin && pin[k];
-            sI[e] = in ? static_cast<double>(pI[k]) : 0.0;
-            sJ[e] = in ? static_cast<double>(pJ[k]) : 0.0;
+            sI[e] = in ? pI[k] : 0.0f;
+            sJ[e] = in ? pJ[k] : 0.0f;
           }
         }
         load_plane(p + 1);
@@ -188,12 +189,12 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
           const int hy = e / (kTX / 2), cx = 2 * (e - hy * (kTX / 2));
           // (scalar loads: staging the W + 1 taps in registers would push
           // the kernel past the register budget of three waves per SIMD)
-          const double* rI = sI + hy * HX + cx;
-          const double* rJ = sJ + hy * HX + cx;
+          const float* rI = sI + hy * HX + cx;
+          const float* rJ = sJ + hy * HX + cx;
           double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0;
 #pragma unroll
           for (int k = 0; k < W; ++k) {
-            const double vi = rI[k], vj = rJ[k];
+            const double vi = rI[k], vj = rJ[k];  // exact widening
             a0 += vi;
             a1 += vj;
             a2 += vi * vi;

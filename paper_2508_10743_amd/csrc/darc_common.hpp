@@ -204,6 +204,16 @@ __device__ __forceinline__ float sample_zero_value(const float* __restrict__ img
   return tri_value(c, t0, t1, t2);
 }
 
+// Trilinear weight of corner (a, b, e) of a cell at fractions (t0, t1, t2).
+// Each further factor (1 - t) is applied as w - w t in one fused
+// multiply-add instead of a subtraction and a product; with the corner
+// indices constant after unrolling, the selects fold away.
+__device__ __forceinline__ float corner_weight(int a, int b, int e, float t0, float t1, float t2) {
+  const float w0 = a ? t0 : 1.0f - t0;
+  const float w1 = b ? w0 * t1 : fmaf(-w0, t1, w0);
+  return e ? w1 * t2 : fmaf(-w1, t2, w1);
+}
+
 // Border cell of the position x + u in all three axes.
 struct BorderCell {
   int base;        // linear index of corner (0, 0, 0)

@@ -607,7 +607,7 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
             if (j < nsrc) {
               const float4 p = sdat4[j][ci];
               const float2 q = sdat2[j][ci];
-              const float w = (a ? p.x : 1.0f - p.x) * (b ? p.y : 1.0f - p.y) * (e ? p.z : 1.0f - p.z);
+              const float w = corner_weight(a, b, e, p.x, p.y, p.z);
               r0 += w * p.w;
               r1 += w * q.x;
               r2 += w * q.y;
@@ -939,8 +939,7 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
             for (int j = 0; j < KSLOT; ++j) {
               const float4 p = bd4[cs][j][ci];
               const float2 q = bd2[cs][j][ci];
-              const float w =
-                  (a ? p.x : 1.0f - p.x) * (b ? p.y : 1.0f - p.y) * (e ? p.z : 1.0f - p.z);
+              const float w = corner_weight(a, b, e, p.x, p.y, p.z);
               r0 += w * p.w;
               r1 += w * q.x;
               r2 += w * q.y;

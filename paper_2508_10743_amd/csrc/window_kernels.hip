@@ -263,13 +263,14 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
 // FUSED: continues through the warp adjoint, gu = dD/dI * grad I_orig(x + u)
 // + lam dR/du, and adds lam R(u) to the loss; otherwise writes dD/dI.
 template <int W, bool FUSED>
-__global__ __launch_bounds__(kNT) void k_lncc_bwd(
+__global__ __launch_bounds__(kNT, W <= 9 ? 3 : 2) void k_lncc_bwd(
     const float* __restrict__ fields, const float* __restrict__ wimg,
     const float* __restrict__ atlas, float* __restrict__ gw, const float* __restrict__ img,
     const float* __restrict__ u, float* __restrict__ gu, double* __restrict__ loss,
     int loss_stride, RegW rw, MarchGeom mg, double neg_inv_v, long long wstr, long long astr) {
   constexpr int R = W / 2, HX = kTX + 2 * R, HY = kTY + 2 * R;
-  __shared__ __attribute__((aligned(16))) double sIn[4][HY * HX];
+  // staged factor planes in FP32 (their stored precision), widened at the taps
+  __shared__ __attribute__((aligned(16))) float sIn[4][HY * HX];
   __shared__ double sr[4][HY * kTX];
   __shared__ double sc[4][kTY * kTX];
   __shared__ double red[kNT / 64];
@@ -399,12 +400,12 @@ __global__ __launch_bounds__(kNT) void k_lncc_bwd(
           const int o = hy * kTX + cx;
 #pragma unroll
           for (int c = 0; c < 4; ++c) {
-            // aligned 16-byte pairs, conflict-free across the wave
-            const double2* pr = reinterpret_cast<const double2*>(&sIn[c][hy * HX + cx]);
+            // aligned 8-byte pairs
+            const float2* pr = reinterpret_cast<const float2*>(&sIn[c][hy * HX + cx]);
             double t[W + 1];
 #pragma unroll
             for (int q = 0; q < (W + 1) / 2; ++q) {
-              const double2 a = pr[q];
+              const float2 a = pr[q];
               t[2 * q] = a.x;
               t[2 * q + 1] = a.y;
             }

@@ -493,14 +493,19 @@ __global__ __launch_bounds__(kNT) void k_gauss(const float* __restrict__ in,
   const Tile tl = march_tile<kGX, kGY>(mg);
   const int tid = threadIdx.x, lx = tid % kGX, y0 = (tid / kGX) * kGR;
   const float* src = in + static_cast<size_t>(tl.chan) * g.V;
-  float* dst = out + static_cast<size_t>(tl.chan) * g.V;
+  // outputs written by range-checked stores issued on every plane
+  const MaskedOut dst = masked_out(out + static_cast<size_t>(tl.chan) * g.V, g.V);
   float ring[W2][kGR];
 #pragma unroll
   for (int j = 0; j < W2; ++j)
 #pragma unroll
     for (int r = 0; r < kGR; ++r) ring[j][r] = 0.0f;
+  // planes walked: the chunk and R on either side, padded to a multiple of
+  // W2 so that the unrolled body has no branch around its loads and stores
   const int nplanes = (tl.z1 - tl.z0) + 2 * R;
-  // staged positions: volume offset (replicated border) and LDS slot
+  const int npad = (nplanes + W2 - 1) / W2 * W2;
+  // staged positions: volume offset (replicated border; positions past the
+  // staged plane load a clamped voxel that is never staged) and LDS slot
   int eoff[NE], eslot[NE];
 #pragma unroll
   for (int k = 0; k < NE; ++k) {
@@ -511,25 +516,27 @@ __global__ __launch_bounds__(kNT) void k_gauss(const float* __restrict__ in,
     eoff[k] = y * g.d2 + x;
     eslot[k] = hy * SX + hx;
   }
-  // the next plane is loaded into registers while the current one is filtered
+  // the next plane is loaded into registers while the current one is
+  // filtered; every lane loads (a conditional load would be waited for at
+  // once)
   float pre[NE];
   auto load_plane = [&](int p) {
     const int zc = min(max(tl.z0 - R + p, 0), g.d0 - 1);
 #pragma unroll
     for (int k = 0; k < NE; ++k)
-      if (tid + k * kNT < HY * HX) pre[k] = src[zc * g.plane + eoff[k]];
+      pre[k] = ld_at(src, static_cast<uint32_t>(zc * g.plane + eoff[k]));
   };
   load_plane(0);
   const int x = tl.xb + lx;
-  for (int base = 0; base < nplanes; base += W2) {
+  for (int base = 0; base < npad; base += W2) {
 #pragma unroll
     for (int j = 0; j < W2; ++j) {
       const int p = base + j;
-      if (p < nplanes) {
+      {
 #pragma unroll
         for (int k = 0; k < NE; ++k)
           if (tid + k * kNT < HY * HX) sIn[eslot[k]] = pre[k];
-        if (p + 1 < nplanes) load_plane(p + 1);
+        load_plane(p + 1);
         __syncthreads();
         // along d2: four adjacent outputs per work item
         for (int e = tid; e < HY * GPR; e += kNT) {
@@ -566,18 +573,16 @@ __global__ __launch_bounds__(kNT) void k_gauss(const float* __restrict__ in,
           for (int k = 0; k < W2; ++k) a += gw.w[k] * c[r + k];
           ring[j][r] = a;
         }
-        if (p >= 2 * R && x < g.d2) {
-          const int zo = tl.z0 - 2 * R + p;
+        const int zo = tl.z0 - 2 * R + p;
+        const bool zout = p >= 2 * R && zo < tl.z1 && x < g.d2;
 #pragma unroll
-          for (int r = 0; r < kGR; ++r) {
-            const int y = tl.yb + y0 + r;
-            if (y < g.d1) {
-              float o = 0.0f;
+        for (int r = 0; r < kGR; ++r) {
+          const int y = tl.yb + y0 + r;
+          float o = 0.0f;
 #pragma unroll
-              for (int k = 0; k < W2; ++k) o += gw.w[k] * ring[(j + 1 + k) % W2][r];
-              dst[(zo * g.d1 + y) * g.d2 + x] = o;
-            }
-          }
+          for (int k = 0; k < W2; ++k) o += gw.w[k] * ring[(j + 1 + k) % W2][r];
+          store_masked(dst, static_cast<uint32_t>((zo * g.d1 + y) * g.d2 + x), o,
+                       zout && y < g.d1);
         }
       }
     }

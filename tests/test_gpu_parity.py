@@ -224,6 +224,52 @@ def test_gauss_smooth(dev, sigma, dims):
         assert rel_linf(out[i], O.gauss_smooth(x[i], sigma)) <= TOL_WARP
 
 
+def _guarded(n_elem, dtype, dev, guard=4096, sentinel=7.25):
+    """A buffer of n_elem elements between two guard bands holding a sentinel."""
+    buf = torch.full((guard + n_elem + guard,), sentinel, dtype=dtype, device=dev)
+    return buf, buf[guard:guard + n_elem], guard
+
+
+def _guards_intact(buf, guard, sentinel=7.25):
+    b = h(buf)
+    return bool((b[:guard] == sentinel).all() and (b[-guard:] == sentinel).all())
+
+
+@pytest.mark.parametrize("win", [3, 9, 11])
+def test_range_checked_stores_stay_in_their_arrays(dev, win):
+    """The smoother and the LNCC statistics write through buffer stores whose
+    masked lanes are dropped by the range check: with the output arrays (and
+    the workspace holding the factor fields) placed between guard bands, the
+    guards keep their sentinel and the outputs equal those of ordinary
+    allocations bit for bit.  Ragged shapes give lanes outside the volume in
+    every tile, chunks whose plane count is not a multiple of the window, and
+    padding planes."""
+    dims = (11, 70, 45)
+    n, V = 2, 11 * 70 * 45
+    x = g(random_volume(171, (n, 3) + dims, -1.0, 1.0), dev)
+    ref = D.gauss_smooth(x, 1.5)
+    buf, out, guard = _guarded(n * 3 * V, torch.float32, dev)
+    D._call("darc_smooth3d", D._p(x), D._p(out), n, 3, *dims, D.L.DARC_GAUSS, 1.5, None, None, 0,
+            D._stream())
+    assert _guards_intact(buf, guard)
+    assert torch.equal(out.view(ref.shape), ref)
+
+    imgs, atlas = g(blobs(n, dims, 172), dev), g(blobs(1, dims, 173)[0], dev)
+    loss_ref, gw_ref = D.sim_grad(imgs, atlas, "lncc", win, 1e-5)
+    m = D.METRICS["lncc"]
+    ws_bytes = D.lib().darc_sim_grad_ws_bytes(m, n, *dims)
+    wbuf, ws, wguard = _guarded(ws_bytes, torch.uint8, dev, sentinel=0x5A)
+    gbuf, gw, gguard = _guarded(n * V, torch.float32, dev)
+    loss = torch.zeros(n, dtype=torch.float64, device=dev)
+    D._call("darc_sim_grad", D._p(imgs), D._p(atlas), m, win, 1e-5, D._p(loss), D._p(gw), n,
+            *dims, D._p(ws), ws_bytes, D._stream())
+    assert _guards_intact(wbuf, wguard, sentinel=0x5A)
+    assert _guards_intact(gbuf, gguard)
+    assert torch.equal(gw.view(gw_ref.shape), gw_ref)
+    # the loss is summed by FP64 atomics, in an order that varies by run
+    assert torch.allclose(loss, loss_ref, rtol=1e-12, atol=0.0)
+
+
 def test_diffusion_regulariser(dev):
     x = random_volume(116, (2, 3) + DIMS, -1.0, 1.0)
     out, loss = D.diffusion(g(x, dev), 0.3)

@@ -220,16 +220,39 @@ __global__ __launch_bounds__(kBlock) void k_adam_dev(const float* __restrict__ v
 // ---------------------------------------------------------------- centring
 
 // mean(e) = (1/n) sum_i u_i(e) over the 3V entries e; u_i <- u_i - mean.
+// REGS (n <= kCenterRegs): the n values stay in registers between the sum
+// and the update, so each entry is read once; the sum runs in the same order
+// (unused slots add exact zeros).
+constexpr int kCenterRegs = 16;
+
+template <bool REGS>
 __global__ __launch_bounds__(kBlock) void k_center(float* __restrict__ u,
                                                    float* __restrict__ mean_out, int n,
                                                    long long fs) {
   const long long e = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
   if (e >= fs) return;
-  double acc = 0.0;
-  for (int i = 0; i < n; ++i) acc += static_cast<double>(u[i * fs + e]);
-  const double mean = acc / n;
-  if (mean_out) mean_out[e] = static_cast<float>(mean);
-  for (int i = 0; i < n; ++i) u[i * fs + e] = static_cast<float>(static_cast<double>(u[i * fs + e]) - mean);
+  if (REGS) {
+    // every slot loads (slots past n repeat subject n - 1, then count zero):
+    // a load under a branch would be waited for at once
+    float x[kCenterRegs];
+#pragma unroll
+    for (int i = 0; i < kCenterRegs; ++i) x[i] = u[min(i, n - 1) * fs + e];
+    double acc = 0.0;
+#pragma unroll
+    for (int i = 0; i < kCenterRegs; ++i) acc += i < n ? static_cast<double>(x[i]) : 0.0;
+    const double mean = acc / n;
+    if (mean_out) mean_out[e] = static_cast<float>(mean);
+#pragma unroll
+    for (int i = 0; i < kCenterRegs; ++i)
+      if (i < n) u[i * fs + e] = static_cast<float>(static_cast<double>(x[i]) - mean);
+  } else {
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) acc += static_cast<double>(u[i * fs + e]);
+    const double mean = acc / n;
+    if (mean_out) mean_out[e] = static_cast<float>(mean);
+    for (int i = 0; i < n; ++i)
+      u[i * fs + e] = static_cast<float>(static_cast<double>(u[i * fs + e]) - mean);
+  }
 }
 
 // ------------------------------------------------------------------- atlas
@@ -406,8 +429,12 @@ void launch_step_add(long long* step_dev, long long k, hipStream_t st) {
 void launch_center(float* u, float* mean_out, const Geom& g, int n, hipStream_t st) {
   const long long fs = 3ll * g.V;
   prof_begin(st, KC_CENTER);
-  hipLaunchKernelGGL(k_center, dim3(blocks_for(fs, kBlock)), dim3(kBlock), 0, st, u, mean_out, n,
-                     fs);
+  if (n <= kCenterRegs)
+    hipLaunchKernelGGL(k_center<true>, dim3(blocks_for(fs, kBlock)), dim3(kBlock), 0, st, u,
+                       mean_out, n, fs);
+  else
+    hipLaunchKernelGGL(k_center<false>, dim3(blocks_for(fs, kBlock)), dim3(kBlock), 0, st, u,
+                       mean_out, n, fs);
   prof_end(st, KC_CENTER);
 }
 

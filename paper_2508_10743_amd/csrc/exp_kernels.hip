@@ -746,7 +746,9 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
     const int cs = cplane & 1;
     const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float2 z2 = make_float2(0.0f, 0.0f);
-    for (int i = threadIdx.x; i < MCP; i += ENT) {
+    // threads in reverse order: the cells past ENT fall to the last wave,
+    // which stages no halo voxels
+    for (int i = ENT - 1 - static_cast<int>(threadIdx.x); i < MCP; i += ENT) {
       bcnt[cs][i] = 0;
 #pragma unroll
       for (int k = 0; k < KSLOT; ++k) {

@@ -329,6 +329,24 @@ def test_center_and_atlas(dev):
     assert rel_linf(A2, ref) <= TOL_WARP
 
 
+@pytest.mark.parametrize("n", [1, 16, 17])
+def test_center_register_and_loop_paths(dev, n):
+    """Centring holds up to 16 subjects in registers between the mean and the
+    update and loops over larger cohorts: both sides of that boundary, and
+    one subject (its mean is the field itself, so the centred field is
+    exactly zero), against the oracle."""
+    dims = (5, 9, 33)
+    u = random_velocity(123 + n, n, dims, 2.0)
+    ud = g(u, dev)
+    mean = h(D.center(ud))
+    uh, rmean = O.center(u)
+    assert rel_linf(mean, rmean) <= 1e-6
+    if n == 1:
+        assert np.array_equal(mean, u[0]) and not h(ud).any()
+    else:
+        assert rel_linf(h(ud), uh) <= 1e-6
+
+
 # ------------------------------------------------------------------ errors
 
 

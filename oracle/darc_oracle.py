@@ -502,6 +502,7 @@ class SweepParams:
     k3: int = 20                 # SGD atlas epochs
     atlas_batch: int = 4         # SGD atlas minibatch
     atlas_lr: float = 1e-2
+    sgd_init: str = "warm"       # SGD atlas start: "warm" (A^k) | "initial" (A^0 of main)
 
     def resolved_atlas_mode(self) -> str:
         if self.atlas_mode != "auto":
@@ -521,7 +522,13 @@ def dissimilarity(warped, atlas, p: SweepParams):
 
 def atlas_update(images, u_hat, atlas, p: SweepParams) -> np.ndarray:
     """Step 3 of a sweep: the closed form of the metric (mean for MSE,
-    median for L1) or the minibatch stochastic update (NCC)."""
+    median for L1) or the minibatch stochastic update (NCC).
+
+    Algorithm 1's ``SGD_for_atlas`` opens with ``A = initialize()``, which the
+    paper leaves unspecified.  ``sgd_init = "warm"`` starts from the current
+    atlas A^k; ``"initial"`` takes the literal reading: the same
+    ``initialize()`` as ``main``, i.e. A^0, the mean of the unwarped
+    subjects."""
     mode = p.resolved_atlas_mode()
     if mode == "mean":
         return atlas_mean(images, u_hat)
@@ -529,7 +536,13 @@ def atlas_update(images, u_hat, atlas, p: SweepParams) -> np.ndarray:
         return atlas_median(images, u_hat)
     if mode == "sgd":
         warped = np.stack([warp3d(images[i], u_hat[i]) for i in range(len(images))])
-        return atlas_sgd(warped, atlas, p.k3, p.atlas_batch, p.win, p.ncc_eps, p.atlas_lr,
+        if p.sgd_init == "warm":
+            start = atlas
+        elif p.sgd_init == "initial":
+            start = initial_atlas(images)
+        else:
+            raise ValueError(p.sgd_init)
+        return atlas_sgd(warped, start, p.k3, p.atlas_batch, p.win, p.ncc_eps, p.atlas_lr,
                          p.beta1, p.beta2, p.adam_eps)[0]
     raise ValueError(mode)
 

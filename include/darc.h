@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define DARC_ABI_VERSION 2
+#define DARC_ABI_VERSION 3
 
 /* status codes */
 #define DARC_OK 0
@@ -78,6 +78,11 @@ extern "C" {
 #define DARC_ATLAS_MEAN 0   /* MSE closed form: mean of the warped subjects */
 #define DARC_ATLAS_MEDIAN 1 /* L1 closed form: voxelwise median of the warped subjects */
 #define DARC_ATLAS_SGD 2    /* minibatch Adam on the LNCC of the warped subjects */
+
+/* Start of the stochastic atlas update (Algorithm 1, SGD_for_atlas, opens
+ * with A = initialize(), which the paper leaves unspecified). */
+#define DARC_SGD_INIT_WARM 0    /* from the current atlas A^k */
+#define DARC_SGD_INIT_INITIAL 1 /* from A^0 of main: the mean of the unwarped subjects */
 
 /* smoothing modes */
 #define DARC_GAUSS 0     /* separable Gaussian, replicated border */
@@ -219,7 +224,8 @@ int darc_center(float* u, float* mean_out, int n, int d0, int d1, int d2, void* 
  * darc_atlas_update -- the MSE atlas closed form (Section 3, "Dissimilarity
  * metrics"): A = (1/n) sum_i I_i o phi_hat_i, i.e.
  *   A(x) = (1/n) sum_i I_i(x + u_i(x) - mean(x)),  trilinear, zero padding.
- *   images [n][V] in, u [n][3][V] in.
+ *   images [n][V] in, u [n][3][V] in, or NULL for zero displacements (A is
+ *          then the mean of the unwarped images, the A^0 of Algorithm 1).
  *   mean   [3][V] in, or NULL (u is then taken as already centred).
  *   atlas  [V] out.  Accumulated in FP64.
  * ---------------------------------------------------------------------- */
@@ -453,6 +459,7 @@ typedef struct darc_params {
   int k3;             /* SGD atlas: epochs (>= 1) */
   int atlas_batch;    /* SGD atlas: subjects per minibatch (>= 1) */
   float atlas_lr;     /* SGD atlas: Adam learning rate (betas and eps as above) */
+  int sgd_init;       /* SGD atlas start: DARC_SGD_INIT_WARM or DARC_SGD_INIT_INITIAL */
 } darc_params;
 
 /* sizeof(darc_state) and sizeof(darc_params) as compiled into the library,

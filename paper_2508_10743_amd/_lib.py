@@ -14,7 +14,7 @@ from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_longlong, c_si
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdarc.so")
 
-DARC_ABI_VERSION = 2
+DARC_ABI_VERSION = 3
 
 DARC_OK = 0
 DARC_EINVAL = -1
@@ -28,6 +28,8 @@ DARC_L1 = 2
 DARC_ATLAS_MEAN = 0
 DARC_ATLAS_MEDIAN = 1
 DARC_ATLAS_SGD = 2
+DARC_SGD_INIT_WARM = 0
+DARC_SGD_INIT_INITIAL = 1
 DARC_GAUSS = 0
 DARC_DIFFUSION = 1
 DARC_CENTER_DISPLACEMENT = 0
@@ -82,6 +84,7 @@ class DarcParams(ctypes.Structure):
         ("k3", c_int),
         ("atlas_batch", c_int),
         ("atlas_lr", c_float),
+        ("sgd_init", c_int),
     ]
 
 

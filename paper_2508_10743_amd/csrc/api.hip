@@ -360,7 +360,8 @@ int darc_atlas_update(const float* images, const float* u, const float* mean, fl
                       int d0, int d1, int d2, void* stream) {
   DARC_TRY(check_dims("darc_atlas_update", n, d0, d1, d2));
   if (n < 1) return fail(DARC_EINVAL, "darc_atlas_update: n must be >= 1");
-  if (!images || !u || !atlas) return fail(DARC_EINVAL, "darc_atlas_update: NULL pointer");
+  if (!images || !atlas) return fail(DARC_EINVAL, "darc_atlas_update: NULL pointer");
+  if (!u && mean) return fail(DARC_EINVAL, "darc_atlas_update: mean given without u");
   launch_atlas(images, u, mean, atlas, make_geom(d0, d1, d2), n, as_stream(stream));
   return check_launch("darc_atlas_update");
 }
@@ -1000,6 +1001,8 @@ int check_sweep(const darc_state* st, const darc_params* p) {
       return fail(DARC_EINVAL, "darc_sweep: the stochastic atlas update is for the LNCC metric");
     DARC_TRY(check_sgd("darc_sweep", p->atlas_batch, p->k3, p->win, p->ncc_eps, p->atlas_lr,
                        p->beta1, p->beta2, p->adam_eps));
+    if (p->sgd_init != DARC_SGD_INIT_WARM && p->sgd_init != DARC_SGD_INIT_INITIAL)
+      return fail(DARC_EINVAL, "darc_sweep: unknown sgd_init %d", p->sgd_init);
   } else if (p->atlas_mode != DARC_ATLAS_MEAN) {
     return fail(DARC_EINVAL, "darc_sweep: unknown atlas_mode %d", p->atlas_mode);
   }
@@ -1111,6 +1114,9 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
   } else if (p->atlas_mode == DARC_ATLAS_SGD) {
     float* wall = reinterpret_cast<float*>(w + L.wall);
     launch_warp(st->images, uh, wall, g, n, s);
+    // Algorithm 1's A = initialize() read literally: restart from A^0
+    if (p->sgd_init == DARC_SGD_INIT_INITIAL)
+      launch_atlas(st->images, nullptr, nullptr, st->atlas, g, n, s);
     run_atlas_sgd(wall, st->atlas, n, g, p->atlas_batch < n ? p->atlas_batch : n, p->k3, p->win,
                   p->ncc_eps, p->atlas_lr, p->beta1, p->beta2, p->adam_eps, nullptr, w + L.sgd, s);
   } else {

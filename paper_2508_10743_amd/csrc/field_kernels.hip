@@ -274,11 +274,16 @@ __global__ __launch_bounds__(kBlock) void k_atlas(const float* __restrict__ imag
     m2 = mean[2 * g.V + lin];
   }
   double acc = 0.0;
-  for (int i = 0; i < n; ++i) {
-    const float* f = u + static_cast<size_t>(i) * 3 * g.V;
-    const float* I = images + static_cast<size_t>(i) * g.V;
-    acc += static_cast<double>(sample_zero_value(I, g, x0, x1, x2, f[lin] - m0, f[g.V + lin] - m1,
-                                                 f[2 * g.V + lin] - m2));
+  if (!u) {
+    // zero displacements: the sample at x is the voxel itself
+    for (int i = 0; i < n; ++i) acc += static_cast<double>(images[static_cast<size_t>(i) * g.V + lin]);
+  } else {
+    for (int i = 0; i < n; ++i) {
+      const float* f = u + static_cast<size_t>(i) * 3 * g.V;
+      const float* I = images + static_cast<size_t>(i) * g.V;
+      acc += static_cast<double>(sample_zero_value(I, g, x0, x1, x2, f[lin] - m0,
+                                                   f[g.V + lin] - m1, f[2 * g.V + lin] - m2));
+    }
   }
   atlas[lin] = static_cast<float>(acc / n);
 }

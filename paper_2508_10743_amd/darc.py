@@ -23,6 +23,7 @@ from ._lib import DarcError  # noqa: F401
 
 METRICS = {"mse": L.DARC_MSE, "lncc": L.DARC_LNCC, "l1": L.DARC_L1}
 ATLAS_MODES = {"mean": L.DARC_ATLAS_MEAN, "median": L.DARC_ATLAS_MEDIAN, "sgd": L.DARC_ATLAS_SGD}
+SGD_INITS = {"warm": L.DARC_SGD_INIT_WARM, "initial": L.DARC_SGD_INIT_INITIAL}
 CENTER_MODES = {"displacement": L.DARC_CENTER_DISPLACEMENT, "velocity": L.DARC_CENTER_VELOCITY}
 
 
@@ -217,12 +218,14 @@ def center(u: torch.Tensor) -> torch.Tensor:
     return mean
 
 
-def atlas_update(images: torch.Tensor, u: torch.Tensor,
+def atlas_update(images: torch.Tensor, u: Optional[torch.Tensor],
                  mean: Optional[torch.Tensor] = None) -> torch.Tensor:
-    """A(x) = (1/n) sum_i I_i(x + u_i(x) - mean(x))."""
+    """A(x) = (1/n) sum_i I_i(x + u_i(x) - mean(x)); ``u = None`` gives the
+    mean of the unwarped images (A^0)."""
     n, d0, d1, d2 = _images("images", images)
-    _same("u", u.shape, "expected", (n, 3, d0, d1, d2))
-    _field("u", u)
+    if u is not None:
+        _same("u", u.shape, "expected", (n, 3, d0, d1, d2))
+        _field("u", u)
     if mean is not None:
         _dev("mean", mean, ndim=4)
         _same("mean", mean.shape, "expected", (3, d0, d1, d2))
@@ -357,6 +360,7 @@ class SweepParams:
     k3: int = 20  # stochastic atlas: epochs
     atlas_batch: int = 4  # stochastic atlas: subjects per minibatch
     atlas_lr: float = 1e-2  # stochastic atlas: Adam learning rate
+    sgd_init: str = "warm"  # stochastic atlas start: warm (A^k) | initial (A^0, Alg. 1 literal)
 
     def resolved_atlas_mode(self) -> str:
         if self.atlas_mode != "auto":
@@ -369,7 +373,7 @@ class SweepParams:
                             self.beta1, self.beta2, self.adam_eps,
                             CENTER_MODES[self.center_mode], int(self.reinit_v), self.batch,
                             ATLAS_MODES[self.resolved_atlas_mode()], self.k3, self.atlas_batch,
-                            self.atlas_lr)
+                            self.atlas_lr, SGD_INITS[self.sgd_init])
 
 
 class Cohort:
@@ -400,8 +404,8 @@ class Cohort:
             _same("v0", v0.shape, "expected", shape)
             self.v = v0  # adopted, not copied
         self.u_hat = torch.zeros_like(self.m) if keep_u_hat else None
-        # A^0: the mean of the unwarped subjects (m is still all zeros here)
-        self.atlas = atlas_update(images, self.m)
+        # A^0: the mean of the unwarped subjects
+        self.atlas = atlas_update(images, None)
         self.step = 0
         self.sweeps = 0
         self.step_dev = torch.zeros(1, dtype=torch.int64, device=dev) if device_step else None

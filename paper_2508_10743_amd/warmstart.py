@@ -51,7 +51,7 @@ def make_triples(w: Workload, seeds, params: D.SweepParams, sweeps: int, device)
     for s in seeds:
         imgs = torch.from_numpy(make_cohort(w, seed=int(s))).to(device)
         coh, _ = darc_run(imgs, params, sweeps)
-        out.append(Triple(imgs.mean(0).contiguous(), imgs, coh.v.clone()))
+        out.append(Triple(D.atlas_update(imgs, None), imgs, coh.v.clone()))
     torch.cuda.synchronize()
     return out
 
@@ -92,7 +92,7 @@ def evaluate(net: N.UNet, w: Workload, seeds, params: D.SweepParams, sweeps: int
         t0 = time.perf_counter()
         _, lp = darc_run(imgs, params, sweeps)
         t1 = time.perf_counter()
-        v0 = net(imgs.mean(0).contiguous(), imgs)
+        v0 = net(D.atlas_update(imgs, None), imgs)
         _, lw = darc_run(imgs, params, sweeps, v0=v0)
         t2 = time.perf_counter()
         target = tol * lp[-1]

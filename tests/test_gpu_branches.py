@@ -202,6 +202,24 @@ def test_lncc_sweep_with_sgd_atlas(dev):
     _run_pair(dev, imgs, D.SweepParams(batch=2, **kw), O.SweepParams(**kw), 2, atlas_tol=1e-4)
 
 
+def test_lncc_sweep_with_sgd_atlas_literal_start(dev):
+    """Algorithm 1's ``A = initialize()`` read literally: every stochastic
+    update restarts from A^0 (the mean of the unwarped subjects).  Tolerance
+    as in the warm-started case."""
+    imgs = blobs(5, (12, 10, 40), 417)
+    kw = dict(metric="lncc", win=5, k2=2, atlas_mode="sgd", k3=3, atlas_batch=2,
+              sgd_init="initial")
+    _run_pair(dev, imgs, D.SweepParams(batch=2, **kw), O.SweepParams(**kw), 2, atlas_tol=1e-4)
+
+
+def test_atlas_update_without_displacements_is_the_mean(dev):
+    """u = NULL: A^0, the FP64 mean of the unwarped subjects rounded once."""
+    imgs = blobs(7, (9, 14, 33), 418)
+    A = D.atlas_update(g(imgs, dev), None)
+    ref = imgs.astype(np.float64).mean(axis=0).astype(np.float32)
+    assert np.array_equal(h(A), ref)
+
+
 def test_level_start_is_steps_two_and_three(dev):
     imgs = blobs(3, (12, 10, 40), 414)
     v = random_velocity(415, 3, (12, 10, 40), 1.0, corr_len=3.0)

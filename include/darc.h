@@ -183,6 +183,29 @@ int darc_sim_grad(const float* warped, const float* atlas, int metric, int win, 
                   size_t ws_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
+ * darc_sim_grad_noalloc -- darc_sim_grad without a workspace argument, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * results and errors as darc_sim_grad minus ws/ws_bytes.
+ *
+ * The LNCC gradient's scratch (darc_sim_grad_ws_bytes: 16 bytes per
+ * subject-voxel) lives in a file-scope device array of
+ * darc_sim_grad_noalloc_max_bytes() = 128 MiB that every GPU the library runs
+ * on holds until the process ends; its address is looked up once per device
+ * (hipGetSymbolAddress) on the first call there.  The call itself allocates
+ * nothing.  A call that would need more scratch (more than 8 388 608
+ * subject-voxels, e.g. one 160 x 192 x 224 subject fits, two do not) fails
+ * with DARC_EWORKSPACE and enqueues nothing.  Every call on one GPU shares
+ * that GPU's array and overwrites it completely before reading it (nothing
+ * needs to start at zero); calls that overlap on one GPU (different streams,
+ * or threads) race on it and must be ordered by the caller.
+ * ---------------------------------------------------------------------- */
+size_t darc_sim_grad_noalloc_max_bytes(void);
+int darc_sim_grad_noalloc(const float* warped, const float* atlas, int metric, int win, float eps,
+                          double* loss, float* g_warped, int n, int d0, int d1, int d2,
+                          void* stream);
+
+/* ------------------------------------------------------------------------
  * darc_smooth3d -- smoothing of ncomp-component volumes [n][ncomp][V].
  *
  *   DARC_GAUSS (param = sigma > 0): out = G_sigma * in per component,

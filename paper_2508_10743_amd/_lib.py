@@ -110,6 +110,8 @@ PROTOTYPES = {
     "darc_warp3d_bwd": (c_int, [_P, _P, _P, _P, _I, _I, _I, _I, _P]),
     "darc_sim_grad_ws_bytes": (c_size_t, [_I, _I, _I, _I, _I]),
     "darc_sim_grad": (c_int, [_P, _P, _I, _I, c_float, _P, _P, _I, _I, _I, _I, _P, _Z, _P]),
+    "darc_sim_grad_noalloc_max_bytes": (c_size_t, []),
+    "darc_sim_grad_noalloc": (c_int, [_P, _P, _I, _I, c_float, _P, _P, _I, _I, _I, _I, _P]),
     "darc_smooth3d": (c_int, [_P, _P, _I, _I, _I, _I, _I, _I, c_float, _P, _P, _Z, _P]),
     "darc_adam_step": (c_int, [_P, _P, _P, _P, c_longlong, c_longlong, c_float, c_double,
                                c_double, c_float, _P]),

@@ -302,6 +302,78 @@ int darc_sim_grad(const float* warped, const float* atlas, int metric, int win, 
   return check_launch("darc_sim_grad");
 }
 
+}  // extern "C"
+
+// ------------------------------------------- dissimilarity without allocation
+
+namespace {
+
+// The scratch of darc_sim_grad_noalloc: one array per GPU, held until the
+// process ends.  Host code never passes `scratch` itself to a kernel (on the
+// host the name is a stand-in, not a device address): every use goes through
+// the address hipGetSymbolAddress returns for the current device.
+constexpr size_t kNoallocScratchBytes = static_cast<size_t>(128) << 20;
+__device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per device, filled on first use
+
+int scratch_for_current_device(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess)
+    return fail(DARC_EHIP, "darc_sim_grad_noalloc: hipGetDevice: %s", hipGetErrorString(e));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_ptr.empty()) {
+    int count = 0;
+    e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count < 1)
+      return fail(DARC_EHIP, "darc_sim_grad_noalloc: hipGetDeviceCount: %s",
+                  hipGetErrorString(e));
+    g_scratch_ptr.assign(static_cast<size_t>(count), nullptr);
+  }
+  if (dev < 0 || dev >= static_cast<int>(g_scratch_ptr.size()))
+    return fail(DARC_EHIP, "darc_sim_grad_noalloc: device %d out of range", dev);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(DARC_EHIP, "darc_sim_grad_noalloc: hipGetSymbolAddress: %s",
+                  hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return DARC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t darc_sim_grad_noalloc_max_bytes(void) { return kNoallocScratchBytes; }
+
+int darc_sim_grad_noalloc(const float* warped, const float* atlas, int metric, int win, float eps,
+                          double* loss, float* g_warped, int n, int d0, int d1, int d2,
+                          void* stream) {
+  DARC_TRY(check_dims("darc_sim_grad_noalloc", n, d0, d1, d2));
+  const size_t need = (g_warped && n > 0) ? darc_sim_grad_ws_bytes(metric, n, d0, d1, d2) : 0;
+  if (need > kNoallocScratchBytes)
+    return fail(DARC_EWORKSPACE,
+                "darc_sim_grad_noalloc: %d subjects of %d x %d x %d need %zu bytes of scratch, "
+                "more than the %zu held per GPU; split the batch or use darc_sim_grad",
+                n, d0, d1, d2, need, kNoallocScratchBytes);
+  void* ws = nullptr;
+  if (need > 0) DARC_TRY(scratch_for_current_device(&ws));
+  const int rc = darc_sim_grad(warped, atlas, metric, win, eps, loss, g_warped, n, d0, d1, d2, ws,
+                               need > 0 ? kNoallocScratchBytes : 0, stream);
+  if (rc != DARC_OK) {
+    // name this entry point in the message darc_sim_grad left
+    const std::string msg = g_err;
+    return fail(rc, "darc_sim_grad_noalloc: %s", msg.c_str());
+  }
+  return rc;
+}
+
 // ------------------------------------------------------------- smoothing
 
 int darc_smooth3d(const float* in, float* out, int n, int ncomp, int d0, int d1, int d2, int mode,

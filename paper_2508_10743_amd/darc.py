@@ -169,6 +169,24 @@ def sim_grad(warped: torch.Tensor, atlas: torch.Tensor, metric: str = "mse", win
     return loss, g
 
 
+def sim_grad_noalloc(warped: torch.Tensor, atlas: torch.Tensor, loss: torch.Tensor,
+                     g: Optional[torch.Tensor], metric: str = "lncc", win: int = 9,
+                     eps: float = 1e-5) -> None:
+    """``sim_grad`` into caller-provided outputs through the entry point that
+    allocates nothing (its scratch is the library's per-GPU array):
+    ``loss[i] += D_i`` (FP64 ``[n]``) and, if ``g`` is given, g = dD/dwarped."""
+    n, d0, d1, d2 = _images("warped", warped)
+    _dev("atlas", atlas, ndim=3)
+    _same("atlas", atlas.shape, "volume", (d0, d1, d2))
+    _dev("loss", loss, dtype=torch.float64, ndim=1)
+    _same("loss", loss.shape, "expected", (n,))
+    if g is not None:
+        _images("g", g)
+        _same("g", g.shape, "warped", warped.shape)
+    _call("darc_sim_grad_noalloc", _p(warped), _p(atlas), METRICS[metric], win, eps, _p(loss),
+          _p(g), n, d0, d1, d2, _stream())
+
+
 # ----------------------------------------------------------------- smoothing
 
 

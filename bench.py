@@ -6,11 +6,17 @@ iterations per subject (Exp by scaling and squaring, warp, dissimilarity and
 regulariser, adjoint through warp and squarings, Adam, Gaussian smoothing of
 v), then Exp, centrality activation, mean atlas and group loss.  Inputs are a
 seeded synthetic cohort already resident in GPU memory when timing starts.
+The default workload is the full-resolution level of the 200-subject cohort
+(200 x 160x192x224, LNCC 9^3, Gaussian sigma 1.5 on v), 64 subjects per
+launch.
 
 Prints one JSON line: subject-voxel-iterations per second (n * V * K2 per
 sweep time), the roofline position of the kernel class that takes the most
-time, the per-class achieved bandwidth, and the FP64 CPU oracle timed on a
-bounded sample of the same workload on one host core.
+time (against the vendor's 8 TB/s and against the copy bandwidth measured
+live), the per-class achieved bandwidth, the brain workload
+(16 x 160x192x160) as a second line of figures, the measured time-to-loss of
+the batched, warm-started form against plain DARC, and the FP64 CPU oracle
+timed on a bounded sample of the same workload on one host core.
 """
 
 import argparse
@@ -26,7 +32,14 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, vendor figure
 BF16_PEAK_FLOPS = 2.5e15  # MI355X dense BF16 matrix-core peak, vendor figure
 
-DEFAULT_WORKLOAD = "brain-16x160x192x160-lncc9"
+DEFAULT_WORKLOAD = "compartments-200x160x192x224-lncc9"
+SECOND_WORKLOAD = "brain-16x160x192x160-lncc9"
+TTL_WORKLOAD = "blobs-4x96x112x96-mse"
+MAX_BATCH = 64  # subjects per launch for cohorts larger than this
+
+
+def log(msg):
+    print(f"# {msg}", file=sys.stderr, flush=True)
 
 
 def algorithmic_bytes(w, batch):
@@ -160,78 +173,180 @@ def time_extras(D, cohort, w, reps=3):
     res["unet_train_step_2"] = {"ms": round(ms, 3), "GFLOP": round(flop2 / 1e9, 1),
                                 "TFLOP/s": round(flop2 / (ms * 1e-3) / 1e12, 1),
                                 "frac_bf16_peak": round(flop2 / (ms * 1e-3) / BF16_PEAK_FLOPS, 4)}
-    res["warm_start"] = warm_start_trial(dev=imgs.device)
     return res
 
 
-def warm_start_trial(dev, n_train=64, n_test=8, epochs=10):
-    """Time-to-loss of the learned warm start on 4 x 32^3 blob cohorts:
-    train the U-Net on DARC's velocities (20 sweeps of 20 steps) for n_train
-    cohorts, then on n_test held-out cohorts run the C1 schedule (10 sweeps
-    of 5 steps) from v = 0 and from the network's velocities, and count the
-    sweeps until the group loss is within 0.5 % of plain DARC's final one."""
-    from synthetic.cohorts import WORKLOADS
+def attainable_bandwidth(dev, gib=4, reps=5):
+    """Copy, read-only and write-only streams of this library's own kernels
+    over `gib` GiB buffers: the bandwidth this GPU reaches, in GB/s (best of
+    `reps` timed launches after one untimed one)."""
+    import ctypes
+
+    import torch
 
     from paper_2508_10743_amd import darc as D
-    from paper_2508_10743_amd import warmstart as WS
 
-    w = WORKLOADS["blobs-4x32^3-mse"]
-    t0 = time.perf_counter()
-    train = WS.make_triples(w, range(2000, 2000 + n_train), D.SweepParams(k2=20), 20, dev)
-    t1 = time.perf_counter()
-    net, hist = WS.train(train, epochs=epochs, lr=1e-3)
-    torch_sync = __import__("torch").cuda.synchronize
-    torch_sync()
-    t2 = time.perf_counter()
-    r = WS.evaluate(net, w, range(3000, 3000 + n_test), D.SweepParams(k2=5), 10, dev)
-    return {"train_cohorts": n_train, "epochs": epochs, "triples_s": round(t1 - t0, 2),
-            "train_s": round(t2 - t1, 2), "train_loss_first_last": [round(hist[0], 5),
-                                                                   round(hist[-1], 5)],
-            "sweeps_to_plain_final": {"plain": r["plain_sweeps"], "warm": r["warm_sweeps"]},
-            "seconds_to_plain_final": {"plain": round(r["plain_s"], 4),
-                                       "warm": round(r["warm_s"], 4)},
-            "loss_after_1_sweep": {"plain": r["plain_first"], "warm": r["warm_first"]}}
+    lb = D.lib()
+    nbytes = gib << 30
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+    b = torch.empty_like(a)
+    sink = torch.zeros(1, dtype=torch.float32, device=dev)
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    pa, pb, ps = (ctypes.c_void_p(t.data_ptr()) for t in (a, b, sink))
+    cases = {
+        "copy": (lambda: lb.darc_bw_copy(pa, pb, nbytes, 0, st), 2 * nbytes),
+        "read": (lambda: lb.darc_bw_read(pa, nbytes, ps, 0, st), nbytes),
+        "write": (lambda: lb.darc_bw_write(pb, nbytes, 0, st), nbytes),
+    }
+    out = {}
+    for name, (fn, moved) in cases.items():
+        assert fn() == 0, name
+        best = None
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            assert fn() == 0, name
+            e1.record()
+            e1.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[name] = round(moved / (best * 1e-3) / 1e9, 1)
+    torch.cuda.synchronize()
+    del a, b, sink
+    torch.cuda.empty_cache()
+    out["buffer_GiB"] = gib
+    return out
 
 
-def cpu_baseline(w, seconds_hint=True):
-    """The FP64 oracle on one subject's central crop (1/8 of the voxels),
-    two inner iterations, one thread."""
+def cpu_baseline(w, max_crop=(40, 96, 112), n_sub=2):
+    """The FP64 oracle on a bounded sample of workload `w`: one whole sweep
+    (K2 inner iterations per subject, then Exp, centring, the atlas update
+    and the group loss) of `n_sub` subjects cropped to at most `max_crop`
+    about the volume centre, on one thread, in subject-voxel-iterations/s."""
+    import platform
+
     import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle import darc_oracle as O
     from synthetic.cohorts import make_cohort
 
-    imgs = make_cohort(w, n=2)
-    d0, d1, d2 = w.dims
-    sl = (slice(d0 // 4, d0 // 4 + d0 // 2), slice(d1 // 4, d1 // 4 + d1 // 2),
-          slice(d2 // 4, d2 // 4 + d2 // 2))
-    subj = imgs[0][sl].astype(np.float64)
-    atlas = imgs[1][sl].astype(np.float64)
+    imgs = make_cohort(w, n=n_sub)
+    sl = tuple(slice((d - min(d, c)) // 2, (d - min(d, c)) // 2 + min(d, c))
+               for d, c in zip(w.dims, max_crop))
+    sub = np.stack([im[sl] for im in imgs]).astype(np.float64)
     p = O.SweepParams(metric=w.metric, win=w.win, ncc_eps=w.ncc_eps, lam=w.lam,
                       smooth_sigma=w.smooth_sigma, n_sq=w.n_sq, k2=w.k2)
-    iters = 2
+    z = np.zeros((n_sub, 3) + sub.shape[1:])
     with threadpool_limits(limits=1):
-        v = np.zeros((3,) + subj.shape)
-        m = np.zeros_like(v)
-        s = np.zeros_like(v)
         t0 = time.perf_counter()
-        for k in range(iters):
-            _, g = O.subject_loss_grad(subj, v, atlas, p)
-            v, m, s = O.adam_step(v, m, s, g, k + 1)
-            if p.smooth_sigma > 0:
-                v = O.gauss_smooth(v, p.smooth_sigma)
+        O.sweep(sub, z, z, z, 0, O.initial_atlas(sub), p)
         dt = time.perf_counter() - t0
-    vox = subj.size
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {
-        "value": vox * iters / dt,
+        "value": n_sub * sub[0].size * w.k2 / dt,
         "unit": "subject-voxel-iters/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": f"1 subject, central {subj.shape[0]}x{subj.shape[1]}x{subj.shape[2]} crop "
-                  f"of {w.name}, {iters} inner iterations (Exp, warp, dissimilarity, adjoint, "
-                  f"Adam, smoothing), FP64 NumPy, {dt:.1f} s",
+        "sample": f"one oracle sweep of {n_sub} subjects of {w.name} cropped to "
+                  f"{'x'.join(str(d) for d in sub.shape[1:])} about the centre: {w.k2} inner "
+                  f"iterations each (Exp, warp, dissimilarity, adjoint, Adam, smoothing), then "
+                  f"Exp, centring, atlas and group loss; FP64 NumPy on one thread, {dt:.1f} s",
+        "host": {"cpu_model": model or platform.processor(), "cpu_count": os.cpu_count()},
     }
+
+
+def run_workload(D, w, batch, steps, warmup, dev, profile=True, graph=False, keep=False,
+                 workers=1):
+    """Generate workload `w`, run `warmup` untimed sweeps and `steps` timed
+    ones; returns (result dict, cohort or None)."""
+    import torch
+
+    from synthetic.cohorts import make_cohort
+
+    t0 = time.perf_counter()
+    images = torch.from_numpy(make_cohort(w, workers=workers)).to(dev)
+    log(f"generated {w.name} in {time.perf_counter() - t0:.1f} s ({workers} processes)")
+    params = D.SweepParams(metric=w.metric, win=w.win, ncc_eps=w.ncc_eps, lam=w.lam,
+                           smooth_sigma=w.smooth_sigma, n_sq=w.n_sq, k2=w.k2, lr=w.lr,
+                           beta1=w.beta1, beta2=w.beta2, adam_eps=w.adam_eps, batch=batch)
+    cohort = D.Cohort(images, params, device_step=graph)
+    torch.cuda.synchronize()
+    for i in range(warmup):
+        cohort.sweep()
+        torch.cuda.synchronize()
+        log(f"{w.name}: warmup sweep {i + 1}/{warmup}: F = {cohort.group_loss():.6f}")
+    if profile:
+        D.profile_reset()
+        D.profile_enable(True)
+    torch.cuda.synchronize()
+    if graph:
+        sweep_graph = cohort.capture()
+        torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        if graph:
+            sweep_graph.replay()
+        else:
+            cohort.sweep()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    log(f"{w.name}: {steps} timed sweeps in {t1 - t0:.2f} s, F = {cohort.group_loss():.6f}")
+    kernels = {}
+    if profile:
+        D.profile_enable(False)
+        prof = D.profile_collect()
+        algo = algorithmic_bytes(w, batch)
+        for cls, (cnt, ms) in prof.items():
+            if cnt == 0:
+                continue
+            entry = {"launches": cnt, "ms": round(ms, 4), "avg_us": round(1e3 * ms / cnt, 2)}
+            if cls in algo:
+                entry["algo_GB_per_launch"] = round(algo[cls] * steps / cnt / 1e9, 4)
+                entry["GB/s"] = round(algo[cls] * steps / (ms * 1e-3) / 1e9, 1)
+            kernels[cls] = entry
+    ms_per_step = (t1 - t0) * 1e3 / steps
+    res = {
+        "workload": w.name,
+        "ms_per_step": round(ms_per_step, 3),
+        "value": round(w.n * w.voxels * w.k2 / (ms_per_step * 1e-3), 1),
+        "group_loss": cohort.group_loss(),
+        "kernels": kernels,
+    }
+    if not keep:
+        del cohort, images
+        torch.cuda.empty_cache()
+        cohort = None
+    return res, cohort
+
+
+def roofline_of(w, kernels, attainable):
+    """Roofline position of the kernel class that takes the most time."""
+    dom = max((c for c in kernels if "GB/s" in kernels[c]), key=lambda c: kernels[c]["ms"])
+    achieved = kernels[dom]["GB/s"]
+    out = {
+        "kernel": dom,
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": measured_traffic(w.name, dom),
+        "traffic_unit": "GB per launch (HBM, from counters)",
+        "algo_GB_per_launch": kernels[dom]["algo_GB_per_launch"],
+        "avg_us": kernels[dom]["avg_us"],
+    }
+    if attainable:
+        out["attainable_copy"] = attainable["copy"]
+        out["frac_attainable"] = round(achieved / attainable["copy"], 4)
+    return out
 
 
 def main():
@@ -240,14 +355,22 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed sweeps")
     ap.add_argument("--warmup", type=int, default=1, help="untimed sweeps before timing")
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
-    ap.add_argument("--batch", type=int, default=0, help="subjects per launch (0 = all)")
+    ap.add_argument("--batch", type=int, default=None,
+                    help=f"subjects per launch (default: all, at most {MAX_BATCH})")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true", help="skip the per-kernel event timing")
+    ap.add_argument("--no-second", action="store_true",
+                    help=f"skip the second workload ({SECOND_WORKLOAD})")
+    ap.add_argument("--no-time-to-loss", action="store_true",
+                    help="skip the warm-start time-to-loss trial")
+    ap.add_argument("--no-attainable", action="store_true",
+                    help="skip the copy/read/write bandwidth measurement")
     ap.add_argument("--graph", action="store_true",
                     help="capture one sweep in a HIP graph and time its replays")
     ap.add_argument("--extras", action="store_true",
                     help="also time the method's other branches (median and stochastic atlas, "
-                         "one-shot segmentation, pyramid resampling) on the same cohort")
+                         "one-shot segmentation, pyramid resampling, the network) on the same "
+                         "cohort")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device-to-device copy first (a known-size kernel for "
                          "calibrating HBM byte counters)")
@@ -258,10 +381,18 @@ def main():
               f"no multi-GPU mode (asked for --gpus {args.gpus})", file=sys.stderr)
         sys.exit(2)
 
-    from synthetic.cohorts import WORKLOADS, make_cohort
+    from synthetic.cohorts import WORKLOADS
 
     w = WORKLOADS[args.workload]
-    cpu = None if args.no_cpu_baseline else cpu_baseline(w)
+    batch = args.batch if args.batch is not None else (MAX_BATCH if w.n > MAX_BATCH else 0)
+    # large cohorts are generated in a process pool (same images), sized to the
+    # CPU share of one GPU
+    workers = min(16, os.cpu_count() or 1)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle sample")
+        cpu = cpu_baseline(w)
+        log(f"CPU oracle: {cpu['sample']}")
 
     import torch
 
@@ -269,16 +400,11 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
-    print(f"# generating {w.name}", file=sys.stderr, flush=True)
-    # large cohorts are generated in a process pool (same images), sized to the
-    # CPU share of one GPU
-    workers = min(16, os.cpu_count() or 1) if w.n >= 32 else 1
-    images = torch.from_numpy(make_cohort(w, workers=workers)).to(dev)
-    params = D.SweepParams(metric=w.metric, win=w.win, ncc_eps=w.ncc_eps, lam=w.lam,
-                           smooth_sigma=w.smooth_sigma, n_sq=w.n_sq, k2=w.k2, lr=w.lr,
-                           beta1=w.beta1, beta2=w.beta2, adam_eps=w.adam_eps, batch=args.batch)
-    cohort = D.Cohort(images, params, device_step=args.graph)
-    torch.cuda.synchronize()
+    D.lib()
+    attainable = None
+    if not args.no_attainable:
+        attainable = attainable_bandwidth(dev)
+        log(f"attainable bandwidth (GB/s): {attainable}")
     if args.calib_copy:
         a = torch.full((1 << 28,), 1.0, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
@@ -286,70 +412,47 @@ def main():
         b.copy_(a)  # reads 1 GiB, writes 1 GiB
         torch.cuda.synchronize()
         del a, b
-    for i in range(args.warmup):
-        cohort.sweep()
-        torch.cuda.synchronize()
-        print(f"# warmup sweep {i + 1}/{args.warmup}: F = {cohort.group_loss():.6f}",
-              file=sys.stderr, flush=True)
 
-    # per-kernel events cannot be recorded inside a captured graph
     profile = not args.no_profile and not args.graph
-    if profile:
-        D.profile_reset()
-        D.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    if args.graph:
-        # one sweep captured into a HIP graph, replayed per timed step
-        graph = cohort.capture()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            graph.replay()
-    else:
-        for _ in range(args.steps):
-            cohort.sweep()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    kernels = {}
-    roofline = None
-    if profile:
-        D.profile_enable(False)
-        prof = D.profile_collect()
-        algo = algorithmic_bytes(w, args.batch)
-        for cls, (cnt, ms) in prof.items():
-            if cnt == 0:
-                continue
-            entry = {"launches": cnt, "ms": round(ms, 4), "avg_us": round(1e3 * ms / cnt, 2)}
-            if cls in algo:
-                gbs = algo[cls] * args.steps / (ms * 1e-3) / 1e9
-                entry["algo_GB_per_launch"] = round(algo[cls] * args.steps / cnt / 1e9, 4)
-                entry["GB/s"] = round(gbs, 1)
-            kernels[cls] = entry
-        dom = max((c for c in kernels if "GB/s" in kernels[c]), key=lambda c: kernels[c]["ms"])
-        achieved = kernels[dom]["GB/s"]
-        roofline = {
-            "kernel": dom,
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(w.name, dom),
-            "traffic_unit": "GB per launch (HBM, from counters)",
-        }
-
+    res, cohort = run_workload(D, w, batch, args.steps, args.warmup, dev, profile=profile,
+                               graph=args.graph, keep=args.extras,
+                               workers=workers if w.n >= 32 else 1)
+    roofline = roofline_of(w, res["kernels"], attainable) if profile else None
     extras = time_extras(D, cohort, w) if args.extras else None
-    ms_per_step = (t1 - t0) * 1e3 / args.steps
-    value = w.n * w.voxels * w.k2 / (ms_per_step * 1e-3)
+    del cohort
+    torch.cuda.empty_cache()
+
+    second = None
+    if not args.no_second and args.workload == DEFAULT_WORKLOAD:
+        w2 = WORKLOADS[SECOND_WORKLOAD]
+        r2, _ = run_workload(D, w2, 0, max(3, args.steps // 4), 1, dev, profile=True,
+                             workers=workers)
+        second = {k: r2[k] for k in ("workload", "ms_per_step", "value", "group_loss")}
+        second["n_subjects"] = w2.n
+        second["dims"] = list(w2.dims)
+        second["roofline"] = roofline_of(w2, r2["kernels"], attainable)
+        second["kernels"] = r2["kernels"]
+
+    ttl = None
+    if not args.no_time_to_loss and args.workload == DEFAULT_WORKLOAD:
+        from paper_2508_10743_amd import warmstart as WS
+
+        log(f"time-to-loss trial on {TTL_WORKLOAD}")
+        t0 = time.perf_counter()
+        ttl = WS.time_to_loss(WORKLOADS[TTL_WORKLOAD], range(2000, 2064), range(3000, 3008), dev,
+                              workers=workers)
+        log(f"time-to-loss trial took {time.perf_counter() - t0:.1f} s: plain "
+            f"{ttl['plain_s']:.3f} s, warm {ttl.get('warm_s')} s "
+            f"({ttl['warm_reached']}/{ttl['test_cohorts']} reached)")
+
     out = {
         "metric": "subject-voxel-iters/s per DARC sweep",
-        "value": round(value, 1),
+        "value": res["value"],
         "unit": "subject-voxel-iters/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": res["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -357,6 +460,7 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": w.name,
+            "level": "full resolution",
             "n_subjects": w.n,
             "dims": list(w.dims),
             "metric": f"{w.metric}{w.win if w.metric == 'lncc' else ''}",
@@ -364,12 +468,15 @@ def main():
             "n_sq": w.n_sq,
             "smooth_sigma": w.smooth_sigma,
             "lam": w.lam,
-            "batch": args.batch or w.n,
+            "batch": batch or w.n,
         },
-        "group_loss": cohort.group_loss(),
+        "group_loss": res["group_loss"],
         "roofline": roofline,
+        "attainable_GBs": attainable,
         "cpu_baseline": cpu,
-        "kernels": kernels,
+        "time_to_loss": ttl,
+        "second_workload": second,
+        "kernels": res["kernels"],
     }
     if extras is not None:
         out["extras"] = extras

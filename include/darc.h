@@ -529,6 +529,23 @@ int darc_profile_num_classes(void);
 const char* darc_profile_name(int cls);
 int darc_profile_collect(long long* counts, double* ms, int max_classes);
 
+/* ------------------------------------------------------------------------
+ * Attainable HBM bandwidth (measurement helpers, not part of the method):
+ * plain streams over caller buffers that read the path's kernels against what
+ * this GPU reaches, beside the vendor's peak.  `bytes` is a multiple of 16 and
+ * every pointer 16-byte aligned; blocks = 0 picks 2048 blocks of 256 threads
+ * (grid-stride loops, four 16-byte vectors per thread and trip).
+ *   darc_bw_copy : dst = src (reads and writes `bytes`).
+ *   darc_bw_read : reads `bytes` of non-negative floats from src; sink [1]
+ *                  is written only for a negative sum (never, in effect).
+ *   darc_bw_write: fills dst with a per-thread pattern (writes `bytes`).
+ * Return DARC_EINVAL on a bad argument (nothing enqueued), DARC_EHIP on a
+ * launch failure; darc_last_error() is not set by these three.
+ * ---------------------------------------------------------------------- */
+int darc_bw_copy(const void* src, void* dst, size_t bytes, int blocks, void* stream);
+int darc_bw_read(const void* src, size_t bytes, float* sink, int blocks, void* stream);
+int darc_bw_write(void* dst, size_t bytes, int blocks, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -155,6 +155,9 @@ PROTOTYPES = {
     "darc_profile_num_classes": (c_int, []),
     "darc_profile_name": (c_char_p, [_I]),
     "darc_profile_collect": (c_int, [POINTER(c_longlong), POINTER(c_double), _I]),
+    "darc_bw_copy": (c_int, [_P, _P, _Z, _I, _P]),
+    "darc_bw_read": (c_int, [_P, _Z, _P, _I, _P]),
+    "darc_bw_write": (c_int, [_P, _Z, _I, _P]),
 }
 
 

@@ -1,0 +1,113 @@
+// Attainable HBM bandwidth on this GPU: a copy, a read-only and a write-only
+// stream over caller buffers.  Not part of the method: the path's kernels are
+// read against what these reach as well as against the vendor's peak.
+//
+// Each thread moves four 16-byte vectors per loop trip (all four loads
+// issued before any is used), over a grid-stride loop; `blocks` = 0 picks
+// 2048 blocks of 256 threads (eight per CU).  The read stream folds every
+// value into a sum that reaches memory only under a condition the data never
+// meets, so no load can be dropped.
+#include "darc.h"
+#include "darc_kernels.hpp"
+
+namespace darc {
+namespace {
+
+constexpr int kBT = 256;
+constexpr int kUnroll = 4;
+
+__global__ __launch_bounds__(kBT) void k_bw_copy(const float4* __restrict__ src,
+                                                 float4* __restrict__ dst, long long n4) {
+  const long long stride = static_cast<long long>(gridDim.x) * kBT;
+  long long i = static_cast<long long>(blockIdx.x) * kBT + threadIdx.x;
+  for (; i + (kUnroll - 1) * stride < n4; i += kUnroll * stride) {
+    float4 r[kUnroll];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) r[k] = src[i + k * stride];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) dst[i + k * stride] = r[k];
+  }
+  for (; i < n4; i += stride) dst[i] = src[i];
+}
+
+__global__ __launch_bounds__(kBT) void k_bw_read(const float4* __restrict__ src, long long n4,
+                                                 float* __restrict__ sink) {
+  const long long stride = static_cast<long long>(gridDim.x) * kBT;
+  long long i = static_cast<long long>(blockIdx.x) * kBT + threadIdx.x;
+  float acc = 0.0f;
+  for (; i + (kUnroll - 1) * stride < n4; i += kUnroll * stride) {
+    float4 r[kUnroll];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) r[k] = src[i + k * stride];
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) acc += (r[k].x + r[k].y) + (r[k].z + r[k].w);
+  }
+  for (; i < n4; i += stride) {
+    const float4 r = src[i];
+    acc += (r.x + r.y) + (r.z + r.w);
+  }
+  if (acc == -1.0f) sink[0] = acc;  // buffers hold non-negative values
+}
+
+__global__ __launch_bounds__(kBT) void k_bw_write(float4* __restrict__ dst, long long n4) {
+  const long long stride = static_cast<long long>(gridDim.x) * kBT;
+  long long i = static_cast<long long>(blockIdx.x) * kBT + threadIdx.x;
+  const float f = static_cast<float>(threadIdx.x);
+  const float4 val = make_float4(f, f + 1.0f, f + 2.0f, f + 3.0f);
+  for (; i + (kUnroll - 1) * stride < n4; i += kUnroll * stride) {
+#pragma unroll
+    for (int k = 0; k < kUnroll; ++k) dst[i + k * stride] = val;
+  }
+  for (; i < n4; i += stride) dst[i] = val;
+}
+
+unsigned grid_of(int blocks) { return blocks > 0 ? static_cast<unsigned>(blocks) : 2048u; }
+
+}  // namespace
+}  // namespace darc
+
+using namespace darc;
+
+namespace {
+
+// 16-byte aligned buffers of a whole number of 16-byte vectors
+bool bw_ok(const void* a, const void* b, size_t bytes, int blocks) {
+  return a && b && bytes % 16 == 0 &&
+         (reinterpret_cast<uintptr_t>(a) | reinterpret_cast<uintptr_t>(b)) % 16 == 0 &&
+         blocks >= 0 && blocks <= (1 << 20);
+}
+
+int bw_launched() { return hipGetLastError() == hipSuccess ? DARC_OK : DARC_EHIP; }
+
+}  // namespace
+
+extern "C" {
+
+int darc_bw_copy(const void* src, void* dst, size_t bytes, int blocks, void* stream) {
+  if (!bw_ok(src, dst, bytes, blocks)) return DARC_EINVAL;
+  if (bytes == 0) return DARC_OK;
+  hipLaunchKernelGGL(k_bw_copy, dim3(grid_of(blocks)), dim3(kBT), 0,
+                     reinterpret_cast<hipStream_t>(stream), static_cast<const float4*>(src),
+                     static_cast<float4*>(dst), static_cast<long long>(bytes / 16));
+  return bw_launched();
+}
+
+int darc_bw_read(const void* src, size_t bytes, float* sink, int blocks, void* stream) {
+  if (!bw_ok(src, sink, bytes, blocks)) return DARC_EINVAL;
+  if (bytes == 0) return DARC_OK;
+  hipLaunchKernelGGL(k_bw_read, dim3(grid_of(blocks)), dim3(kBT), 0,
+                     reinterpret_cast<hipStream_t>(stream), static_cast<const float4*>(src),
+                     static_cast<long long>(bytes / 16), sink);
+  return bw_launched();
+}
+
+int darc_bw_write(void* dst, size_t bytes, int blocks, void* stream) {
+  if (!bw_ok(dst, dst, bytes, blocks)) return DARC_EINVAL;
+  if (bytes == 0) return DARC_OK;
+  hipLaunchKernelGGL(k_bw_write, dim3(grid_of(blocks)), dim3(kBT), 0,
+                     reinterpret_cast<hipStream_t>(stream), static_cast<float4*>(dst),
+                     static_cast<long long>(bytes / 16));
+  return bw_launched();
+}
+
+}  // extern "C"

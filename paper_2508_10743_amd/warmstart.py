@@ -16,7 +16,7 @@ from typing import List, Tuple
 import numpy as np
 import torch
 
-from synthetic.cohorts import Workload, make_cohort
+from synthetic.cohorts import Workload, make_cohorts
 
 from . import darc as D
 from . import unet as N
@@ -44,12 +44,14 @@ def darc_run(images: torch.Tensor, params: D.SweepParams, sweeps: int,
     return coh, losses
 
 
-def make_triples(w: Workload, seeds, params: D.SweepParams, sweeps: int, device) -> List[Triple]:
+def make_triples(w: Workload, seeds, params: D.SweepParams, sweeps: int, device,
+                 workers: int = 1) -> List[Triple]:
     """One triple per seed: the cohort, its A^0 and DARC's velocities after
-    ``sweeps`` sweeps with ``params``."""
+    ``sweeps`` sweeps with ``params`` (phantoms generated in ``workers``
+    processes)."""
     out = []
-    for s in seeds:
-        imgs = torch.from_numpy(make_cohort(w, seed=int(s))).to(device)
+    for imgs in make_cohorts(w, seeds, workers=workers):
+        imgs = torch.from_numpy(imgs).to(device)
         coh, _ = darc_run(imgs, params, sweeps)
         out.append(Triple(D.atlas_update(imgs, None), imgs, coh.v.clone()))
     torch.cuda.synchronize()
@@ -72,36 +74,112 @@ def train(triples: List[Triple], epochs: int, lr: float = 1e-3, seed: int = 0,
     return net, hist
 
 
-def sweeps_to_reach(losses: List[float], target: float) -> int:
-    """First sweep index whose group loss is <= target (len if never)."""
-    for k, f in enumerate(losses):
+def loss_target(f_final: float, tol: float = 0.005) -> float:
+    """Equal final loss within +-tol: a run has reached F_final once its group
+    loss is at most F_final + tol |F_final| (losses fall; LNCC's are negative)."""
+    return f_final + tol * abs(f_final)
+
+
+def first_reach(times: List[float], losses: List[float], target: float):
+    """(seconds, sweeps) at the first sweep whose group loss is <= target, or
+    (None, None)."""
+    for k, (t, f) in enumerate(zip(times, losses)):
         if f <= target:
-            return k
-    return len(losses)
+            return t, k + 1
+    return None, None
 
 
-def evaluate(net: N.UNet, w: Workload, seeds, params: D.SweepParams, sweeps: int, device,
-             tol: float = 1.005) -> dict:
-    """Held-out cohorts: DARC from v = 0 and from the network's velocities.
-    Time-to-loss: sweeps (and seconds) until F <= tol * F_plain_final."""
-    res = {"plain_final": [], "plain_sweeps": [], "warm_sweeps": [], "plain_s": [],
-           "warm_s": [], "warm_first": [], "plain_first": []}
-    for s in seeds:
-        imgs = torch.from_numpy(make_cohort(w, seed=int(s))).to(device)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, lp = darc_run(imgs, params, sweeps)
-        t1 = time.perf_counter()
-        v0 = net(D.atlas_update(imgs, None), imgs)
-        _, lw = darc_run(imgs, params, sweeps, v0=v0)
-        t2 = time.perf_counter()
-        target = tol * lp[-1]
-        kp, kw = sweeps_to_reach(lp, target), sweeps_to_reach(lw, target)
-        res["plain_final"].append(lp[-1])
-        res["plain_first"].append(lp[1])
-        res["warm_first"].append(lw[1])
-        res["plain_sweeps"].append(kp)
-        res["warm_sweeps"].append(kw)
-        res["plain_s"].append((t1 - t0) * kp / sweeps)
-        res["warm_s"].append((t2 - t1) * kw / sweeps)
-    return {k: float(np.mean(v)) for k, v in res.items()}
+def timed_run(images: torch.Tensor, params: D.SweepParams, sweeps: int,
+              net: N.UNet = None) -> Tuple[List[float], List[float]]:
+    """One DARC run, timed on the GPU: from v = 0, or from the network's
+    velocities (its inference, the atlas of A^0 it reads and the level start
+    inside the timed region).  Returns the seconds from the start to the end
+    of each sweep and the group loss after each sweep; the host enqueues the
+    sweeps back to back and synchronises once at the end."""
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    start.record()
+    v0 = net(D.atlas_update(images, None), images) if net is not None else None
+    coh = D.Cohort(images, params, v0=v0)
+    if v0 is not None:
+        coh.level_start()
+    events, fs = [], []
+    for _ in range(sweeps):
+        losses = coh.sweep()
+        fs.append(losses[-1:].clone())
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record()
+        events.append(ev)
+    torch.cuda.synchronize()
+    return [start.elapsed_time(e) * 1e-3 for e in events], [float(f.item()) for f in fs]
+
+
+def evaluate(net: N.UNet, cohorts: List[torch.Tensor], params: D.SweepParams, sweeps: int,
+             tol: float = 0.005) -> dict:
+    """Time-to-loss on held-out cohorts: plain DARC (one subject per launch,
+    from v = 0) runs ``sweeps`` sweeps and sets the target F_plain_final +
+    tol |F_plain_final|; the batched, warm-started form (every subject in one
+    launch, from the network's velocities) runs until it reaches that target
+    or ``sweeps`` sweeps.  Wall-clock seconds are measured, per cohort."""
+    plain_p = dataclasses.replace(params, batch=1)
+    warm_p = dataclasses.replace(params, batch=0)
+    rows = []
+    # first calls load code objects and grow the allocator: run both once untimed
+    timed_run(cohorts[0], plain_p, 1)
+    timed_run(cohorts[0], warm_p, 1, net)
+    for imgs in cohorts:
+        tp, fp = timed_run(imgs, plain_p, sweeps)
+        target = loss_target(fp[-1], tol)
+        sp, kp = first_reach(tp, fp, target)
+        tw, fw = timed_run(imgs, warm_p, sweeps, net)
+        sw, kw = first_reach(tw, fw, target)
+        rows.append(dict(plain_final=fp[-1], target=target, plain_s=sp, plain_sweeps=kp,
+                         warm_s=sw, warm_sweeps=kw, warm_final=fw[-1], plain_first=fp[0],
+                         warm_first=fw[0]))
+    return {"cohorts": rows}
+
+
+def time_to_loss(w: Workload, train_seeds, test_seeds, device, target_sweeps: int = 10,
+                 target_k2: int = 10, epochs: int = 10, lr: float = 1e-3,
+                 workers: int = 1) -> dict:
+    """The whole comparison on cohorts of workload ``w``: training triples from
+    plain DARC (``target_sweeps`` sweeps of ``target_k2`` steps), the U-Net
+    trained on them, then :func:`evaluate` on held-out cohorts with the
+    workload's own schedule (K1 sweeps of K2 steps).  Times of each stage in
+    seconds; per-cohort results plus their means."""
+    params = D.SweepParams(metric=w.metric, win=w.win, ncc_eps=w.ncc_eps, lam=w.lam,
+                           smooth_sigma=w.smooth_sigma, n_sq=w.n_sq, k2=w.k2, lr=w.lr,
+                           beta1=w.beta1, beta2=w.beta2, adam_eps=w.adam_eps)
+    t0 = time.perf_counter()
+    triples = make_triples(w, train_seeds, dataclasses.replace(params, k2=target_k2),
+                           target_sweeps, device, workers=workers)
+    t1 = time.perf_counter()
+    net, hist = train(triples, epochs=epochs, lr=lr)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    del triples
+    test = [torch.from_numpy(c).to(device) for c in make_cohorts(w, test_seeds, workers=workers)]
+    res = evaluate(net, test, params, w.k1)
+    rows = res["cohorts"]
+    reached = [r for r in rows if r["warm_s"] is not None]
+    out = {
+        "cohort": w.name,
+        "schedule": f"{w.k1} sweeps x {w.k2} steps",
+        "target": "F <= F_plain_final + 0.005 |F_plain_final|",
+        "plain": "one subject per launch, from v = 0",
+        "warm": "all subjects per launch, from the U-Net's velocities (inference timed)",
+        "train": {"cohorts": len(train_seeds), "pairs": len(train_seeds) * w.n,
+                  "target_run": f"{target_sweeps} sweeps x {target_k2} steps",
+                  "epochs": epochs, "triples_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
+                  "loss_first_last": [round(hist[0], 6), round(hist[-1], 6)]},
+        "test_cohorts": len(rows),
+        "warm_reached": len(reached),
+        "plain_s": float(np.mean([r["plain_s"] for r in rows])),
+        "plain_sweeps": float(np.mean([r["plain_sweeps"] for r in rows])),
+        "cohorts_detail": rows,
+    }
+    if reached:
+        out["warm_s"] = float(np.mean([r["warm_s"] for r in reached]))
+        out["warm_sweeps"] = float(np.mean([r["warm_sweeps"] for r in reached]))
+        out["speedup"] = float(np.mean([r["plain_s"] / r["warm_s"] for r in reached]))
+    return out

@@ -69,6 +69,8 @@ WORKLOADS: Dict[str, Workload] = {
                  1002, "lncc", 9, 1e-5, 0.0, 1.5, 7, 20, 5),
         Workload("blobs-64x128^3-lncc9", 64, (128, 128, 128), "blobs", 3.0, 4.0, 0.0, 1003,
                  "lncc", 9, 1e-5, 0.01, 0.0, 7, 10, 5),
+        Workload("blobs-4x96x112x96-mse", 4, (96, 112, 96), "blobs", 3.0, 4.0, 0.0, 1004,
+                 "mse", 9, 1e-5, 0.01, 0.0, 7, 10, 5),
         Workload("compartments-200x160x192x224-lncc9", 200, (160, 192, 224), "compartments",
                  10.0, 8.0, 0.0, 1005, "lncc", 9, 1e-5, 0.0, 1.5, 7, 30, 5),
     ]
@@ -206,10 +208,49 @@ def make_cohort(w: Workload, n: Optional[int] = None, dims=None, seed: Optional[
     return images
 
 
-def random_velocity(seed: int, n: int, dims, max_norm: float, corr_len: float = 4.0) -> np.ndarray:
-    """Seeded smooth velocity fields ``[n, 3, D0, D1, D2]`` FP32 for test inputs."""
-    rngs = [np.random.default_rng(s) for s in np.random.SeedSequence(seed).spawn(n)]
-    return np.stack([smooth_random_field(r, dims, max_norm, corr_len) for r in rngs]).astype(np.float32)
+def make_cohorts(w: Workload, seeds, n: Optional[int] = None, dims=None, workers: int = 1):
+    """``make_cohort(w, n, dims, seed)`` for every seed in ``seeds``, with the
+    subjects of all cohorts spread over ``workers`` processes (same images as
+    one cohort at a time)."""
+    n = w.n if n is None else n
+    dims = tuple(w.dims if dims is None else dims)
+    seeds = [int(s) for s in seeds]
+    out = [np.empty((n,) + dims, dtype=np.float32) for _ in seeds]
+    jobs = [(c, i) for c in range(len(seeds)) for i in range(n)]
+    if workers > 1 and len(jobs) > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(workers, len(jobs))) as ex:
+            futs = [ex.submit(_subject, w, n, dims, seeds[c], i) for c, i in jobs]
+            for (c, i), f in zip(jobs, futs):
+                out[c][i] = f.result()
+    else:
+        for c, i in jobs:
+            out[c][i] = _subject(w, n, dims, seeds[c], i)
+    return out
+
+
+def _velocity(ss, dims, max_norm: float, corr_len: float) -> np.ndarray:
+    return smooth_random_field(np.random.default_rng(ss), dims, max_norm,
+                               corr_len).astype(np.float32)
+
+
+def random_velocity(seed: int, n: int, dims, max_norm: float, corr_len: float = 4.0,
+                    workers: int = 1) -> np.ndarray:
+    """Seeded smooth velocity fields ``[n, 3, D0, D1, D2]`` FP32 for test inputs
+    (``workers`` processes give the same fields)."""
+    sss = np.random.SeedSequence(seed).spawn(n)
+    dims = tuple(dims)
+    out = np.empty((n, 3) + dims, dtype=np.float32)
+    if workers > 1 and n > 1:
+        from concurrent.futures import ProcessPoolExecutor
+        with ProcessPoolExecutor(max_workers=min(workers, n)) as ex:
+            futs = [ex.submit(_velocity, ss, dims, max_norm, corr_len) for ss in sss]
+            for i, f in enumerate(futs):
+                out[i] = f.result()
+    else:
+        for i, ss in enumerate(sss):
+            out[i] = _velocity(ss, dims, max_norm, corr_len)
+    return out
 
 
 def random_volume(seed: int, shape, lo: float = 0.0, hi: float = 1.0) -> np.ndarray:

@@ -26,7 +26,11 @@ def test_warm_start_learns_and_helps():
     err = np.mean([float(((net(t.atlas0, t.images) - t.v) ** 2).mean()) for t in test])
     zero = np.mean([float((t.v ** 2).mean()) for t in test])
     assert err < 0.5 * zero, (err, zero)
-    res = WS.evaluate(net, w, range(5000, 5004), D.SweepParams(metric="mse", lam=0.01, k2=5), 4,
-                      dev)
-    assert res["warm_first"] < res["plain_first"], res
-    assert res["warm_sweeps"] <= res["plain_sweeps"], res
+    res = WS.evaluate(net, [t.images for t in test], D.SweepParams(metric="mse", lam=0.01, k2=5),
+                      4)["cohorts"]
+    for r in res:
+        assert r["warm_first"] < r["plain_first"], r
+        assert r["plain_sweeps"] is not None and r["plain_s"] > 0.0, r
+        assert r["warm_sweeps"] is not None and r["warm_sweeps"] <= r["plain_sweeps"], r
+        assert r["target"] >= r["plain_final"]
+

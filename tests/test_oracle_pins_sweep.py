@@ -270,3 +270,18 @@ def test_jacobian_det_of_an_affine_field(seed):
     assert np.abs(det - ref).max() < 1e-12 * max(1.0, abs(ref))
     if seed == 2:
         assert ref < 0 and (det < 0).all()
+
+
+# --------------------------------------------- the squaring adjoint at v = 0
+
+
+def test_exp_adjoint_at_zero_velocity_is_the_identity():
+    """At v = 0 every u_t is 0: the position derivative vanishes and each
+    sample sits on its own voxel with weight 1 (the last voxel of an axis at
+    fraction 1 of the last cell), so each adjoint step doubles g and
+    dL/dv = 2^N g / 2^N = dL/du exactly."""
+    rng = np.random.default_rng(12)
+    dims = (5, 7, 6)
+    g = rng.normal(size=(3,) + dims)
+    _, steps = O.exp_svf(np.zeros((3,) + dims), 7)
+    assert np.array_equal(O.exp_svf_bwd(steps, g), g)

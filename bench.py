@@ -372,8 +372,8 @@ def main():
                          "one-shot segmentation, pyramid resampling, the network) on the same "
                          "cohort")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="run one 1 GiB device-to-device copy first (a known-size kernel for "
-                         "calibrating HBM byte counters)")
+                    help="run one 1 GiB copy stream (k_bw_copy) first: a kernel of known "
+                         "traffic for calibrating HBM byte counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -406,10 +406,15 @@ def main():
         attainable = attainable_bandwidth(dev)
         log(f"attainable bandwidth (GB/s): {attainable}")
     if args.calib_copy:
+        import ctypes
+
         a = torch.full((1 << 28,), 1.0, dtype=torch.float32, device=dev)
         b = torch.empty_like(a)
         torch.cuda.synchronize()
-        b.copy_(a)  # reads 1 GiB, writes 1 GiB
+        # k_bw_copy reads 1 GiB and writes 1 GiB
+        assert D.lib().darc_bw_copy(ctypes.c_void_p(a.data_ptr()), ctypes.c_void_p(b.data_ptr()),
+                                    1 << 30, 0,
+                                    ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)) == 0
         torch.cuda.synchronize()
         del a, b
 

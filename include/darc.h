@@ -533,8 +533,9 @@ int darc_profile_collect(long long* counts, double* ms, int max_classes);
  * Attainable HBM bandwidth (measurement helpers, not part of the method):
  * plain streams over caller buffers that read the path's kernels against what
  * this GPU reaches, beside the vendor's peak.  `bytes` is a multiple of 16 and
- * every pointer 16-byte aligned; blocks = 0 picks 2048 blocks of 256 threads
- * (grid-stride loops, four 16-byte vectors per thread and trip).
+ * every pointer 16-byte aligned; blocks = 0 gives each thread of 256-thread
+ * blocks a single 16-byte vector (bytes / 4096 blocks), otherwise `blocks`
+ * blocks walk the buffers in grid-stride loops (four vectors per trip).
  *   darc_bw_copy : dst = src (reads and writes `bytes`).
  *   darc_bw_read : reads `bytes` of non-negative floats from src; sink [1]
  *                  is written only for a negative sum (never, in effect).

@@ -3,10 +3,12 @@
 // read against what these reach as well as against the vendor's peak.
 //
 // Each thread moves four 16-byte vectors per loop trip (all four loads
-// issued before any is used), over a grid-stride loop; `blocks` = 0 picks
-// 2048 blocks of 256 threads (eight per CU).  The read stream folds every
-// value into a sum that reaches memory only under a condition the data never
-// meets, so no load can be dropped.
+// issued before any is used), over a grid-stride loop.  `blocks` = 0 gives
+// every thread a single vector (bytes / 4096 blocks of 256 threads): on this
+// GPU many short blocks reach more bandwidth than a few persistent ones
+// (measured: copy 6.2 TB/s against 4.7 TB/s with 2048 blocks).  The read stream folds
+// every value into a sum that reaches memory only under a condition the data
+// never meets, so no load can be dropped.
 #include "darc.h"
 #include "darc_kernels.hpp"
 
@@ -61,7 +63,12 @@ __global__ __launch_bounds__(kBT) void k_bw_write(float4* __restrict__ dst, long
   for (; i < n4; i += stride) dst[i] = val;
 }
 
-unsigned grid_of(int blocks) { return blocks > 0 ? static_cast<unsigned>(blocks) : 2048u; }
+unsigned grid_of(int blocks, size_t bytes) {
+  if (blocks > 0) return static_cast<unsigned>(blocks);
+  const size_t per_block = static_cast<size_t>(kBT) * 16;
+  const size_t b = (bytes + per_block - 1) / per_block;
+  return static_cast<unsigned>(b < 1 ? 1 : (b > 0x7fffffffu ? 0x7fffffffu : b));
+}
 
 }  // namespace
 }  // namespace darc
@@ -86,7 +93,7 @@ extern "C" {
 int darc_bw_copy(const void* src, void* dst, size_t bytes, int blocks, void* stream) {
   if (!bw_ok(src, dst, bytes, blocks)) return DARC_EINVAL;
   if (bytes == 0) return DARC_OK;
-  hipLaunchKernelGGL(k_bw_copy, dim3(grid_of(blocks)), dim3(kBT), 0,
+  hipLaunchKernelGGL(k_bw_copy, dim3(grid_of(blocks, bytes)), dim3(kBT), 0,
                      reinterpret_cast<hipStream_t>(stream), static_cast<const float4*>(src),
                      static_cast<float4*>(dst), static_cast<long long>(bytes / 16));
   return bw_launched();
@@ -95,7 +102,7 @@ int darc_bw_copy(const void* src, void* dst, size_t bytes, int blocks, void* str
 int darc_bw_read(const void* src, size_t bytes, float* sink, int blocks, void* stream) {
   if (!bw_ok(src, sink, bytes, blocks)) return DARC_EINVAL;
   if (bytes == 0) return DARC_OK;
-  hipLaunchKernelGGL(k_bw_read, dim3(grid_of(blocks)), dim3(kBT), 0,
+  hipLaunchKernelGGL(k_bw_read, dim3(grid_of(blocks, bytes)), dim3(kBT), 0,
                      reinterpret_cast<hipStream_t>(stream), static_cast<const float4*>(src),
                      static_cast<long long>(bytes / 16), sink);
   return bw_launched();
@@ -104,7 +111,7 @@ int darc_bw_read(const void* src, size_t bytes, float* sink, int blocks, void* s
 int darc_bw_write(void* dst, size_t bytes, int blocks, void* stream) {
   if (!bw_ok(dst, dst, bytes, blocks)) return DARC_EINVAL;
   if (bytes == 0) return DARC_OK;
-  hipLaunchKernelGGL(k_bw_write, dim3(grid_of(blocks)), dim3(kBT), 0,
+  hipLaunchKernelGGL(k_bw_write, dim3(grid_of(blocks, bytes)), dim3(kBT), 0,
                      reinterpret_cast<hipStream_t>(stream), static_cast<float4*>(dst),
                      static_cast<long long>(bytes / 16));
   return bw_launched();

@@ -60,7 +60,7 @@
 extern "C" {
 #endif
 
-#define DARC_ABI_VERSION 3
+#define DARC_ABI_VERSION 4
 
 /* status codes */
 #define DARC_OK 0
@@ -83,6 +83,12 @@ extern "C" {
  * with A = initialize(), which the paper leaves unspecified). */
 #define DARC_SGD_INIT_WARM 0    /* from the current atlas A^k */
 #define DARC_SGD_INIT_INITIAL 1 /* from A^0 of main: the mean of the unwarped subjects */
+
+/* Inner iterations in one launch each (persistent, grid-synchronised; MSE
+ * and L1 without smoothing of v) instead of ~20 launches each. */
+#define DARC_FUSED_AUTO 0 /* the autotuner's choice for the shape; separate otherwise */
+#define DARC_FUSED_OFF 1  /* separate launches */
+#define DARC_FUSED_ON 2   /* fused; DARC_EUNSUPPORTED for LNCC or smoothing */
 
 /* smoothing modes */
 #define DARC_GAUSS 0     /* separable Gaussian, replicated border */
@@ -483,6 +489,7 @@ typedef struct darc_params {
   int atlas_batch;    /* SGD atlas: subjects per minibatch (>= 1) */
   float atlas_lr;     /* SGD atlas: Adam learning rate (betas and eps as above) */
   int sgd_init;       /* SGD atlas start: DARC_SGD_INIT_WARM or DARC_SGD_INIT_INITIAL */
+  int fused;          /* DARC_FUSED_AUTO, DARC_FUSED_OFF or DARC_FUSED_ON */
 } darc_params;
 
 /* sizeof(darc_state) and sizeof(darc_params) as compiled into the library,
@@ -501,19 +508,48 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
                void* stream);
 
 /* ------------------------------------------------------------------------
- * darc_autotune -- picks the chunk length (planes per block along d0) of the
- * marching kernels for this state's volume shape and batch size by timing
- * the candidates 8, 16, 32, 64 on the sweep's workspace (the squaring steps
- * and their adjoint; the window kernels when the metric is LNCC or v is
- * smoothed).  v, m, s and the atlas are only read.  The choice is kept for
- * every later call with the same shape and batch in this process.  Blocks
- * until `stream` is idle; must not run while a stream is being captured.
- * chosen (nullable) receives {squaring tz, window tz} (0 = not tuned).
- * darc_autotune_clear forgets all choices.
+ * darc_autotune -- picks launch shapes for this state's volume shape and
+ * batch size by timing candidates on the sweep's workspace: for the squaring
+ * steps and their adjoint, marching tiles 8, 16, 32 or 64 planes deep or one
+ * plane per block without marching (-1); the tile depth of the window
+ * kernels (when the metric is LNCC or v is smoothed); and, for MSE / L1
+ * without smoothing, whether an inner iteration runs as one fused launch or
+ * as separate launches (decides DARC_FUSED_AUTO).  v, m, s and the atlas are only read.  The choices are
+ * kept for every later call with the same shape and batch in this process.
+ * Blocks until `stream` is idle; must not run while a stream is being
+ * captured.  chosen (nullable, 3 ints) receives {squaring tz (-1: planes),
+ * window tz, fused: 1 fused, 2 separate} (0 = not tuned).  darc_autotune_clear forgets
+ * all choices.
  * ---------------------------------------------------------------------- */
 int darc_autotune(darc_state* st, const darc_params* p, void* ws, size_t ws_bytes, void* stream,
                   int* chosen);
 int darc_autotune_clear(void);
+
+/* ------------------------------------------------------------------------
+ * darc_set_launch_shape -- sets one entry of the table darc_autotune fills,
+ * for volumes d0 x d1 x d2 and n subjects per launch (all four zero: the
+ * entry every shape without its own falls back to): kind
+ * DARC_SHAPE_SQUARING (value 8, 16, 32, 64: marching tile depth; 1:
+ * marching, depth by the built-in heuristic; -1: one plane per block without
+ * marching), DARC_SHAPE_WINDOW (8, 16, 32, 64, 96) or DARC_SHAPE_FUSED (1
+ * fused, 2 separate launches under DARC_FUSED_AUTO).  value 0 returns the
+ * entry to the built-in heuristic.  Launch shapes change how the same
+ * arithmetic is scheduled, never what it computes.
+ * ---------------------------------------------------------------------- */
+#define DARC_SHAPE_SQUARING 0
+#define DARC_SHAPE_WINDOW 1
+#define DARC_SHAPE_FUSED 2
+int darc_set_launch_shape(int kind, int d0, int d1, int d2, int n, int value);
+
+/* ------------------------------------------------------------------------
+ * darc_fused_barrier_ticks -- bound of one grid-barrier wait of the fused
+ * inner iteration (DARC_FUSED_*), in ticks of the GPU's 100 MHz real-time
+ * counter (default 100 000 000, one second; a negative value restores it).
+ * A wait that reaches the bound gives up: every wave still finishes, and the
+ * sweep reports NaN as its group loss (losses[n * k2]).  Small bounds exist
+ * to exercise that path from the host; process-wide, not thread-safe.
+ * ---------------------------------------------------------------------- */
+int darc_fused_barrier_ticks(long long ticks);
 
 /* ------------------------------------------------------------------------
  * Kernel timing for measurement.  When enabled, every kernel launched by the

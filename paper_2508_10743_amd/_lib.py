@@ -14,7 +14,7 @@ from ctypes import POINTER, c_char_p, c_double, c_float, c_int, c_longlong, c_si
 
 LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libdarc.so")
 
-DARC_ABI_VERSION = 3
+DARC_ABI_VERSION = 4
 
 DARC_OK = 0
 DARC_EINVAL = -1
@@ -30,6 +30,12 @@ DARC_ATLAS_MEDIAN = 1
 DARC_ATLAS_SGD = 2
 DARC_SGD_INIT_WARM = 0
 DARC_SGD_INIT_INITIAL = 1
+DARC_FUSED_AUTO = 0
+DARC_FUSED_OFF = 1
+DARC_FUSED_ON = 2
+DARC_SHAPE_SQUARING = 0
+DARC_SHAPE_WINDOW = 1
+DARC_SHAPE_FUSED = 2
 DARC_GAUSS = 0
 DARC_DIFFUSION = 1
 DARC_CENTER_DISPLACEMENT = 0
@@ -85,6 +91,7 @@ class DarcParams(ctypes.Structure):
         ("atlas_batch", c_int),
         ("atlas_lr", c_float),
         ("sgd_init", c_int),
+        ("fused", c_int),
     ]
 
 
@@ -150,6 +157,8 @@ PROTOTYPES = {
     "darc_autotune": (c_int, [POINTER(DarcState), POINTER(DarcParams), _P, _Z, _P,
                               POINTER(c_int)]),
     "darc_autotune_clear": (c_int, []),
+    "darc_fused_barrier_ticks": (c_int, [c_longlong]),
+    "darc_set_launch_shape": (c_int, [_I, _I, _I, _I, _I, _I]),
     "darc_profile_enable": (c_int, [_I]),
     "darc_profile_reset": (c_int, []),
     "darc_profile_num_classes": (c_int, []),

@@ -88,7 +88,7 @@ double g_prof_ms[KC_NUM];
 
 const char* const kClassNames[KC_NUM] = {
     "exp_fwd_step", "exp_bwd_step", "warp", "warp_bwd", "mse", "lncc_fwd", "lncc_bwd",
-    "gauss", "diffusion", "adam", "center", "atlas", "fill", "misc"};
+    "gauss", "diffusion", "adam", "center", "atlas", "fill", "misc", "iter_fused"};
 
 hipEvent_t take_event() {
   if (!g_event_pool.empty()) {
@@ -135,9 +135,13 @@ std::vector<TuneEntry> g_tune;
 
 int tuned_tz(int kind, const Geom& g, int n) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
-  for (const TuneEntry& e : g_tune)
-    if (e.kind == kind && e.d0 == g.d0 && e.d1 == g.d1 && e.d2 == g.d2 && e.n == n) return e.tz;
-  return 0;
+  int fallback = 0;  // the entry for every shape (dims and n zero), if set
+  for (const TuneEntry& e : g_tune) {
+    if (e.kind != kind) continue;
+    if (e.d0 == g.d0 && e.d1 == g.d1 && e.d2 == g.d2 && e.n == n) return e.tz;
+    if (e.d0 == 0 && e.d1 == 0 && e.d2 == 0 && e.n == 0) fallback = e.tz;
+  }
+  return fallback;
 }
 
 void set_tuned_tz(int kind, const Geom& g, int n, int tz) {
@@ -1004,7 +1008,7 @@ namespace {
 
 struct SweepLayout {
   int B;
-  size_t ckpt, aux, uN, gU, gA, gB, gV, iw, fields, vtmp, uhat, sloss, bc, wall, sgd, total;
+  size_t ckpt, aux, uN, gU, gA, gB, gV, iw, fields, vtmp, uhat, sloss, bc, wall, sgd, bar, total;
 };
 
 SweepLayout sweep_layout(const darc_state* st, const darc_params* p) {
@@ -1037,6 +1041,7 @@ SweepLayout sweep_layout(const darc_state* st, const darc_params* p) {
   const int ab = p->atlas_batch < n ? p->atlas_batch : n;
   L.wall = take(sgd ? static_cast<size_t>(n) * V * sizeof(float) : 0);
   L.sgd = take(sgd ? sgd_layout(st->d0, st->d1, st->d2, ab).total : 0);
+  L.bar = take(2 * sizeof(int));  // barrier counter and error flag of the fused iteration
   L.total = off;
   return L;
 }
@@ -1084,7 +1089,26 @@ int check_sweep(const darc_state* st, const darc_params* p) {
   if (p->center_mode != DARC_CENTER_DISPLACEMENT && p->center_mode != DARC_CENTER_VELOCITY)
     return fail(DARC_EINVAL, "darc_sweep: unknown center_mode %d", p->center_mode);
   if (st->step < 0) return fail(DARC_EINVAL, "darc_sweep: step must be >= 0");
+  if (p->fused != DARC_FUSED_AUTO && p->fused != DARC_FUSED_OFF && p->fused != DARC_FUSED_ON)
+    return fail(DARC_EINVAL, "darc_sweep: unknown fused mode %d", p->fused);
+  if (p->fused == DARC_FUSED_ON && (p->metric == DARC_LNCC || p->smooth_sigma > 0.0f))
+    return fail(DARC_EUNSUPPORTED,
+                "darc_sweep: the fused iteration covers MSE and L1 without smoothing of v");
   return DARC_OK;
+}
+
+// Whether a sweep batch of B subjects runs its inner iterations fused.
+// DARC_FUSED_AUTO follows the autotuner's choice for the shape, and without
+// one takes separate launches: on this GPU a grid barrier costs 5-8 us at 64-
+// 128 blocks (every block's agent-scope fence writes back its XCD's L2), so
+// the 16 barriers of an iteration outweigh the launches they replace (4 x
+// 32^3: 1.79 ms per fused sweep against 0.78 separate).
+bool use_fused(const darc_params* p, const Geom& g, int B) {
+  if (p->fused == DARC_FUSED_OFF || p->metric == DARC_LNCC || p->smooth_sigma > 0.0f)
+    return false;
+  if (fused_resident_blocks(p->metric == DARC_L1) < 8) return false;
+  if (p->fused == DARC_FUSED_ON) return true;
+  return tuned_tz(TUNE_FUSED, g, B) == 1;
 }
 
 }  // namespace
@@ -1130,6 +1154,12 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
 
   launch_fill_f64(losses, static_cast<long long>(n) * k2 + 1, 0.0, s);
   long long step = st->step;
+  const bool fused = use_fused(p, g, B);
+  if (p->fused == DARC_FUSED_ON && !fused)
+    return fail(DARC_EHIP, "darc_sweep: the fused iteration cannot be made resident");
+  unsigned* bar = reinterpret_cast<unsigned*>(w + L.bar);
+  int* err = reinterpret_cast<int*>(w + L.bar) + 1;
+  if (fused) launch_fill_f32(reinterpret_cast<float*>(err), 1, 0.0f, s);
   if (p->reinit_v) {
     const long long cnt = static_cast<long long>(n) * fsv;
     launch_fill_f32(st->v, cnt, 0.0f, s);
@@ -1149,6 +1179,13 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
     const float* ib = st->images + static_cast<size_t>(b0) * g.V;
     for (int k = 0; k < k2; ++k) {
       double* lslot = losses + static_cast<size_t>(b0) * k2 + k;
+      if (fused) {
+        // one launch per inner iteration (capacity checked by use_fused)
+        run_iter_fused(ib, st->atlas, vb, mb, sb, ckpt, aux, uN, gU, gA, gB, gV, lslot, k2, rw, g,
+                       nb, N, st->step_dev, step, k, p->lr, p->beta1, p->beta2, p->adam_eps, l1,
+                       bar, err, s);
+        continue;
+      }
       run_exp_fwd(vb, uN, ckpt, nullptr, aux, g, nb, N, s);
       if (!lncc) {
         launch_mse_fused(ib, st->atlas, uN, gU, lslot, k2, rw, g, nb, l1, s);
@@ -1209,6 +1246,7 @@ int darc_sweep(darc_state* st, const darc_params* p, double* losses, void* ws, s
     }
   }
   launch_sum_f64(sloss, n, 1.0 / n, losses + static_cast<size_t>(n) * k2, s);
+  if (fused) flag_fused_error(err, losses + static_cast<size_t>(n) * k2, s);
   st->step = step + k2;
   return check_launch("darc_sweep");
 }
@@ -1233,11 +1271,13 @@ int darc_autotune(darc_state* st, const darc_params* p, void* ws, size_t ws_byte
   float* gB = reinterpret_cast<float*>(w + L.gB);
   float* gV = reinterpret_cast<float*>(w + L.gV);
   const int cands[4] = {8, 16, 32, 64};
+  // the squaring kernels also try one plane per block without marching (-1)
+  const int exp_cands[5] = {-1, 8, 16, 32, 64};
   int pick[2] = {0, 0};
   // squaring steps and their adjoint on the first batch (u_N stands in for dL/du)
   {
     float best = -1.0f;
-    for (int tz : cands) {
+    for (int tz : exp_cands) {
       set_tuned_tz(TUNE_EXP, g, B, tz);
       const float ms = time_on(s, [&] {
         run_exp_fwd(st->v, uN, ckpt, nullptr, aux, g, B, N, s);
@@ -1280,15 +1320,66 @@ int darc_autotune(darc_state* st, const darc_params* p, void* ws, size_t ws_byte
     set_tuned_tz(TUNE_WINDOW, g, B, pick[1]);
     set_tuned_tz(TUNE_WINDOW, g, 3 * B, pick[1]);
   }
+  // one inner iteration fused against separate launches (MSE / L1 without
+  // smoothing); Adam's results go to scratch, so the state is left as it is
+  int fused_pick = 0;
+  if (!lncc && !smooth && fused_resident_blocks(p->metric == DARC_L1) >= 8) {
+    const bool l1 = p->metric == DARC_L1;
+    const RegW rw = make_regw(g, 3, p->lam);
+    double* sloss = reinterpret_cast<double*>(w + L.sloss);
+    unsigned* bar = reinterpret_cast<unsigned*>(w + L.bar);
+    int* err = reinterpret_cast<int*>(w + L.bar) + 1;
+    launch_fill_f32(reinterpret_cast<float*>(err), 1, 0.0f, s);
+    const long long cnt = static_cast<long long>(B) * 3 * g.V;
+    const float t_sep = time_on(s, [&] {
+      run_exp_fwd(st->v, uN, ckpt, nullptr, aux, g, B, N, s);
+      launch_mse_fused(st->images, st->atlas, uN, gU, sloss, 1, rw, g, B, l1, s);
+      run_exp_bwd(st->v, ckpt, gU, gV, gA, gB, aux, true, g, B, N, s);
+      launch_adam(st->v, gA, gB, uN, gV, cnt, 1, p->lr, p->beta1, p->beta2, p->adam_eps, s);
+    });
+    const float t_fused = time_on(s, [&] {
+      run_iter_fused(st->images, st->atlas, st->v, st->m, st->s, ckpt, aux, uN, gU, gA, gB, gV,
+                     sloss, 1, rw, g, B, N, nullptr, 0, 0, p->lr, p->beta1, p->beta2,
+                     p->adam_eps, l1, bar, err, s, gA, gB, uN);
+    });
+    if (t_sep >= 0.0f && t_fused >= 0.0f) {
+      fused_pick = t_fused < t_sep ? 1 : 2;
+      set_tuned_tz(TUNE_FUSED, g, B, fused_pick);
+    }
+  }
   if (chosen) {
     chosen[0] = pick[0];
     chosen[1] = pick[1];
+    chosen[2] = fused_pick;
   }
   return check_launch("darc_autotune");
 }
 
 int darc_autotune_clear(void) {
   clear_tuned();
+  return ok();
+}
+
+int darc_set_launch_shape(int kind, int d0, int d1, int d2, int n, int value) {
+  const bool every = d0 == 0 && d1 == 0 && d2 == 0 && n == 0;
+  if (!every) DARC_TRY(check_dims("darc_set_launch_shape", n, d0, d1, d2));
+  Geom g{};
+  if (!every) g = make_geom(d0, d1, d2);
+  bool okv = false;
+  if (kind == DARC_SHAPE_SQUARING) okv = value == -1 || value == 1 || value == 8 || value == 16 ||
+                                         value == 32 || value == 64 || value == 0;
+  else if (kind == DARC_SHAPE_WINDOW) okv = value == 8 || value == 16 || value == 32 ||
+                                            value == 64 || value == 96 || value == 0;
+  else if (kind == DARC_SHAPE_FUSED) okv = value >= 0 && value <= 2;
+  else return fail(DARC_EINVAL, "darc_set_launch_shape: unknown kind %d", kind);
+  if (!okv) return fail(DARC_EINVAL, "darc_set_launch_shape: value %d not valid for kind %d", value,
+                        kind);
+  set_tuned_tz(kind, g, n, value);
+  return ok();
+}
+
+int darc_fused_barrier_ticks(long long ticks) {
+  set_barrier_ticks(ticks);
   return ok();
 }
 

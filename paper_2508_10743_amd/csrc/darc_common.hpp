@@ -355,6 +355,7 @@ enum KernelClass : int {
   KC_ATLAS,
   KC_FILL,
   KC_MISC,
+  KC_ITER,
   KC_NUM
 };
 

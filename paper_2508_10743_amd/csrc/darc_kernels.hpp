@@ -34,6 +34,31 @@ void run_exp_bwd_recompute(const float* v, const float* g_u, float* g_v, float* 
                            float* tmp_b, float* rec_a, float* rec_b, int* aux, const Geom& g,
                            int n, int n_sq, hipStream_t st);
 
+// One inner iteration of n subjects (Exp, warp + MSE or L1 + regulariser,
+// both adjoints, Adam on v in place) in one persistent launch of at most as
+// many blocks as the device holds at once, its phases separated by grid
+// barriers; for small cohorts.  ckpt [n_sq-1][n][3][V], aux (records), uN,
+// gU, gA, gB, gV [n][3][V] are scratch; bar and err are two device words (err
+// zeroed once; raised if a barrier wait timed out).  The Adam step count is
+// *step_dev + k + 1 when step_dev is given, else step_host + k + 1; Adam's
+// results go to v_out, m_out, s_out when given (timing runs), else to v, m,
+// s.  Returns false (nothing enqueued) when the launch cannot be made
+// resident.
+bool run_iter_fused(const float* img, const float* atlas, float* v, float* m, float* s,
+                    float* ckpt, int* aux, float* uN, float* gU, float* gA, float* gB, float* gV,
+                    double* loss, int loss_stride, const RegW& rw, const Geom& g, int n, int n_sq,
+                    const long long* step_dev, long long step_host, int k, float lr, double b1,
+                    double b2, float eps, bool l1, unsigned* bar, int* err, hipStream_t st,
+                    float* v_out = nullptr, float* m_out = nullptr, float* s_out = nullptr);
+// out[0] = NaN when err[0] is raised.
+void flag_fused_error(const int* err, double* out, hipStream_t st);
+// Blocks of the fused kernel the current device holds at once.
+int fused_resident_blocks(bool l1);
+// Bound of one grid-barrier wait of the fused kernel, in ticks of the 100 MHz
+// real-time counter; negative restores the default (1 s).
+constexpr long long kDefaultBarrierTicks = 100000000;
+void set_barrier_ticks(long long ticks);
+
 // --- warp -----------------------------------------------------------------
 void launch_warp(const float* img, const float* u, float* out, const Geom& g, int n,
                  hipStream_t st);
@@ -97,7 +122,7 @@ void launch_atlas(const float* images, const float* u, const float* mean, float*
 // --- chunk lengths of the marching kernels ---------------------------------
 // Planes per block along d0.  0 = not tuned (the launchers then use their own
 // heuristic); set by darc_autotune for one volume shape and batch size.
-enum TuneKind : int { TUNE_EXP = 0, TUNE_WINDOW = 1, TUNE_NUM };
+enum TuneKind : int { TUNE_EXP = 0, TUNE_WINDOW = 1, TUNE_FUSED = 2, TUNE_NUM };
 int tuned_tz(int kind, const Geom& g, int n);
 void set_tuned_tz(int kind, const Geom& g, int n, int tz);
 void clear_tuned();

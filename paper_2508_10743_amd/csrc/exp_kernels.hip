@@ -18,6 +18,7 @@
 #include <climits>
 
 #include "darc_kernels.hpp"
+#include "voxel_bodies.hpp"
 
 namespace darc {
 
@@ -380,24 +381,31 @@ struct BwdGeom {
 //    only).
 // 3. Each thread gathers, for each of its voxels y and each corner offset k,
 //    the sources stored in cell y - k with weight w_k.
-template <bool FIRST>
-__global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
-                                                 const float* __restrict__ gin,
-                                                 float* __restrict__ gout, BwdGeom bg,
-                                                 float scale, float oscale,
-                                                 const int* __restrict__ boxes,
-                                                 const int* __restrict__ reach) {
-  __shared__ int cnt[NCELL];
-  __shared__ float4 sdat4[KSLOT][NCELL];  // t0, t1, t2, g0 of a binned source
-  __shared__ float2 sdat2[KSLOT][NCELL];  // g1, g2
-  __shared__ float ovf[3][BTILE];
-  __shared__ int ubox[6];  // union of the candidate source sub-boxes
+// LDS of the tiled adjoint.
+struct TiledBwdLds {
+  int cnt[NCELL];
+  float4 sdat4[KSLOT][NCELL];  // t0, t1, t2, g0 of a binned source
+  float2 sdat2[KSLOT][NCELL];  // g1, g2
+  float ovf[3][BTILE];
+  int ubox[6];  // union of the candidate source sub-boxes
+};
+
+// Blocks blk of nblk walk the adjoint tiles; ALL: every subject, otherwise
+// only those with a reach beyond 1 (the marching kernel takes the others).
+template <bool FIRST, bool ALL>
+__device__ __forceinline__ void exp_bwd_tiled_body(TiledBwdLds& L, uint32_t blk, uint32_t nblk,
+                                                   const float* __restrict__ ut,
+                                                   const float* __restrict__ gin,
+                                                   float* __restrict__ gout, const BwdGeom& bg,
+                                                   float scale, float oscale,
+                                                   const int* __restrict__ boxes,
+                                                   const int* __restrict__ reach) {
   const TileGeom& tg = bg.src;
   const Geom& g = tg.g;
   // persistent: each block walks a contiguous run of tiles (runs of
   // neighbouring blocks sit on the same XCD)
-  const uint32_t run = (bg.total + gridDim.x - 1) / gridDim.x;
-  const uint32_t first = xcd_remap(blockIdx.x, gridDim.x) * run;
+  const uint32_t run = (bg.total + nblk - 1) / nblk;
+  const uint32_t first = xcd_remap(blk, nblk) * run;
   for (uint32_t bid = first; bid < min(first + run, bg.total); ++bid) {
   const int s = static_cast<int>(bid / bg.ntiles);
   const int tile = static_cast<int>(bid - static_cast<uint32_t>(s) * bg.ntiles);
@@ -412,7 +420,8 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
     // subjects with reach 1 everywhere are handled by the marching kernel:
     // skip the rest of this subject's tiles
     const int* rc = reach + s * 8;
-    if (rc[0] <= 1 && rc[1] <= 1 && rc[2] <= 1 && rc[3] <= 1 && rc[4] <= 1 && rc[5] <= 1) {
+    if (!ALL && rc[0] <= 1 && rc[1] <= 1 && rc[2] <= 1 && rc[3] <= 1 && rc[4] <= 1 &&
+        rc[5] <= 1) {
       bid = static_cast<uint32_t>(s + 1) * bg.ntiles - 1;
       continue;
     }
@@ -422,9 +431,9 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
   const float* gi = gin + off;
   const float js = FIRST ? scale : 1.0f;
 
-  for (int i = threadIdx.x; i < NCELL; i += BNT) cnt[i] = 0;
-  for (int i = threadIdx.x; i < 3 * BTILE; i += BNT) (&ovf[0][0])[i] = 0.0f;
-  if (threadIdx.x < 6) ubox[threadIdx.x] = threadIdx.x < 3 ? INT_MAX : INT_MIN;
+  for (int i = threadIdx.x; i < NCELL; i += BNT) L.cnt[i] = 0;
+  for (int i = threadIdx.x; i < 3 * BTILE; i += BNT) (&L.ovf[0][0])[i] = 0.0f;
+  if (threadIdx.x < 6) L.ubox[threadIdx.x] = threadIdx.x < 3 ? INT_MAX : INT_MIN;
 
   // 1. direct term of the two voxels (z = 2 lz, 2 lz + 1) this thread owns
   float acc[2][3];
@@ -487,18 +496,18 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
       const int a2 = max(sx * ETX, ox - 1 - bx[5]);
       const int b2 = min(min(sx * ETX + ETX, g.d2) - 1, L2 - bx[2]);
       if (a0 <= b0 && a1 <= b1 && a2 <= b2) {
-        atomicMin(&ubox[0], a0);
-        atomicMin(&ubox[1], a1);
-        atomicMin(&ubox[2], a2);
-        atomicMax(&ubox[3], b0);
-        atomicMax(&ubox[4], b1);
-        atomicMax(&ubox[5], b2);
+        atomicMin(&L.ubox[0], a0);
+        atomicMin(&L.ubox[1], a1);
+        atomicMin(&L.ubox[2], a2);
+        atomicMax(&L.ubox[3], b0);
+        atomicMax(&L.ubox[4], b1);
+        atomicMax(&L.ubox[5], b2);
       }
     }
   }
   __syncthreads();
-  const int ua0 = ubox[0], ua1 = ubox[1], ua2 = ubox[2];
-  const int ub0 = ubox[3], ub1 = ubox[4], ub2 = ubox[5];
+  const int ua0 = L.ubox[0], ua1 = L.ubox[1], ua2 = L.ubox[2];
+  const int ub0 = L.ubox[3], ub1 = L.ubox[4], ub2 = L.ubox[5];
   if (ua0 <= ub0 && ua1 <= ub1 && ua2 <= ub2) {
     const int e2 = ub2 - ua2 + 1, e1 = ub1 - ua1 + 1;
     const int nvox = (ub0 - ua0 + 1) * e1 * e2;
@@ -553,10 +562,10 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
         if (c0 < 0 || c0 >= CZ || c1 < 0 || c1 >= CY || c2 < 0 || c2 >= CX) continue;
         const int ci = (c0 * CY + c1) * CX + c2;
         const float g0 = gg[j][0], g1 = gg[j][1], g2 = gg[j][2];
-        const int slot = atomicAdd(&cnt[ci], 1);
+        const int slot = atomicAdd(&L.cnt[ci], 1);
         if (slot < KSLOT) {
-          sdat4[slot][ci] = make_float4(bc.t0, bc.t1, bc.t2, g0);
-          sdat2[slot][ci] = make_float2(g1, g2);
+          L.sdat4[slot][ci] = make_float4(bc.t0, bc.t1, bc.t2, g0);
+          L.sdat2[slot][ci] = make_float2(g1, g2);
         } else {
           const float w0[2] = {1.0f - bc.t0, bc.t0};
           const float w1[2] = {1.0f - bc.t1, bc.t1};
@@ -572,9 +581,9 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
                 if (q0 >= 0 && q0 < BTZ && q1 >= 0 && q1 < BTY && q2 >= 0 && q2 < BTX) {
                   const float w = w0[a] * w1[b] * w2[e];
                   const int li = (q0 * BTY + q1) * BTX + q2;
-                  atomicAdd(&ovf[0][li], w * g0);
-                  atomicAdd(&ovf[1][li], w * g1);
-                  atomicAdd(&ovf[2][li], w * g2);
+                  atomicAdd(&L.ovf[0][li], w * g0);
+                  atomicAdd(&L.ovf[1][li], w * g1);
+                  atomicAdd(&L.ovf[2][li], w * g2);
                 }
               }
             }
@@ -601,12 +610,12 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
 #pragma unroll
         for (int e = 0; e < 2; ++e) {
           const int ci = ((z + 1 - a) * CY + (ly + 1 - b)) * CX + (lx + 1 - e);
-          const int nsrc = min(cnt[ci], KSLOT);
+          const int nsrc = min(L.cnt[ci], KSLOT);
 #pragma unroll
           for (int j = 0; j < KSLOT; ++j) {
             if (j < nsrc) {
-              const float4 p = sdat4[j][ci];
-              const float2 q = sdat2[j][ci];
+              const float4 p = L.sdat4[j][ci];
+              const float2 q = L.sdat2[j][ci];
               const float w = corner_weight(a, b, e, p.x, p.y, p.z);
               r0 += w * p.w;
               r1 += w * q.x;
@@ -617,9 +626,9 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
       }
     }
     const int li = (z * BTY + ly) * BTX + lx;
-    r0 += ovf[0][li];
-    r1 += ovf[1][li];
-    r2 += ovf[2][li];
+    r0 += L.ovf[0][li];
+    r1 += L.ovf[1][li];
+    r2 += L.ovf[2][li];
     const int lin = (y0 * g.d1 + y1) * g.d2 + y2;
     go[lin] = r0 * oscale;
     go[g.V + lin] = r1 * oscale;
@@ -627,6 +636,18 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
   }
   __syncthreads();  // the next tile reuses the LDS bins
   }
+}
+
+template <bool FIRST, bool ALL>
+__global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
+                                                 const float* __restrict__ gin,
+                                                 float* __restrict__ gout, BwdGeom bg,
+                                                 float scale, float oscale,
+                                                 const int* __restrict__ boxes,
+                                                 const int* __restrict__ reach) {
+  __shared__ TiledBwdLds L;
+  exp_bwd_tiled_body<FIRST, ALL>(L, blockIdx.x, gridDim.x, ut, gin, gout, bg, scale, oscale,
+                                 boxes, reach);
 }
 
 // Adjoint of one squaring step, marching, for a subject whose every cell
@@ -1005,6 +1026,275 @@ AuxPtrs aux_ptrs(int* aux, const TileGeom& tg, int n, int n_sq) {
   return a;
 }
 
+
+// ---------------------------------------------------------------------------
+// One inner iteration in one launch (small cohorts).
+//
+// For small volumes the marching kernels are bound by their serial planes
+// (a 32^3 subject gives a squaring launch only 64 blocks of 8+ planes each)
+// and by the ~20 launches of an iteration, not by memory.  This persistent
+// kernel runs the whole iteration -- the squaring steps, warp + MSE/L1 +
+// regulariser with their adjoints, the squaring adjoint and Adam -- as
+// phases of tile-parallel work separated by grid barriers.  Its squaring
+// steps gather directly (no plane ring) and write the same per-tile records
+// as the marching forward; its adjoint is the tiled adjoint for every
+// subject; the loss and the Adam update are the bodies of the separate
+// kernels.
+
+// One plane of a record tile (32 x 8 voxels, one per thread) of a squaring
+// step: the arithmetic of k_exp_fwd<FIRST, REC> with the corners read from
+// memory.  With REC the block merges its cell offsets into the tile's record
+// (global atomics on boxes initialised by k_box_init) and raises the
+// subject's reaches.  Blocks are (subject, tile, plane), so a small volume
+// gets eight times the blocks of the marching kernel and no serial planes.
+template <bool FIRST, bool REC>
+__device__ __forceinline__ void exp_fwd_plane_body(int (*red)[ENT / 64], uint32_t blk,
+                                                   const float* __restrict__ src,
+                                                   float* __restrict__ dst, const TileGeom& tg,
+                                                   float scale, int* __restrict__ boxes,
+                                                   int* __restrict__ reach) {
+  const Geom& g = tg.g;
+  const uint32_t b = xcd_remap(blk, tg.total * ETZ);
+  const uint32_t bt = b / ETZ;
+  const int k = static_cast<int>(b - bt * ETZ);
+  const int s = static_cast<int>(bt / tg.ntiles);
+  const int tile = static_cast<int>(bt - static_cast<uint32_t>(s) * tg.ntiles);
+  const int ox = (tile % tg.ntx) * ETX;
+  const int oy = ((tile / tg.ntx) % tg.nty) * ETY;
+  const int x0 = (tile / (tg.ntx * tg.nty)) * ETZ + k;
+  const size_t off = static_cast<size_t>(s) * 3 * g.V;
+  const float* f = src + off;
+  float* o = dst + off;
+  const float* fc[3] = {f, f + g.V, f + 2 * static_cast<size_t>(g.V)};
+  const int lx = threadIdx.x % ETX, ly = threadIdx.x / ETX;
+  const int x2 = ox + lx, x1 = oy + ly;
+  int mn0 = INT_MAX, mn1 = INT_MAX, mn2 = INT_MAX, mx0 = INT_MIN, mx1 = INT_MIN, mx2 = INT_MIN;
+  if (x2 < g.d2 && x1 < g.d1 && x0 < g.d0) {
+    const uint32_t lin = static_cast<uint32_t>(x0 * g.plane + x1 * g.d2 + x2);
+    float u0 = ld_at(fc[0], lin), u1 = ld_at(fc[1], lin), u2 = ld_at(fc[2], lin);
+    if (FIRST) {
+      u0 *= scale;
+      u1 *= scale;
+      u2 *= scale;
+    }
+    const BorderCell bc = border_cell(g, x0, x1, x2, u0, u1, u2);
+    float cv[3][8];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) corners_border(fc[c], g, bc.base, cv[c]);
+    float r[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      r[c] = tri_value(cv[c], bc.t0, bc.t1, bc.t2);
+      if (FIRST) r[c] *= scale;
+    }
+    st_at(o, lin, u0 + r[0]);
+    st_at(o + g.V, lin, u1 + r[1]);
+    st_at(o + 2 * static_cast<size_t>(g.V), lin, u2 + r[2]);
+    mn0 = mx0 = bc.i0 - x0;
+    mn1 = mx1 = bc.i1 - x1;
+    mn2 = mx2 = bc.i2 - x2;
+  }
+  if (REC) {
+    mn0 = wave_min(mn0);
+    mn1 = wave_min(mn1);
+    mn2 = wave_min(mn2);
+    mx0 = wave_max(mx0);
+    mx1 = wave_max(mx1);
+    mx2 = wave_max(mx2);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+      red[0][w] = mn0;
+      red[1][w] = mn1;
+      red[2][w] = mn2;
+      red[3][w] = mx0;
+      red[4][w] = mx1;
+      red[5][w] = mx2;
+    }
+    __syncthreads();
+    if (threadIdx.x < 6) {
+      const int q = threadIdx.x;
+      int r = red[q][0];
+      for (int i = 1; i < ENT / 64; ++i) r = q < 3 ? min(r, red[q][i]) : max(r, red[q][i]);
+      int* bx = boxes + (static_cast<size_t>(s) * tg.ntiles + tile) * 8;
+      if (q < 3) {
+        atomicMin(bx + q, r);
+        if (-r > 0) atomicMax(reach + s * 8 + q, -r);
+      } else {
+        atomicMax(bx + q, r);
+        if (r + 1 > 0) atomicMax(reach + s * 8 + q, r + 1);
+      }
+    }
+    __syncthreads();  // `red` is rewritten by the block's next plane
+  }
+}
+
+// Record boxes of `count` tiles set to the empty box (min INT_MAX, max
+// INT_MIN), before planes merge into them.
+__global__ __launch_bounds__(ENT) void k_box_init(int* __restrict__ boxes, long long count) {
+  const long long stride = static_cast<long long>(gridDim.x) * ENT;
+  for (long long i = static_cast<long long>(blockIdx.x) * ENT + threadIdx.x; i < count * 8;
+       i += stride) {
+    const int e = static_cast<int>(i & 7);
+    boxes[i] = e < 3 ? INT_MAX : (e < 6 ? INT_MIN : 0);
+  }
+}
+
+template <bool FIRST, bool REC>
+__global__ __launch_bounds__(ENT) void k_exp_fwd_planes(const float* __restrict__ src,
+                                                        float* __restrict__ dst, TileGeom tg,
+                                                        float scale, int* __restrict__ boxes,
+                                                        int* __restrict__ reach) {
+  __shared__ int red[6][ENT / 64];
+  exp_fwd_plane_body<FIRST, REC>(red, blockIdx.x, src, dst, tg, scale, boxes, reach);
+}
+
+// Grid-wide barrier of a launch whose blocks are all resident.  bar[0]
+// counts arrivals over the launch (zeroed before it); the k-th barrier
+// returns once k * gridDim.x blocks have arrived.  The wait is bounded by the
+// real-time counter: a block that has waited `ticks` raises err[0] and goes
+// on, so every wave reaches the end of the kernel even if some block never
+// ran.
+__device__ __forceinline__ void grid_barrier(unsigned* bar, int* err, unsigned k,
+                                             long long ticks) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    atomicAdd(bar, 1u);
+    const unsigned target = k * gridDim.x;
+    const long long t0 = wall_clock64();
+    while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (wall_clock64() - t0 > ticks) {
+        atomicOr(err, 1);
+        break;
+      }
+      __builtin_amdgcn_s_sleep(2);
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+
+struct IterArgs {
+  const float* img;    // [B][V]
+  const float* atlas;  // [V]
+  float* v;            // [B][3][V], updated in place (no smoothing on this path)
+  float* m;
+  float* s;
+  float* v_out;        // Adam's outputs: v, m, s themselves, or scratch when timing
+  float* m_out;
+  float* s_out;
+  float* ckpt;         // [n_sq - 1][B][3][V]
+  float* uN;
+  float* gU;
+  float* gA;
+  float* gB;
+  float* gV;
+  int* boxes;          // [n_sq][B][ntiles][8]
+  int* reach;          // [n_sq][B][8]
+  size_t box_stride, reach_stride;
+  double* loss;        // loss[b * loss_stride] += L_b
+  int loss_stride;
+  RegW rw;
+  TileGeom tg;
+  BwdGeom bg;
+  int n_sq;
+  float scale;         // 2^-n_sq
+  double inv_v;
+  uint32_t nbx;        // voxel blocks per subject
+  long long count;     // B * 3V
+  const long long* step_dev;  // device step count, or NULL: step_host
+  long long step_host;
+  int k;               // inner iteration within the sweep
+  float lr;
+  double b1, b2;
+  float eps;
+  unsigned* bar;
+  int* err;
+  long long ticks;     // bound of a barrier wait (real-time counter ticks)
+};
+
+constexpr size_t kIterLds = sizeof(TiledBwdLds);
+
+template <bool L1>
+__global__ __launch_bounds__(ENT) void k_iter_fused(IterArgs a) {
+  __shared__ __align__(16) unsigned char lds[kIterLds];
+  const Geom& g = a.tg.g;
+  const uint32_t G = gridDim.x;
+  const size_t fs = static_cast<size_t>(a.tg.total / a.tg.ntiles) * 3 * g.V;
+  unsigned nbar = 0;
+  // the records are running minima / maxima: start the reaches at zero and
+  // the boxes empty
+  {
+    const long long cnt = static_cast<long long>(a.reach_stride) * a.n_sq;
+    for (long long i = static_cast<long long>(blockIdx.x) * ENT + threadIdx.x; i < cnt;
+         i += static_cast<long long>(G) * ENT)
+      a.reach[i] = 0;
+    const long long nb = static_cast<long long>(a.box_stride) * a.n_sq;
+    for (long long i = static_cast<long long>(blockIdx.x) * ENT + threadIdx.x; i < nb;
+         i += static_cast<long long>(G) * ENT) {
+      const int e = static_cast<int>(i & 7);
+      a.boxes[i] = e < 3 ? INT_MAX : (e < 6 ? INT_MIN : 0);
+    }
+  }
+  grid_barrier(a.bar, a.err, ++nbar, a.ticks);
+  // squaring steps (u_0 = v / 2^N scaled on the fly), records for the adjoint
+  int (*red)[ENT / 64] = reinterpret_cast<int(*)[ENT / 64]>(lds);
+  const float* src = a.v;
+  for (int t = 0; t < a.n_sq; ++t) {
+    float* dst = (t == a.n_sq - 1) ? a.uN : a.ckpt + static_cast<size_t>(t) * fs;
+    int* bx = a.boxes + a.box_stride * t;
+    int* rc = a.reach + a.reach_stride * t;
+    for (uint32_t b = blockIdx.x; b < a.tg.total * ETZ; b += G) {
+      if (t == 0)
+        exp_fwd_plane_body<true, true>(red, b, src, dst, a.tg, a.scale, bx, rc);
+      else
+        exp_fwd_plane_body<false, true>(red, b, src, dst, a.tg, 1.0f, bx, rc);
+    }
+    grid_barrier(a.bar, a.err, ++nbar, a.ticks);
+    src = dst;
+  }
+  // dissimilarity + regulariser, and dL/du_N
+  {
+    const uint32_t total = a.nbx * (a.tg.total / a.tg.ntiles);
+    double* rd = reinterpret_cast<double*>(lds);
+    for (uint32_t b = blockIdx.x; b < total; b += G)
+      mse_fused_block<L1, true>(xcd_remap(b, total), rd, a.img, a.atlas, a.uN, a.gU, a.loss,
+                                a.loss_stride, a.rw, g, a.inv_v, a.nbx);
+  }
+  grid_barrier(a.bar, a.err, ++nbar, a.ticks);
+  // squaring adjoint, every subject on the tiled path
+  TiledBwdLds& L = *reinterpret_cast<TiledBwdLds*>(lds);
+  const float* gin = a.gU;
+  for (int t = a.n_sq - 1; t >= 0; --t) {
+    float* gout = (t == 0) ? a.gV : (((a.n_sq - 1 - t) % 2 == 0) ? a.gA : a.gB);
+    const float* ut = (t == 0) ? a.v : a.ckpt + static_cast<size_t>(t - 1) * fs;
+    const int* bx = a.boxes + a.box_stride * t;
+    const int* rc = a.reach + a.reach_stride * t;
+    if (t == 0)
+      exp_bwd_tiled_body<true, true>(L, blockIdx.x, G, ut, gin, gout, a.bg, a.scale, a.scale, bx,
+                                     rc);
+    else
+      exp_bwd_tiled_body<false, true>(L, blockIdx.x, G, ut, gin, gout, a.bg, 1.0f, 1.0f, bx, rc);
+    grid_barrier(a.bar, a.err, ++nbar, a.ticks);
+    gin = gout;
+  }
+  // Adam; bias corrections formed in FP64 and rounded once, as the separate
+  // kernels do
+  const double tt = static_cast<double>((a.step_dev ? a.step_dev[0] : a.step_host) + a.k + 1);
+  const float bc1 = static_cast<float>(1.0 - pow(a.b1, tt));
+  const float bc2 = static_cast<float>(1.0 - pow(a.b2, tt));
+  const float b1f = static_cast<float>(a.b1), b2f = static_cast<float>(a.b2);
+  const float omb1 = static_cast<float>(1.0 - a.b1), omb2 = static_cast<float>(1.0 - a.b2);
+  for (long long i = static_cast<long long>(blockIdx.x) * ENT + threadIdx.x; i < a.count;
+       i += static_cast<long long>(G) * ENT)
+    adam_step_to(a.v, a.m, a.s, a.gV, a.v_out, a.m_out, a.s_out, i, a.lr, b1f, omb1, b2f, omb2,
+                 bc1, bc2, a.eps);
+}
+
+// A barrier that timed out leaves NaN as the group loss.
+__global__ void k_flag_loss(const int* __restrict__ err, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && err[0]) out[0] = __builtin_nan("");
+}
 }  // namespace
 
 size_t exp_aux_bytes(const Geom& g, int n, int n_sq) {
@@ -1017,7 +1307,8 @@ size_t exp_aux_bytes(const Geom& g, int n, int n_sq) {
 // planes of ramp-up; shorter ones give small cohorts enough blocks.
 int march_tz(const TileGeom& tg, int n) {
   const int tuned = tuned_tz(TUNE_EXP, tg.g, n);
-  if (tuned > 0) return tuned;
+  if (tuned > 1) return tuned;
+  if (tuned < 0) return ETZ;  // plane-parallel kernels; the chunk is not used
   // long chunks amortise the ramp-up planes, short ones keep each block's
   // planes in flight within L2 (64 planes measured no faster than 32 and
   // fetched more from HBM); shorter still for small cohorts
@@ -1025,6 +1316,20 @@ int march_tz(const TileGeom& tg, int n) {
   while (tz > ETZ && static_cast<long long>(tg.ntx) * tg.nty * ((tg.g.d0 + tz - 1) / tz) * n < 4096)
     tz /= 2;
   return tz;
+}
+
+// The other shape of the squaring steps and their adjoint: one plane of a
+// tile per block (k_exp_fwd_planes) and the tiled adjoint for every subject,
+// no marching.  It wins on small volumes, where the marching kernels' serial
+// planes are the whole cost (4 x 32^3: 0.78 ms per sweep against 1.60).
+// Untuned, it is taken when the marching grid would hold fewer than four
+// blocks per CU even with 8-plane chunks.
+bool plane_mode(const Geom& g, int n) {
+  const int tuned = tuned_tz(TUNE_EXP, g, n);
+  if (tuned != 0) return tuned < 0;
+  const long long march_blocks = static_cast<long long>((g.d2 + ETX - 1) / ETX) *
+                                 ((g.d1 + ETY - 1) / ETY) * ((g.d0 + ETZ - 1) / ETZ) * n;
+  return march_blocks < 1024;
 }
 
 void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, int* aux, const Geom& g, int n,
@@ -1039,10 +1344,21 @@ void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, int* aux, co
   const TileGeom tg = make_tiles(g, n);
   const MarchGeom m = make_march(tg, n, march_tz(tg, n));
   const AuxPtrs ap = aux_ptrs(aux, tg, n, n_sq);
-  // the reaches are running maxima: start them at zero (all-zero bits)
-  if (aux)
+  const bool planes = plane_mode(g, n);
+  // the reaches are running maxima: start them at zero (all-zero bits); the
+  // planes kernel merges into its boxes, which start empty
+  if (aux) {
     launch_fill_f32(reinterpret_cast<float*>(ap.reach),
                     static_cast<long long>(ap.reach_stride) * n_sq, 0.0f, st);
+    if (planes) {
+      const long long nbox = static_cast<long long>(ap.box_stride / 8) * n_sq;
+      prof_begin(st, KC_FILL);
+      hipLaunchKernelGGL(k_box_init, dim3(static_cast<uint32_t>(
+                                         nbox * 8 / ENT + 1 < 65536 ? nbox * 8 / ENT + 1 : 65536)),
+                         dim3(ENT), 0, st, ap.boxes, nbox);
+      prof_end(st, KC_FILL);
+    }
+  }
   // Exp(-v) negates the scaled field of the first step (exact)
   const float scale = negate ? -ldexpf(1.0f, -n_sq) : ldexpf(1.0f, -n_sq);
   const float* src = v;
@@ -1057,7 +1373,21 @@ void run_exp_fwd(const float* v, float* u, float* ckpt, float* tmp, int* aux, co
     int* bx = aux ? ap.boxes + ap.box_stride * t : nullptr;
     int* rc = aux ? ap.reach + ap.reach_stride * t : nullptr;
     prof_begin(st, KC_EXP_FWD);
-    if (t == 0) {
+    if (planes) {
+      const dim3 grid(tg.total * ETZ);
+      if (t == 0 && aux)
+        hipLaunchKernelGGL((k_exp_fwd_planes<true, true>), grid, dim3(ENT), 0, st, src, dst, tg,
+                           scale, bx, rc);
+      else if (t == 0)
+        hipLaunchKernelGGL((k_exp_fwd_planes<true, false>), grid, dim3(ENT), 0, st, src, dst, tg,
+                           scale, bx, rc);
+      else if (aux)
+        hipLaunchKernelGGL((k_exp_fwd_planes<false, true>), grid, dim3(ENT), 0, st, src, dst, tg,
+                           1.0f, bx, rc);
+      else
+        hipLaunchKernelGGL((k_exp_fwd_planes<false, false>), grid, dim3(ENT), 0, st, src, dst,
+                           tg, 1.0f, bx, rc);
+    } else if (t == 0) {
       if (aux)
         hipLaunchKernelGGL((k_exp_fwd<true, true>), dim3(m.total), dim3(ENT), 0, st, src, dst, m,
                            scale, bx, rc);
@@ -1091,21 +1421,32 @@ void launch_rec(const float* ut, bool first, const TileGeom& tg, float scale, in
 }
 
 void launch_bwd_step(const float* ut, const float* gin, float* gout, bool first, const MarchGeom& m,
-                     const BwdGeom& bg, float scale, const int* bx, const int* rc,
+                     const BwdGeom& bg, float scale, const int* bx, const int* rc, bool planes,
                      hipStream_t st) {
+  prof_begin(st, KC_EXP_BWD);
+  if (planes) {
+    // every subject on the tiled adjoint
+    if (first)
+      hipLaunchKernelGGL((k_exp_bwd<true, true>), dim3(bwd_grid(bg)), dim3(BNT), 0, st, ut, gin,
+                         gout, bg, scale, scale, bx, rc);
+    else
+      hipLaunchKernelGGL((k_exp_bwd<false, true>), dim3(bwd_grid(bg)), dim3(BNT), 0, st, ut, gin,
+                         gout, bg, 1.0f, 1.0f, bx, rc);
+    prof_end(st, KC_EXP_BWD);
+    return;
+  }
   // each subject is handled by exactly one of the two kernels (decided on the
   // device from its reach); the other one's blocks return at once
-  prof_begin(st, KC_EXP_BWD);
   if (first) {
     hipLaunchKernelGGL((k_exp_bwd_march<true>), dim3(m.total), dim3(ENT), 0, st, ut, gin, gout, m,
                        scale, scale, rc);
-    hipLaunchKernelGGL((k_exp_bwd<true>), dim3(bwd_grid(bg)), dim3(BNT), 0, st, ut, gin, gout, bg,
-                       scale, scale, bx, rc);
+    hipLaunchKernelGGL((k_exp_bwd<true, false>), dim3(bwd_grid(bg)), dim3(BNT), 0, st, ut, gin,
+                       gout, bg, scale, scale, bx, rc);
   } else {
     hipLaunchKernelGGL((k_exp_bwd_march<false>), dim3(m.total), dim3(ENT), 0, st, ut, gin, gout, m,
                        1.0f, 1.0f, rc);
-    hipLaunchKernelGGL((k_exp_bwd<false>), dim3(bwd_grid(bg)), dim3(BNT), 0, st, ut, gin, gout, bg,
-                       1.0f, 1.0f, bx, rc);
+    hipLaunchKernelGGL((k_exp_bwd<false, false>), dim3(bwd_grid(bg)), dim3(BNT), 0, st, ut, gin,
+                       gout, bg, 1.0f, 1.0f, bx, rc);
   }
   prof_end(st, KC_EXP_BWD);
 }
@@ -1141,7 +1482,7 @@ void run_exp_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v
     float* gout = (t == 0) ? g_v : (((n_sq - 1 - t) % 2 == 0) ? tmp_a : tmp_b);
     const float* ut = (t == 0) ? v : ckpt + static_cast<size_t>(t - 1) * fs;
     launch_bwd_step(ut, gin, gout, t == 0, m, bg, scale, ap.boxes + ap.box_stride * t,
-                    ap.reach + ap.reach_stride * t, st);
+                    ap.reach + ap.reach_stride * t, plane_mode(g, n), st);
     gin = gout;
   }
 }
@@ -1176,9 +1517,123 @@ void run_exp_bwd_recompute(const float* v, const float* g_u, float* g_v, float* 
     int* rc = ap.reach + ap.reach_stride * t;
     launch_rec(ut, t == 0, tg, scale, bx, rc, st);
     float* gout = (t == 0) ? g_v : (((n_sq - 1 - t) % 2 == 0) ? tmp_a : tmp_b);
-    launch_bwd_step(ut, gin, gout, t == 0, m, bg, scale, bx, rc, st);
+    launch_bwd_step(ut, gin, gout, t == 0, m, bg, scale, bx, rc, plane_mode(g, n), st);
     gin = gout;
   }
 }
+
+namespace {
+
+long long g_barrier_ticks = kDefaultBarrierTicks;
+
+// Resident blocks of the fused kernel on the current device (0 when the
+// query fails).
+template <bool L1>
+int fused_capacity() {
+  static int cap[2][64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  int& c = cap[L1 ? 1 : 0][dev];
+  if (c == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_iter_fused<L1>, ENT, 0) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    c = per_cu * cus;
+  }
+  return c;
+}
+
+template <bool L1>
+bool launch_iter(const IterArgs& a, uint32_t needed, hipStream_t st) {
+  const int cap = fused_capacity<L1>();
+  if (cap < 8) return false;
+  uint32_t grid = needed < static_cast<uint32_t>(cap) ? needed : static_cast<uint32_t>(cap);
+  // a multiple of the 8 XCDs, so that the XCD of a virtual block index is
+  // that of the hardware block running it
+  // at most 128 blocks: every block's agent-scope fence in a grid barrier
+  // writes back its XCD's L2, and the fences serialise (measured 4.6 us per
+  // barrier at 64 blocks, 8.1 at 128, 37 at 512)
+  grid = grid < 128u ? grid : 128u;
+  grid = grid >= 8 ? grid / 8 * 8 : 8;
+  if (grid > static_cast<uint32_t>(cap)) return false;
+  hipLaunchKernelGGL((k_iter_fused<L1>), dim3(grid), dim3(ENT), 0, st, a);
+  return true;
+}
+
+}  // namespace
+
+bool run_iter_fused(const float* img, const float* atlas, float* v, float* m, float* s,
+                    float* ckpt, int* aux, float* uN, float* gU, float* gA, float* gB, float* gV,
+                    double* loss, int loss_stride, const RegW& rw, const Geom& g, int n, int n_sq,
+                    const long long* step_dev, long long step_host, int k, float lr, double b1,
+                    double b2, float eps, bool l1, unsigned* bar, int* err, hipStream_t st,
+                    float* v_out, float* m_out, float* s_out) {
+  if (n_sq < 1 || (!ckpt && n_sq >= 2)) return false;
+  const TileGeom tg = make_tiles(g, n);
+  const AuxPtrs ap = aux_ptrs(aux, tg, n, n_sq);
+  IterArgs a;
+  a.img = img;
+  a.atlas = atlas;
+  a.v = v;
+  a.m = m;
+  a.s = s;
+  a.v_out = v_out ? v_out : v;
+  a.m_out = m_out ? m_out : m;
+  a.s_out = s_out ? s_out : s;
+  a.ckpt = ckpt;
+  a.uN = uN;
+  a.gU = gU;
+  a.gA = gA;
+  a.gB = gB;
+  a.gV = gV;
+  a.boxes = ap.boxes;
+  a.reach = ap.reach;
+  a.box_stride = ap.box_stride;
+  a.reach_stride = ap.reach_stride;
+  a.loss = loss;
+  a.loss_stride = loss_stride;
+  a.rw = rw;
+  a.tg = tg;
+  a.bg = make_bwd(tg, n);
+  a.n_sq = n_sq;
+  a.scale = ldexpf(1.0f, -n_sq);
+  a.inv_v = 1.0 / g.V;
+  a.nbx = blocks_for(g.V, kBlock);
+  a.count = static_cast<long long>(n) * 3 * g.V;
+  a.step_dev = step_dev;
+  a.step_host = step_host;
+  a.k = k;
+  a.lr = lr;
+  a.b1 = b1;
+  a.b2 = b2;
+  a.eps = eps;
+  a.bar = bar;
+  a.err = err;
+  a.ticks = g_barrier_ticks;
+  const uint32_t nv = a.nbx * static_cast<uint32_t>(n);
+  uint32_t needed = tg.total * ETZ > nv ? tg.total * ETZ : nv;
+  needed = needed > a.bg.total ? needed : a.bg.total;
+  // the arrival counter starts every launch at zero (a fill kernel, so that
+  // the sequence can be captured)
+  launch_fill_f32(reinterpret_cast<float*>(bar), 1, 0.0f, st);
+  prof_begin(st, KC_ITER);
+  const bool ok = l1 ? launch_iter<true>(a, needed, st) : launch_iter<false>(a, needed, st);
+  prof_end(st, KC_ITER);
+  return ok;
+}
+
+void flag_fused_error(const int* err, double* out, hipStream_t st) {
+  prof_begin(st, KC_MISC);
+  hipLaunchKernelGGL(k_flag_loss, dim3(1), dim3(64), 0, st, err, out);
+  prof_end(st, KC_MISC);
+}
+
+void set_barrier_ticks(long long ticks) {
+  g_barrier_ticks = ticks < 0 ? kDefaultBarrierTicks : ticks;
+}
+
+int fused_resident_blocks(bool l1) { return l1 ? fused_capacity<true>() : fused_capacity<false>(); }
 
 }  // namespace darc

@@ -3,6 +3,7 @@
 // blocks, blocks remapped so that each XCD walks a contiguous range of voxels
 // (the gathers of neighbouring voxels then share that XCD's L2).
 #include "darc_kernels.hpp"
+#include "voxel_bodies.hpp"
 
 namespace darc {
 
@@ -62,19 +63,6 @@ __global__ __launch_bounds__(kBlock) void k_warp_bwd(const float* __restrict__ i
 
 // -------------------------------------------------------------------- MSE
 
-// Pointwise dissimilarity of d = Iw - A: MSE (d^2, gradient 2d/V) or L1
-// (|d|, subgradient sign(d)/V with sign(0) = 0).  The difference is formed in
-// FP64 from the FP32 inputs, so the sign is exact.
-template <bool L1>
-__device__ __forceinline__ double point_loss(double d) {
-  return L1 ? fabs(d) : d * d;
-}
-template <bool L1>
-__device__ __forceinline__ float point_grad(double d, double inv_v) {
-  return L1 ? static_cast<float>(((d > 0.0) - (d < 0.0)) * inv_v)
-            : static_cast<float>(2.0 * inv_v * d);
-}
-
 template <bool L1>
 __global__ __launch_bounds__(kBlock) void k_mse(const float* __restrict__ w,
                                                 const float* __restrict__ atlas,
@@ -104,36 +92,8 @@ __global__ __launch_bounds__(kBlock) void k_mse_fused(const float* __restrict__ 
                                                       RegW rw, Geom g, double inv_v, uint32_t nbx,
                                                       uint32_t total) {
   __shared__ double red[kBlock / 64];
-  const VoxelBlock vb = voxel_block(nbx, total);
-  double acc = 0.0;
-  if (vb.lin < g.V) {
-    const int lin = vb.lin;
-    const float* I = img + static_cast<size_t>(vb.s) * g.V;
-    const size_t off = static_cast<size_t>(vb.s) * 3 * g.V;
-    const float* f = u + off;
-    int x0, x1, x2;
-    voxel_coords(g, lin, x0, x1, x2);
-    const Tri t = sample_zero(I, g, x0, x1, x2, f[lin], f[g.V + lin], f[2 * g.V + lin]);
-    const double diff = static_cast<double>(t.v) - static_cast<double>(atlas[lin]);
-    acc = point_loss<L1>(diff) * inv_v;
-    float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f;
-    if (rw.on) {
-      double racc = 0.0;
-      r0 = reg_at(f, g, lin, x0, x1, x2, rw, racc);
-      r1 = reg_at(f + g.V, g, lin, x0, x1, x2, rw, racc);
-      r2 = reg_at(f + 2 * g.V, g, lin, x0, x1, x2, rw, racc);
-      acc += rw.lam * racc;
-    }
-    if (GRAD) {
-      const float gw = point_grad<L1>(diff, inv_v);
-      float* o = gu + off;
-      o[lin] = gw * t.d0 + r0;
-      o[g.V + lin] = gw * t.d1 + r1;
-      o[2 * g.V + lin] = gw * t.d2 + r2;
-    }
-  }
-  const double tot = block_sum<kBlock>(acc, red);
-  if (threadIdx.x == 0) atomicAdd(loss + static_cast<size_t>(vb.s) * loss_stride, tot);
+  mse_fused_block<L1, GRAD>(xcd_remap(blockIdx.x, total), red, img, atlas, u, gu, loss,
+                            loss_stride, rw, g, inv_v, nbx);
 }
 
 // Diffusion regulariser of an ncomp-component field (one launch covers the
@@ -172,14 +132,8 @@ __global__ __launch_bounds__(kBlock) void k_adam(const float* __restrict__ v_in,
                                                  float omb2, float bc1, float bc2, float eps) {
   const long long stride = static_cast<long long>(gridDim.x) * kBlock;
   for (long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x; i < count;
-       i += stride) {
-    const float gi = g[i];
-    const float mi = b1 * m[i] + omb1 * gi;
-    const float si = b2 * s[i] + omb2 * gi * gi;
-    m[i] = mi;
-    s[i] = si;
-    v_out[i] = v_in[i] - lr * (mi / bc1) / (sqrtf(si / bc2) + eps);
-  }
+       i += stride)
+    adam_update(v_in, v_out, m, s, g, i, lr, b1, omb1, b2, omb2, bc1, bc2, eps);
 }
 
 // The step count lives on the device so that a captured sweep can be
@@ -207,14 +161,8 @@ __global__ __launch_bounds__(kBlock) void k_adam_dev(const float* __restrict__ v
   const float bc1 = bc[0], bc2 = bc[1];
   const long long stride = static_cast<long long>(gridDim.x) * kBlock;
   for (long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x; i < count;
-       i += stride) {
-    const float gi = g[i];
-    const float mi = b1 * m[i] + omb1 * gi;
-    const float si = b2 * s[i] + omb2 * gi * gi;
-    m[i] = mi;
-    s[i] = si;
-    v_out[i] = v_in[i] - lr * (mi / bc1) / (sqrtf(si / bc2) + eps);
-  }
+       i += stride)
+    adam_update(v_in, v_out, m, s, g, i, lr, b1, omb1, b2, omb2, bc1, bc2, eps);
 }
 
 // ---------------------------------------------------------------- centring

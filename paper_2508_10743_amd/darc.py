@@ -23,6 +23,7 @@ from ._lib import DarcError  # noqa: F401
 
 METRICS = {"mse": L.DARC_MSE, "lncc": L.DARC_LNCC, "l1": L.DARC_L1}
 ATLAS_MODES = {"mean": L.DARC_ATLAS_MEAN, "median": L.DARC_ATLAS_MEDIAN, "sgd": L.DARC_ATLAS_SGD}
+FUSED_MODES = {"auto": L.DARC_FUSED_AUTO, "off": L.DARC_FUSED_OFF, "on": L.DARC_FUSED_ON}
 SGD_INITS = {"warm": L.DARC_SGD_INIT_WARM, "initial": L.DARC_SGD_INIT_INITIAL}
 CENTER_MODES = {"displacement": L.DARC_CENTER_DISPLACEMENT, "velocity": L.DARC_CENTER_VELOCITY}
 
@@ -379,6 +380,7 @@ class SweepParams:
     atlas_batch: int = 4  # stochastic atlas: subjects per minibatch
     atlas_lr: float = 1e-2  # stochastic atlas: Adam learning rate
     sgd_init: str = "warm"  # stochastic atlas start: warm (A^k) | initial (A^0, Alg. 1 literal)
+    fused: str = "auto"  # one launch per inner iteration: auto | off | on (MSE/L1, no smoothing)
 
     def resolved_atlas_mode(self) -> str:
         if self.atlas_mode != "auto":
@@ -391,7 +393,7 @@ class SweepParams:
                             self.beta1, self.beta2, self.adam_eps,
                             CENTER_MODES[self.center_mode], int(self.reinit_v), self.batch,
                             ATLAS_MODES[self.resolved_atlas_mode()], self.k3, self.atlas_batch,
-                            self.atlas_lr, SGD_INITS[self.sgd_init])
+                            self.atlas_lr, SGD_INITS[self.sgd_init], FUSED_MODES[self.fused])
 
 
 class Cohort:
@@ -476,14 +478,16 @@ class Cohort:
 
     def autotune(self) -> tuple:
         """Time the candidate plane-chunk lengths of the marching kernels on
-        this cohort's shapes and keep the fastest for later launches; returns
-        (squaring chunk, window-kernel chunk).  Only workspace memory is
+        this cohort's shapes, and (MSE / L1 without smoothing) one fused
+        inner iteration against separate launches, and keep the fastest for
+        later launches; returns (squaring chunk, window-kernel chunk, fused
+        choice: 1 fused, 2 separate, 0 not tuned).  Only workspace memory is
         written; the cohort state is left as it is."""
         self._refresh_state()
-        chosen = (ctypes.c_int * 2)()
+        chosen = (ctypes.c_int * 3)()
         _call("darc_autotune", ctypes.byref(self._state), ctypes.byref(self._cparams),
               _p(self.ws), self.ws.numel(), _stream(), chosen)
-        return int(chosen[0]), int(chosen[1])
+        return int(chosen[0]), int(chosen[1]), int(chosen[2])
 
     def capture(self) -> "SweepGraph":
         """Capture one sweep into a HIP graph (needs ``device_step=True``).
@@ -558,6 +562,27 @@ class SweepGraph:
         c.step += c.params.k2
         c.sweeps += 1
         return c.losses
+
+
+SHAPE_KINDS = {"squaring": L.DARC_SHAPE_SQUARING, "window": L.DARC_SHAPE_WINDOW,
+               "fused": L.DARC_SHAPE_FUSED}
+
+
+def set_launch_shape(kind: str, dims, n: int, value: int) -> None:
+    """Set one entry of the autotuner's table for volumes ``dims`` and ``n``
+    subjects per launch, or for every shape without an entry of its own
+    (``dims=None``): kind "squaring": tile depth, 1 marching at the built-in
+    depth, -1 one plane per block; "window": tile depth; "fused": 1 fused, 2
+    separate; 0 resets."""
+    d0, d1, d2 = dims if dims is not None else (0, 0, 0)
+    n = n if dims is not None else 0
+    _call("darc_set_launch_shape", SHAPE_KINDS[kind], d0, d1, d2, n, value)
+
+
+def fused_barrier_ticks(ticks: int) -> None:
+    """Bound of one grid-barrier wait of the fused iteration (ticks of the
+    100 MHz counter; negative restores the one-second default)."""
+    _call("darc_fused_barrier_ticks", int(ticks))
 
 
 def autotune_clear() -> None:

@@ -85,7 +85,7 @@ def test_autotune_keeps_results(dev, metric, sigma):
     try:
         chosen = tuned.autotune()
         torch.cuda.synchronize()
-        assert chosen[0] in (8, 16, 32, 64)
+        assert chosen[0] in (-1, 8, 16, 32, 64)
         if metric == "lncc" or sigma > 0:
             assert chosen[1] in (8, 16, 32, 64)
         assert torch.equal(tuned.v, v0) and torch.equal(tuned.atlas, a0)

@@ -34,6 +34,16 @@ def dev():
     return torch.device("cuda", 0)
 
 
+@pytest.fixture(autouse=True, params=["march", "planes"])
+def squaring_shape(request, dev):
+    """Every test of this module runs with the marching squaring kernels and
+    with the plane-parallel ones (one plane of a tile per block, the tiled
+    adjoint for every subject)."""
+    D.set_launch_shape("squaring", None, 0, 1 if request.param == "march" else -1)
+    yield request.param
+    D.autotune_clear()
+
+
 def g(a, dev):
     return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
 

@@ -653,36 +653,40 @@ __global__ __launch_bounds__(BNT) void k_exp_bwd(const float* __restrict__ ut,
 // Adjoint of one squaring step, marching, for a subject whose every cell
 // offset lies in [-1, 0] (reach 1 in every direction: all |u_t| < 1, the
 // case of the early sweeps and of the first squaring steps).  A source in
-// plane p then falls in cell plane p-1 or p, and the targets of plane z
-// gather from cell planes z-1 and z only, so two cell planes (by parity) and
-// two overflow planes are live at a time, which keeps the block's LDS under
-// a third of the CU's.  Iteration z: (i) clear cell plane z and target plane
-// z+1's overflow, stage u_t of plane z+1; (ii) cells of the plane-(z+1)
-// sources; (iii) fill cell plane z with the plane-z sources whose cell is in
-// it (cells kept from the last iteration) and the plane-(z+1) sources whose
-// cell is in it (one LDS integer atomic each, two zero-initialised slots per
-// cell, further sources into the overflow accumulator); (iv) the direct term
-// g + J^T g of the plane-z targets; (v) gather, for each target, the sources
-// binned in its 8 neighbouring cells.  Thread (ly, lx) stages and bins its
-// own voxel, so a voxel's cell and g stay in its registers from staging to
-// its direct term; threads below 84 also stage one voxel of the one-voxel
-// halo ring.  Blocks of subjects with a larger reach return at once: the
-// tiled kernel handles those.
+// plane p then falls in cell plane p-1 or p, and cell plane c feeds exactly
+// target planes c (as corner a = 0 of its cells) and c + 1 (corner a = 1).
+// So one cell plane is live at a time: iteration z fills cell plane z and one
+// pass over it completes the targets of plane z (their a = 1 part came from
+// cell plane z - 1 in the previous iteration) and starts those of plane
+// z + 1, kept in registers.  Each slot read serves both targets, which share
+// the in-plane weight; the block's LDS (one cell plane, two overflow planes,
+// the u ring) stays near a quarter of the CU's.  Iteration z: (i) clear the
+// cell plane and target plane z+1's overflow, stage u_t of plane z+1; (ii)
+// cells of the plane-(z+1) sources; (iii) fill cell plane z with the plane-z
+// sources whose cell is in it (cells kept from the last iteration) and the
+// plane-(z+1) sources whose cell is in it (one LDS integer atomic each, two
+// zero-initialised slots per cell, further sources into the overflow
+// accumulator); (iv) the direct term g + J^T g of the plane-z targets; (v)
+// the gather over the four cells around each column.  Thread (ly, lx) stages
+// and bins its own voxel, so a voxel's cell and g stay in its registers from
+// staging to its direct term; threads below 84 also stage one voxel of the
+// one-voxel halo ring.  Blocks of subjects with a larger reach return at
+// once: the tiled kernel handles those.
 constexpr int MCX = ETX + 1, MCY = ETY + 1;  // cells per cell plane: 33 x 9
 constexpr int MCP = MCX * MCY;
 constexpr int MRING = MHP - ENT;             // halo ring positions (84)
 
 template <bool FIRST>
-__global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__ ut,
-                                                       const float* __restrict__ gin,
-                                                       float* __restrict__ gout, MarchGeom m,
-                                                       float scale, float oscale,
-                                                       const int* __restrict__ reach) {
-  __shared__ float uring[3][3][MHP];     // u_t of planes z-1, z, z+1 (slot p % 3)
-  __shared__ int bcnt[2][MCP];           // cell planes by parity
-  __shared__ float4 bd4[2][KSLOT][MCP];  // t0, t1, t2, g0 per binned source (0 if empty)
-  __shared__ float2 bd2[2][KSLOT][MCP];  // g1, g2
-  __shared__ float ovf[2][3][ENT];       // overflow into target planes, by parity
+__global__ __launch_bounds__(ENT, 4) void k_exp_bwd_march(const float* __restrict__ ut,
+                                                          const float* __restrict__ gin,
+                                                          float* __restrict__ gout, MarchGeom m,
+                                                          float scale, float oscale,
+                                                          const int* __restrict__ reach) {
+  __shared__ float uring[3][3][MHP];  // u_t of planes z-1, z, z+1 (slot p % 3)
+  __shared__ int bcnt[MCP];           // the live cell plane
+  __shared__ float4 bd4[KSLOT][MCP];  // t0, t1, t2, g0 per binned source (0 if empty)
+  __shared__ float2 bd2[KSLOT][MCP];  // g1, g2
+  __shared__ float ovf[2][3][ENT];    // overflow into target planes, by parity
   const Geom& g = m.rec.g;
   const MarchId id = march_id(m);
   {
@@ -763,18 +767,17 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
         for (int c = 0; c < 3; ++c) uring[su][c][pe[j]] = su_[j][c];
       }
   };
-  auto clear_cells = [&](int cplane) {
-    const int cs = cplane & 1;
+  auto clear_cells = [&]() {
     const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     const float2 z2 = make_float2(0.0f, 0.0f);
     // threads in reverse order: the cells past ENT fall to the last wave,
     // which stages no halo voxels
     for (int i = ENT - 1 - static_cast<int>(threadIdx.x); i < MCP; i += ENT) {
-      bcnt[cs][i] = 0;
+      bcnt[i] = 0;
 #pragma unroll
       for (int k = 0; k < KSLOT; ++k) {
-        bd4[cs][k][i] = z4;
-        bd2[cs][k][i] = z2;
+        bd4[k][i] = z4;
+        bd2[k][i] = z2;
       }
     }
   };
@@ -800,20 +803,18 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
       }
     }
   };
-  // bin one source into its cell (plane bc.i0, which must be the plane being filled)
-  // Every call site bins into the cell plane being filled, which lies in
-  // [z0 - 1, z1 - 1].  The cell of a tile voxel (halo = false) always lies in
-  // the tile's cell region (offsets in [-1, 0], and border clamping keeps a
-  // cell inside the volume); a halo voxel's cell may not.
+  // Bin one source into the live cell plane (its plane bc.i0 is the one
+  // being filled).  The cell of a tile voxel (halo = false) always lies in the
+  // tile's cell region (offsets in [-1, 0], and border clamping keeps a cell
+  // inside the volume); a halo voxel's cell may not.
   auto bin_one = [&](const BorderCell& bc, float g0, float g1, float g2, bool halo) {
     const int c1 = bc.i1 - id.oy + 1, c2 = bc.i2 - id.ox + 1;
     if (halo && (c1 < 0 || c1 >= MCY || c2 < 0 || c2 >= MCX)) return;
     const int ci = c1 * MCX + c2;
-    const int cs = bc.i0 & 1;
-    const int slot = atomicAdd(&bcnt[cs][ci], 1);
+    const int slot = atomicAdd(&bcnt[ci], 1);
     if (slot < KSLOT) {
-      bd4[cs][slot][ci] = make_float4(bc.t0, bc.t1, bc.t2, g0);
-      bd2[cs][slot][ci] = make_float2(g1, g2);
+      bd4[slot][ci] = make_float4(bc.t0, bc.t1, bc.t2, g0);
+      bd2[slot][ci] = make_float2(g1, g2);
     } else {
       const float w0[2] = {1.0f - bc.t0, bc.t0};
       const float w1[2] = {1.0f - bc.t1, bc.t1};
@@ -839,15 +840,47 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
       }
     }
   };
+  // One pass over the live cell plane: for each of the four cells around the
+  // thread's column and each slot, w12 = the in-plane weight of the corner
+  // (b, e); the target of the cell's lower plane (a = 0) takes w12 (1 - t0),
+  // the one of its upper plane (a = 1) w12 t0.  Empty slots hold zeros.
+  auto gather = [&](float (&lo)[3], float (&up)[3], bool upper) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int ci = (ly + 1 - b) * MCX + (lx + 1 - e);
+#pragma unroll
+        for (int j = 0; j < KSLOT; ++j) {
+          const float4 p = bd4[j][ci];
+          const float2 q = bd2[j][ci];
+          const float w1 = b ? p.y : 1.0f - p.y;
+          const float w12 = e ? w1 * p.z : fmaf(-w1, p.z, w1);
+          const float wl = fmaf(-w12, p.x, w12);
+          lo[0] += wl * p.w;
+          lo[1] += wl * q.x;
+          lo[2] += wl * q.y;
+          if (upper) {
+            const float wu = w12 * p.x;
+            up[0] += wu * p.w;
+            up[1] += wu * q.x;
+            up[2] += wu * q.y;
+          }
+        }
+      }
+    }
+  };
 
   const bool colv = pin[0];
   BorderCell cb[2], nb[2];  // cells of the plane-z and plane-(z+1) sources
   bool cok[2], nok[2];
   float cg[2][3], qu[2][3], qg[2][3];
+  // targets of the next plane, partly gathered (their a = 1 part)
+  float accA[3] = {0.0f, 0.0f, 0.0f}, accB[3] = {0.0f, 0.0f, 0.0f};
 
-  // prologue: cell plane z0-1 from the sources of planes z0-1 and z0; planes
-  // z0+1 and z0+2 in flight
-  clear_cells(id.z0 - 1);
+  // prologue: cell plane z0-1 from the sources of planes z0-1 and z0, and
+  // its a = 1 part of the plane-z0 targets; planes z0+1 and z0+2 in flight
+  clear_cells();
   clear_ovf(id.z0);
   load_plane(id.z0 - 1, pu, pg);
   store_u(id.z0 - 1, pu);
@@ -875,11 +908,19 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
   load_plane(id.z0 + 1, pu, pg);
   load_plane(id.z0 + 2, pu2, pg2);
   __syncthreads();
+  {
+    float none[3] = {0.0f, 0.0f, 0.0f};
+    if (colv) gather(none, accA, true);
+  }
+  __syncthreads();
 
-  // one plane; (xu, xg) holds plane z+1 on entry and takes plane z+3
-  auto step = [&](int z, float (&xu)[2][3], float (&xg)[2][3]) {
-    // (i) clear cell plane z (held z-2) and target plane z+1 (held z-1); stage u of plane z+1
-    clear_cells(z);
+  // one plane; (xu, xg) holds plane z+1 on entry and takes plane z+3; acc
+  // holds the plane-z targets' a = 1 part and receives plane z+1's
+  auto step = [&](int z, float (&xu)[2][3], float (&xg)[2][3], float (&acc)[3],
+                  float (&nacc)[3]) {
+    // (i) clear the cell plane (held z-1) and target plane z+1 (held z-1);
+    //     stage u of plane z+1
+    clear_cells();
     clear_ovf(z + 1);
     store_u(z + 1, xu);
 #pragma unroll
@@ -900,7 +941,7 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
       if (nok[j] && nb[j].i0 == z) bin_one(nb[j], qg[j][0], qg[j][1], qg[j][2], j == 1);
     }
     // (iv) direct term of the plane-z targets
-    float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f;
+    float r[3] = {acc[0], acc[1], acc[2]};
     const int szm = (z + 2) % 3, szc = z % 3, szp = (z + 1) % 3;  // slots of z-1, z, z+1
     if (colv) {
       const BorderCell& bc = cb[0];
@@ -943,41 +984,24 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
           t.d2 += tc.d2 * cg[0][c];
         }
       }
-      r0 = cg[0][0] + (bc.k0 ? 0.0f : t.d0 * js);
-      r1 = cg[0][1] + (bc.k1 ? 0.0f : t.d1 * js);
-      r2 = cg[0][2] + (bc.k2 ? 0.0f : t.d2 * js);
+      r[0] += cg[0][0] + (bc.k0 ? 0.0f : t.d0 * js);
+      r[1] += cg[0][1] + (bc.k1 ? 0.0f : t.d1 * js);
+      r[2] += cg[0][2] + (bc.k2 ? 0.0f : t.d2 * js);
     }
     __syncthreads();
-    // (v) gather from cell planes z-1 (a = 1) and z (a = 0); empty slots hold zeros
+    // (v) gather: finish the plane-z targets, start the plane-(z+1) ones
+#pragma unroll
+    for (int c = 0; c < 3; ++c) nacc[c] = 0.0f;
     if (colv) {
-#pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int cs = (z - a) & 1;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-#pragma unroll
-          for (int e = 0; e < 2; ++e) {
-            const int ci = (ly + 1 - b) * MCX + (lx + 1 - e);
-#pragma unroll
-            for (int j = 0; j < KSLOT; ++j) {
-              const float4 p = bd4[cs][j][ci];
-              const float2 q = bd2[cs][j][ci];
-              const float w = corner_weight(a, b, e, p.x, p.y, p.z);
-              r0 += w * p.w;
-              r1 += w * q.x;
-              r2 += w * q.y;
-            }
-          }
-        }
-      }
+      gather(r, nacc, z + 1 < id.z1);
       const float* ov = &ovf[z & 1][0][0];
-      r0 += ov[threadIdx.x];
-      r1 += ov[ENT + threadIdx.x];
-      r2 += ov[2 * ENT + threadIdx.x];
+      r[0] += ov[threadIdx.x];
+      r[1] += ov[ENT + threadIdx.x];
+      r[2] += ov[2 * ENT + threadIdx.x];
       const uint32_t lin = static_cast<uint32_t>(z * g.plane + py[0] * g.d2 + px[0]);
-      st_at(go, lin, r0 * oscale);
-      st_at(go + g.V, lin, r1 * oscale);
-      st_at(go + 2 * static_cast<size_t>(g.V), lin, r2 * oscale);
+      st_at(go, lin, r[0] * oscale);
+      st_at(go + g.V, lin, r[1] * oscale);
+      st_at(go + 2 * static_cast<size_t>(g.V), lin, r[2] * oscale);
     }
     // (vi) the plane-(z+1) sources become the next iteration's plane-z sources
 #pragma unroll
@@ -989,10 +1013,10 @@ __global__ __launch_bounds__(ENT) void k_exp_bwd_march(const float* __restrict__
     }
     __syncthreads();
   };
-  // unrolled by two so that each prefetch buffer keeps its registers
+  // unrolled by two so that each prefetch buffer and partial keeps its registers
   for (int z = id.z0; z < id.z1; z += 2) {
-    step(z, pu, pg);
-    if (z + 1 < id.z1) step(z + 1, pu2, pg2);
+    step(z, pu, pg, accA, accB);
+    if (z + 1 < id.z1) step(z + 1, pu2, pg2, accB, accA);
   }
 }
 

@@ -264,7 +264,7 @@ def cpu_baseline(w, max_crop=(40, 96, 112), n_sub=2):
 
 
 def run_workload(D, w, batch, steps, warmup, dev, profile=True, graph=False, keep=False,
-                 workers=1):
+                 workers=1, autotune=False):
     """Generate workload `w`, run `warmup` untimed sweeps and `steps` timed
     ones; returns (result dict, cohort or None)."""
     import torch
@@ -279,6 +279,11 @@ def run_workload(D, w, batch, steps, warmup, dev, profile=True, graph=False, kee
                            beta1=w.beta1, beta2=w.beta2, adam_eps=w.adam_eps, batch=batch)
     cohort = D.Cohort(images, params, device_step=graph)
     torch.cuda.synchronize()
+    tuned = None
+    if autotune:
+        t0 = time.perf_counter()
+        tuned = cohort.autotune()
+        log(f"{w.name}: autotuned launch shapes {tuned} in {time.perf_counter() - t0:.1f} s")
     for i in range(warmup):
         cohort.sweep()
         torch.cuda.synchronize()
@@ -320,6 +325,8 @@ def run_workload(D, w, batch, steps, warmup, dev, profile=True, graph=False, kee
         "group_loss": cohort.group_loss(),
         "kernels": kernels,
     }
+    if tuned is not None:
+        res["autotuned"] = {"squaring_tz": tuned[0], "window_tz": tuned[1], "fused": tuned[2]}
     if not keep:
         del cohort, images
         torch.cuda.empty_cache()
@@ -365,6 +372,8 @@ def main():
                     help="skip the warm-start time-to-loss trial")
     ap.add_argument("--no-attainable", action="store_true",
                     help="skip the copy/read/write bandwidth measurement")
+    ap.add_argument("--autotune", action="store_true",
+                    help="run the library's autotuner on the cohort before timing")
     ap.add_argument("--graph", action="store_true",
                     help="capture one sweep in a HIP graph and time its replays")
     ap.add_argument("--extras", action="store_true",
@@ -421,7 +430,7 @@ def main():
     profile = not args.no_profile and not args.graph
     res, cohort = run_workload(D, w, batch, args.steps, args.warmup, dev, profile=profile,
                                graph=args.graph, keep=args.extras,
-                               workers=workers if w.n >= 32 else 1)
+                               workers=workers if w.n >= 32 else 1, autotune=args.autotune)
     roofline = roofline_of(w, res["kernels"], attainable) if profile else None
     extras = time_extras(D, cohort, w) if args.extras else None
     del cohort
@@ -480,6 +489,7 @@ def main():
         "attainable_GBs": attainable,
         "cpu_baseline": cpu,
         "time_to_loss": ttl,
+        "autotuned": res.get("autotuned"),
         "second_workload": second,
         "kernels": res["kernels"],
     }

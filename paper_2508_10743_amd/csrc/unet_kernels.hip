@@ -192,6 +192,204 @@ __global__ __launch_bounds__(CNT) void k_conv3d(const uint16_t* __restrict__ x0,
   }
 }
 
+// Stride-1 3x3x3 convolutions with the input staged in LDS.
+//
+// A block computes a brick of 4 (d0, one plane per wave) x MT (d1, the
+// wave's row tiles) x 16 (d2, the rows of an MFMA tile) output voxels for
+// 16 NT16 output channels.  Its input brick with the one-voxel halo,
+// 6 x (MT + 2) x 18 voxels, is staged in LDS in chunks of CG channel groups
+// (8 channels each): every input value is fetched from memory once per
+// block instead of once per tap, and the 27 taps read their A fragments from
+// LDS.  A voxel's CG groups sit at a stride of an odd number of 16-byte
+// units, so the 8 lanes of a 16-byte LDS read phase (consecutive d2) hit
+// distinct banks.  Within a chunk the reduction runs over (tap, group)
+// pairs, four per 32-wide K step (one per 16-lane group), with the weights
+// read at their place in the [cout][kpad] layout.
+//
+// The index arithmetic is hoisted out of the loops: each thread decodes its
+// staging units (input voxel, inside flags) once and reuses them for every
+// chunk, whose loads it issues one chunk ahead, and a table in LDS gives each (K step, lane group) its A byte
+// offset and weight offset (the row tiles add compile-time immediates).
+// The pairs past a chunk's 27 CG read their own tap-0 input with zero
+// weights.  X0 selects how x0 is read, as in k_conv3d.
+constexpr int LBZ = CWAVES;  // output planes per block (one per wave)
+constexpr int LBX = 16;      // output voxels per MFMA row tile (d2)
+
+template <int MT>
+struct LdsBrick {
+  static constexpr int NY = MT + 2, NX = LBX + 2;
+  static constexpr int NVOX = (LBZ + 2) * NY * NX;
+};
+
+template <int NT16, int MT, int X0, int CG>
+__global__ __launch_bounds__(CNT) void k_conv3d_lds(const uint16_t* __restrict__ x0,
+                                                    const uint16_t* __restrict__ x1,
+                                                    const uint16_t* __restrict__ w,
+                                                    const float* __restrict__ bias,
+                                                    uint16_t* __restrict__ y16,
+                                                    float* __restrict__ y32, ConvGeom cg,
+                                                    int nbz, int nby, int nbx) {
+  using B = LdsBrick<MT>;
+  constexpr int SU = CG % 2 ? CG : CG + 1;  // voxel stride in 16-byte units (odd)
+  constexpr int NPAIR = 27 * CG;
+  constexpr int NSTEP = (NPAIR + 3) / 4;
+  constexpr int NUNIT = B::NVOX * CG;          // 16-byte units staged per chunk
+  constexpr int NU = (NUNIT + CNT - 1) / CNT;  // per thread
+  static_assert(CNT % CG == 0, "a thread's staging units share one channel group");
+  static_assert(NU <= 16, "staging flags fit one word");
+  __shared__ uint4 brick[B::NVOX * SU];
+  __shared__ int2 ktab[NSTEP * 4];  // (A byte offset at row tile 0, weight offset) per pair
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, kg = lane >> 4;
+  // block -> (subject, brick); consecutive bricks of a subject share an XCD
+  const long long per = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
+  const uint32_t nblk = static_cast<uint32_t>(static_cast<long long>(nbz) * nby * nbx * (cg.nvox / per));
+  uint32_t b = xcd_remap(blockIdx.x, nblk);
+  const int bx = static_cast<int>(b % nbx);
+  b /= nbx;
+  const int by = static_cast<int>(b % nby);
+  b /= nby;
+  const int bz = static_cast<int>(b % nbz);
+  const int s = static_cast<int>(b / nbz);
+  const int oz = bz * LBZ, oy = by * MT, ox = bx * LBX;
+  constexpr bool half = X0 != 0;  // x0 is stored at half resolution
+  const int h1 = half ? cg.i1 / 2 : cg.i1, h2 = half ? cg.i2 / 2 : cg.i2;
+  const long long vin0 = static_cast<long long>(half ? cg.i0 / 2 : cg.i0) * h1 * h2;
+  const long long vin1 = static_cast<long long>(cg.i0) * cg.i1 * cg.i2;
+  const uint16_t* sx0 = x0 + s * vin0 * cg.c0;
+  const uint16_t* sx1 = x1 ? x1 + s * vin1 * cg.c1 - cg.c0 : nullptr;  // x1 channels follow c0
+  const int cvec = (cg.c0 + cg.c1) >> 3;
+  const int nco0 = blockIdx.y * 16 * NT16;
+
+  // the K-step table: pair q = 4 st + lane group, tap q / CG, group q % CG
+  if (threadIdx.x < NSTEP * 4) {
+    const int q = threadIdx.x;
+    const int tap = q < NPAIR ? q / CG : 0, g = q % CG;
+    const int toff = ((tap / 9) * B::NY + (tap / 3) % 3) * B::NX + tap % 3;
+    ktab[q] = make_int2(toff * SU * 16 + g * 16, q < NPAIR ? (tap * cvec + g) * 8 : -1);
+  }
+  // staging units of this thread: input voxel (full and, for x0 at half
+  // resolution, half resolution); bit j of ubits: unit j inside the volume,
+  // bit 16 + j: on the even grid (zero-dilated x0)
+  const int sg = threadIdx.x % CG;  // its channel group within a chunk
+  int uvf[NU], uvh[NU];
+  unsigned ubits = 0u;
+#pragma unroll
+  for (int j = 0; j < NU; ++j) {
+    const int i = threadIdx.x + j * CNT;
+    const int vb = (i < NUNIT ? i : 0) / CG;
+    const int ex = vb % B::NX, rest = vb / B::NX;
+    const int ey = rest % B::NY, ez = rest / B::NY;
+    const int p0 = oz - 1 + ez, p1 = oy - 1 + ey, p2 = ox - 1 + ex;
+    const bool in = i < NUNIT && static_cast<unsigned>(p0) < static_cast<unsigned>(cg.i0) &&
+                    static_cast<unsigned>(p1) < static_cast<unsigned>(cg.i1) &&
+                    static_cast<unsigned>(p2) < static_cast<unsigned>(cg.i2);
+    uvf[j] = in ? (p0 * cg.i1 + p1) * cg.i2 + p2 : 0;
+    uvh[j] = in ? ((p0 >> 1) * h1 + (p1 >> 1)) * h2 + (p2 >> 1) : 0;
+    ubits |= (in ? 1u : 0u) << j;
+    ubits |= (X0 != 2 || !((p0 | p1 | p2) & 1) ? 1u : 0u) << (16 + j);
+  }
+  // brick slot of unit j: (threadIdx.x + j CNT) / CG voxels in, group sg
+  const int slot0 = (threadIdx.x / CG) * SU + sg;
+  constexpr int SLOTJ = (CNT / CG) * SU;
+
+  f32x4 acc[MT][NT16];
+#pragma unroll
+  for (int q = 0; q < MT; ++q)
+#pragma unroll
+    for (int t = 0; t < NT16; ++t) acc[q][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  // this lane's A fragment of tap (0, 0, 0), row tile 0
+  const char* abase = reinterpret_cast<const char*>(brick) + ((wave * B::NY) * B::NX + r) * SU * 16;
+  const uint16_t* wrow[NT16];
+  bool cok[NT16];
+#pragma unroll
+  for (int t = 0; t < NT16; ++t) {
+    const int co = nco0 + t * 16 + r;
+    cok[t] = co < cg.cout;
+    wrow[t] = w + static_cast<long long>(cok[t] ? co : 0) * cg.kpad;
+  }
+
+  // staging loads of one chunk into registers (units past the brick and
+  // outside the volume give zeros)
+  const bool lastu = NU * CNT > NUNIT && threadIdx.x + (NU - 1) * CNT >= NUNIT;
+  uint4 pre[NU];
+  auto load_chunk = [&](int cb) {
+    const int ch = (cb + sg) * 8;
+    const bool from0 = ch < cg.c0;
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      const uint16_t* src = from0 ? sx0 + static_cast<long long>(half ? uvh[j] : uvf[j]) * cg.c0 + ch
+                                  : sx1 + static_cast<long long>(uvf[j]) * cg.c1 + ch;
+      pre[j] = make_uint4(0u, 0u, 0u, 0u);
+      if (((ubits >> j) & 1u) && (!from0 || ((ubits >> (16 + j)) & 1u)))
+        pre[j] = *reinterpret_cast<const uint4*>(src);
+    }
+  };
+  load_chunk(0);
+  for (int cb = 0; cb < cvec; cb += CG) {
+    // stage channel groups cb .. cb + CG - 1 of the input brick, then load
+    // the next chunk's while this one is multiplied
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      if (j == NU - 1 && lastu) break;
+      brick[slot0 + j * SLOTJ] = pre[j];
+    }
+    __syncthreads();
+    if (cb + CG < cvec) load_chunk(cb + CG);
+#pragma unroll 2
+    for (int st = 0; st < NSTEP; ++st) {
+      const int2 kt = ktab[4 * st + kg];
+      bf16x8 bfrag[NT16];
+#pragma unroll
+      for (int t = 0; t < NT16; ++t) {
+        uint4 braw = make_uint4(0u, 0u, 0u, 0u);
+        if (cok[t] && kt.y >= 0) braw = *reinterpret_cast<const uint4*>(wrow[t] + cb * 8 + kt.y);
+        bfrag[t] = __builtin_bit_cast(bf16x8, braw);
+      }
+      const char* ap = abase + kt.x;
+#pragma unroll
+      for (int q2 = 0; q2 < MT; ++q2) {
+        // row tile q2 is B::NX voxels further: an immediate offset
+        const uint4 araw = *reinterpret_cast<const uint4*>(ap + q2 * B::NX * SU * 16);
+        const bf16x8 afrag = __builtin_bit_cast(bf16x8, araw);
+#pragma unroll
+        for (int t = 0; t < NT16; ++t)
+          acc[q2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[t], acc[q2][t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // epilogue: lane holds d2 offsets 4 kg .. 4 kg + 3 of channel column r
+  const int z = oz + wave;
+#pragma unroll
+  for (int t = 0; t < NT16; ++t) {
+    const int co = nco0 + t * 16 + r;
+    if (co >= cg.cout) continue;
+    const float bb = bias ? bias[co] : 0.0f;
+#pragma unroll
+    for (int q2 = 0; q2 < MT; ++q2) {
+      const int y = oy + q2;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int x = ox + 4 * kg + i;
+        if (z >= cg.o0 || y >= cg.o1 || x >= cg.o2) continue;
+        const long long vo = (static_cast<long long>(z) * cg.o1 + y) * cg.o2 + x;
+        const long long mo = s * per + vo;
+        float val = acc[q2][t][i] + bb;
+        if (cg.act) val = val > 0.0f ? val : cg.slope * val;
+        if (y16) {
+          y16[mo * cg.cout + co] = to_bf16(val);
+        } else if (cg.ycl32) {
+          float* d = y32 + mo * cg.cout + co;
+          *d = cg.accum ? *d + val : val;
+        } else {
+          y32[(s * cg.cout + co) * per + vo] = val;
+        }
+      }
+    }
+  }
+}
+
 // x [n][V][cpad] BF16 = (A, I_i, 0, ...): the network's input pair.
 __global__ __launch_bounds__(kBlock) void k_pack_pair(const float* __restrict__ atlas,
                                                       const float* __restrict__ images,
@@ -552,6 +750,36 @@ void conv3d_x0(int mode, dim3 grid, const uint16_t* x0, const uint16_t* x1, cons
 }
 }  // namespace
 
+namespace {
+constexpr int kLdsMT = 4;
+
+template <int NT16, int CG>
+void conv3d_lds_x0(int mode, dim3 grid, const uint16_t* x0, const uint16_t* x1, const uint16_t* w,
+                   const float* bias, uint16_t* y16, float* y32, const ConvGeom& cg, int nbz,
+                   int nby, int nbx, hipStream_t st) {
+  if (mode == 0)
+    hipLaunchKernelGGL((k_conv3d_lds<NT16, kLdsMT, 0, CG>), grid, dim3(CNT), 0, st, x0, x1, w,
+                       bias, y16, y32, cg, nbz, nby, nbx);
+  else if (mode == 1)
+    hipLaunchKernelGGL((k_conv3d_lds<NT16, kLdsMT, 1, CG>), grid, dim3(CNT), 0, st, x0, x1, w,
+                       bias, y16, y32, cg, nbz, nby, nbx);
+  else
+    hipLaunchKernelGGL((k_conv3d_lds<NT16, kLdsMT, 2, CG>), grid, dim3(CNT), 0, st, x0, x1, w,
+                       bias, y16, y32, cg, nbz, nby, nbx);
+}
+
+template <int NT16>
+void conv3d_lds_cg(int mode, dim3 grid, const uint16_t* x0, const uint16_t* x1, const uint16_t* w,
+                   const float* bias, uint16_t* y16, float* y32, const ConvGeom& cg, int nbz,
+                   int nby, int nbx, hipStream_t st) {
+  // two channel groups per chunk when they pair up exactly
+  if (((cg.c0 + cg.c1) / 8) % 2)
+    conv3d_lds_x0<NT16, 1>(mode, grid, x0, x1, w, bias, y16, y32, cg, nbz, nby, nbx, st);
+  else
+    conv3d_lds_x0<NT16, 2>(mode, grid, x0, x1, w, bias, y16, y32, cg, nbz, nby, nbx, st);
+}
+}  // namespace
+
 void launch_conv3d(const uint16_t* x0, const uint16_t* x1, const uint16_t* w, const float* bias,
                    uint16_t* y16, float* y32, const ConvGeom& cg, hipStream_t st) {
   // row tiles per wave (MT) share each K step's weight fragments
@@ -561,7 +789,20 @@ void launch_conv3d(const uint16_t* x0, const uint16_t* x1, const uint16_t* w, co
   };
   prof_begin(st, KC_MISC);
   const int mode = cg.dil0 ? 2 : (cg.up0 ? 1 : 0);
-  if (cg.cout <= 16) {
+  if (cg.stride == 1 && cg.ntaps == 27) {
+    // input bricks staged in LDS
+    const int nbz = (cg.o0 + LBZ - 1) / LBZ, nby = (cg.o1 + kLdsMT - 1) / kLdsMT;
+    const int nbx = (cg.o2 + LBX - 1) / LBX;
+    const long long per = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
+    const uint32_t gx = static_cast<uint32_t>(static_cast<long long>(nbz) * nby * nbx * (cg.nvox / per));
+    if (cg.cout <= 16)
+      conv3d_lds_cg<1>(mode, dim3(gx, 1), x0, x1, w, bias, y16, y32, cg, nbz, nby, nbx, st);
+    else if (cg.cout <= 32)
+      conv3d_lds_cg<2>(mode, dim3(gx, 1), x0, x1, w, bias, y16, y32, cg, nbz, nby, nbx, st);
+    else
+      conv3d_lds_cg<4>(mode, dim3(gx, static_cast<uint32_t>((cg.cout + 63) / 64)), x0, x1, w,
+                       bias, y16, y32, cg, nbz, nby, nbx, st);
+  } else if (cg.cout <= 16) {
     conv3d_x0<1, 4>(mode, dim3(gx(4), 1), x0, x1, w, bias, y16, y32, cg, st);
   } else if (cg.cout <= 32) {
     conv3d_x0<2, 2>(mode, dim3(gx(2), 1), x0, x1, w, bias, y16, y32, cg, st);

@@ -453,8 +453,9 @@ def main():
 
         log(f"time-to-loss trial on {TTL_WORKLOAD}")
         t0 = time.perf_counter()
-        ttl = WS.time_to_loss(WORKLOADS[TTL_WORKLOAD], range(2000, 2064), range(3000, 3008), dev,
-                              workers=workers)
+        # 500 training cohorts of 4: 2000 (atlas, subject) pairs
+        ttl = WS.time_to_loss(WORKLOADS[TTL_WORKLOAD], range(2000, 2500), range(3000, 3008), dev,
+                              workers=workers, progress=log)
         log(f"time-to-loss trial took {time.perf_counter() - t0:.1f} s: plain "
             f"{ttl['plain_s']:.3f} s, warm {ttl.get('warm_s')} s "
             f"({ttl['warm_reached']}/{ttl['test_cohorts']} reached)")

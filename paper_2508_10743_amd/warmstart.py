@@ -45,21 +45,69 @@ def darc_run(images: torch.Tensor, params: D.SweepParams, sweeps: int,
 
 
 def make_triples(w: Workload, seeds, params: D.SweepParams, sweeps: int, device,
-                 workers: int = 1) -> List[Triple]:
+                 workers: int = 1, chunk: int = 50, progress=None) -> List[Triple]:
     """One triple per seed: the cohort, its A^0 and DARC's velocities after
     ``sweeps`` sweeps with ``params`` (phantoms generated in ``workers``
-    processes)."""
+    processes, ``chunk`` cohorts at a time; the triples stay on the device).
+    ``progress(msg)``, if given, is called after every chunk."""
+    seeds = list(seeds)
     out = []
-    for imgs in make_cohorts(w, seeds, workers=workers):
-        imgs = torch.from_numpy(imgs).to(device)
-        coh, _ = darc_run(imgs, params, sweeps)
-        out.append(Triple(D.atlas_update(imgs, None), imgs, coh.v.clone()))
+    t0 = time.perf_counter()
+    for c0 in range(0, len(seeds), chunk):
+        for imgs in make_cohorts(w, seeds[c0:c0 + chunk], workers=workers):
+            imgs = torch.from_numpy(imgs).to(device)
+            coh, _ = darc_run(imgs, params, sweeps)
+            out.append(Triple(D.atlas_update(imgs, None), imgs, coh.v.clone()))
+        if progress is not None:
+            torch.cuda.synchronize()
+            progress(f"triples: {len(out)}/{len(seeds)} cohorts in {time.perf_counter() - t0:.1f} s")
     torch.cuda.synchronize()
     return out
 
 
+def unet_flop(n: int, dims) -> float:
+    """Multiply-adds x 2 of one forward pass on n subjects (unpadded channels)."""
+    V = float(np.prod(dims))
+    levels = (0, 1, 2, 3, 2, 1, 0, 0)  # resolution level of each layer's output
+    return sum(2.0 * 27 * cin * cout * n * V / 8 ** lev
+               for lev, (cin, cout, _, _) in zip(levels, N.LAYERS))
+
+
+BF16_PEAK = 2.5e15  # dense BF16 matrix-core FLOP/s of the MI355X
+
+
+def unet_rates(net: N.UNet, triple: Triple, reps: int = 5) -> dict:
+    """Milliseconds and matrix-core rate of the network's forward pass and of
+    one training step (forward, input and weight gradients: three times the
+    forward's products) on one training cohort, timed with GPU events.  The
+    training step runs on a copy of the network's parameters."""
+    tr = N.Trainer(N.UNet(seed=12345, device=net.device))
+
+    def timed(fn):
+        fn()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(reps):
+            fn()
+        b.record()
+        b.synchronize()
+        return a.elapsed_time(b) / reps
+
+    n = triple.images.shape[0]
+    flop = unet_flop(n, tuple(triple.images.shape[1:]))
+    fwd = timed(lambda: net(triple.atlas0, triple.images))
+    step = timed(lambda: tr.step(triple.atlas0, triple.images, triple.v))
+    return {"subjects": n, "dims": list(triple.images.shape[1:]),
+            "forward_ms": round(fwd, 3), "forward_GFLOP": round(flop / 1e9, 1),
+            "forward_TFLOPs": round(flop / fwd / 1e9, 1),
+            "forward_frac_bf16_peak": round(flop / (fwd * 1e-3) / BF16_PEAK, 4),
+            "train_step_ms": round(step, 3),
+            "train_step_TFLOPs": round(3 * flop / step / 1e9, 1),
+            "train_step_frac_bf16_peak": round(3 * flop / (step * 1e-3) / BF16_PEAK, 4)}
+
+
 def train(triples: List[Triple], epochs: int, lr: float = 1e-3, seed: int = 0,
-          net: N.UNet = None) -> Tuple[N.UNet, List[float]]:
+          net: N.UNet = None, progress=None) -> Tuple[N.UNet, List[float]]:
     """Adam on the mean squared velocity error, one cohort per step, cohorts
     in a seeded random order every epoch; returns the net and the per-epoch
     mean loss."""
@@ -71,6 +119,8 @@ def train(triples: List[Triple], epochs: int, lr: float = 1e-3, seed: int = 0,
         losses = [tr.step(t.atlas0, t.images, t.v) for t in
                   (triples[i] for i in rng.permutation(len(triples)))]
         hist.append(float(torch.stack(losses).mean().item()))
+        if progress is not None:
+            progress(f"training: epoch {len(hist)}/{epochs}, mean loss {hist[-1]:.3e}")
     return net, hist
 
 
@@ -141,7 +191,7 @@ def evaluate(net: N.UNet, cohorts: List[torch.Tensor], params: D.SweepParams, sw
 
 def time_to_loss(w: Workload, train_seeds, test_seeds, device, target_sweeps: int = 10,
                  target_k2: int = 10, epochs: int = 10, lr: float = 1e-3,
-                 workers: int = 1) -> dict:
+                 workers: int = 1, progress=None) -> dict:
     """The whole comparison on cohorts of workload ``w``: training triples from
     plain DARC (``target_sweeps`` sweeps of ``target_k2`` steps), the U-Net
     trained on them, then :func:`evaluate` on held-out cohorts with the
@@ -152,11 +202,12 @@ def time_to_loss(w: Workload, train_seeds, test_seeds, device, target_sweeps: in
                            beta1=w.beta1, beta2=w.beta2, adam_eps=w.adam_eps)
     t0 = time.perf_counter()
     triples = make_triples(w, train_seeds, dataclasses.replace(params, k2=target_k2),
-                           target_sweeps, device, workers=workers)
+                           target_sweeps, device, workers=workers, progress=progress)
     t1 = time.perf_counter()
-    net, hist = train(triples, epochs=epochs, lr=lr)
+    net, hist = train(triples, epochs=epochs, lr=lr, progress=progress)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    rates = unet_rates(net, triples[0])
     del triples
     test = [torch.from_numpy(c).to(device) for c in make_cohorts(w, test_seeds, workers=workers)]
     res = evaluate(net, test, params, w.k1)
@@ -172,6 +223,7 @@ def time_to_loss(w: Workload, train_seeds, test_seeds, device, target_sweeps: in
                   "target_run": f"{target_sweeps} sweeps x {target_k2} steps",
                   "epochs": epochs, "triples_s": round(t1 - t0, 2), "train_s": round(t2 - t1, 2),
                   "loss_first_last": [round(hist[0], 6), round(hist[-1], 6)]},
+        "unet": rates,
         "test_cohorts": len(rows),
         "warm_reached": len(reached),
         "plain_s": float(np.mean([r["plain_s"] for r in rows])),

@@ -72,14 +72,22 @@ def algorithmic_bytes(w, batch):
     return b
 
 
-def source_digest():
-    """SHA-256 over the HIP sources, to tell whether counters taken earlier
-    still describe the kernels that run now."""
+# sources that define each timed kernel class's kernels and their launches
+# (the shared headers and the entry points included)
+CLASS_SOURCES = {
+    "exp_bwd_step": ("api.hip", "exp_kernels.hip", "darc_common.hpp", "darc_kernels.hpp",
+                     "voxel_bodies.hpp"),
+}
+
+
+def source_digest(kernel_class="exp_bwd_step"):
+    """SHA-256 over the HIP sources of a kernel class, to tell whether
+    counters taken earlier still describe the kernels that run now."""
     import hashlib
 
     h = hashlib.sha256()
     src = os.path.join(ROOT, "paper_2508_10743_amd", "csrc")
-    for name in sorted(os.listdir(src)):
+    for name in sorted(CLASS_SOURCES[kernel_class]):
         with open(os.path.join(src, name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
@@ -99,7 +107,8 @@ def measured_traffic(workload, kernel_class):
             if line.startswith("- ") and ": " in line:
                 k, v = line[2:].split(": ", 1)
                 fields[k.strip("` ")] = v.strip().strip("`")
-    if fields.get("source_sha256") != source_digest() or fields.get("class") != kernel_class:
+    if (kernel_class not in CLASS_SOURCES or fields.get("class") != kernel_class
+            or fields.get("source_sha256") != source_digest(kernel_class)):
         return None
     try:
         return float(fields["hbm_GB_per_launch"])
@@ -380,6 +389,9 @@ def main():
                     help="also time the method's other branches (median and stochastic atlas, "
                          "one-shot segmentation, pyramid resampling, the network) on the same "
                          "cohort")
+    ap.add_argument("--unet-rates", action="store_true",
+                    help="only time the warm-start network (forward and one training step) "
+                         "on one cohort of the time-to-loss workload, print its rates, exit")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB copy stream (k_bw_copy) first: a kernel of known "
                          "traffic for calibrating HBM byte counters")
@@ -410,6 +422,18 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda", 0)
     D.lib()
+    if args.unet_rates:
+        from paper_2508_10743_amd import unet as N
+        from paper_2508_10743_amd import warmstart as WS
+        from synthetic.cohorts import make_cohort, random_velocity
+
+        wt = WORKLOADS[TTL_WORKLOAD]
+        imgs = torch.from_numpy(make_cohort(wt)).to(dev)
+        v = torch.from_numpy(random_velocity(7, wt.n, wt.dims, 2.0)).to(dev)
+        t = WS.Triple(D.atlas_update(imgs, None), imgs, v)
+        rates = WS.unet_rates(N.UNet(seed=0, device=dev), t)
+        print(json.dumps({"workload": wt.name, "unet": rates}), flush=True)
+        return
     attainable = None
     if not args.no_attainable:
         attainable = attainable_bandwidth(dev)

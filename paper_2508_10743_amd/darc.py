@@ -477,12 +477,14 @@ class Cohort:
         return self.losses[:1]
 
     def autotune(self) -> tuple:
-        """Time the candidate plane-chunk lengths of the marching kernels on
-        this cohort's shapes, and (MSE / L1 without smoothing) one fused
-        inner iteration against separate launches, and keep the fastest for
-        later launches; returns (squaring chunk, window-kernel chunk, fused
-        choice: 1 fused, 2 separate, 0 not tuned).  Only workspace memory is
-        written; the cohort state is left as it is."""
+        """Time the candidate launch shapes on this cohort's shapes -- the
+        squaring steps' marching depth (8 to 64 planes) or plane-parallel
+        shape, the window kernels' chunk length and (MSE / L1 without
+        smoothing) one fused inner iteration against separate launches --
+        and keep the fastest for later launches; returns (squaring shape:
+        planes per chunk or -1 for plane-parallel, window-kernel chunk,
+        fused choice: 1 fused, 2 separate, 0 not tuned).  Only workspace
+        memory is written; the cohort state is left as it is."""
         self._refresh_state()
         chosen = (ctypes.c_int * 3)()
         _call("darc_autotune", ctypes.byref(self._state), ctypes.byref(self._cparams),

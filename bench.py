@@ -228,15 +228,31 @@ def attainable_bandwidth(dev, gib=4, reps=5):
     return out
 
 
-def cpu_baseline(w, max_crop=(40, 96, 112), n_sub=2):
+def _oracle_sweep_seconds(sub, p):
+    """Seconds of one single-threaded oracle sweep of the cropped subjects
+    `sub` (a process-pool task of the whole-host figure)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import darc_oracle as O
+
+    z = np.zeros((len(sub), 3) + sub.shape[1:])
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        O.sweep(sub, z, z, z, 0, O.initial_atlas(sub), p)
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(w, max_crop=(40, 96, 112), n_sub=2, host_procs=16):
     """The FP64 oracle on a bounded sample of workload `w`: one whole sweep
     (K2 inner iterations per subject, then Exp, centring, the atlas update
     and the group loss) of `n_sub` subjects cropped to at most `max_crop`
-    about the volume centre, on one thread, in subject-voxel-iterations/s."""
+    about the volume centre, on one thread, in subject-voxel-iterations/s;
+    `whole_host` runs the same sample in `host_procs` processes at once
+    (at most one per core)."""
     import platform
 
     import numpy as np
-    from threadpoolctl import threadpool_limits
 
     from oracle import darc_oracle as O
     from synthetic.cohorts import make_cohort
@@ -247,11 +263,15 @@ def cpu_baseline(w, max_crop=(40, 96, 112), n_sub=2):
     sub = np.stack([im[sl] for im in imgs]).astype(np.float64)
     p = O.SweepParams(metric=w.metric, win=w.win, ncc_eps=w.ncc_eps, lam=w.lam,
                       smooth_sigma=w.smooth_sigma, n_sq=w.n_sq, k2=w.k2)
-    z = np.zeros((n_sub, 3) + sub.shape[1:])
-    with threadpool_limits(limits=1):
+    dt = _oracle_sweep_seconds(sub, p)
+    # whole host: the same sample in one single-threaded process per core
+    # (subjects are independent within a sweep), timed by the wall clock
+    procs = max(1, min(host_procs, os.cpu_count() or 1))
+    from concurrent.futures import ProcessPoolExecutor
+    with ProcessPoolExecutor(max_workers=procs) as ex:
         t0 = time.perf_counter()
-        O.sweep(sub, z, z, z, 0, O.initial_atlas(sub), p)
-        dt = time.perf_counter() - t0
+        list(ex.map(_oracle_sweep_seconds, [sub] * procs, [p] * procs))
+        wall = time.perf_counter() - t0
     model = ""
     try:
         with open("/proc/cpuinfo") as f:
@@ -269,6 +289,10 @@ def cpu_baseline(w, max_crop=(40, 96, 112), n_sub=2):
                   f"iterations each (Exp, warp, dissimilarity, adjoint, Adam, smoothing), then "
                   f"Exp, centring, atlas and group loss; FP64 NumPy on one thread, {dt:.1f} s",
         "host": {"cpu_model": model or platform.processor(), "cpu_count": os.cpu_count()},
+        "whole_host": {"value": procs * n_sub * sub[0].size * w.k2 / wall, "processes": procs,
+                       "seconds": round(wall, 1),
+                       "sample": "the same sample in each of `processes` single-threaded "
+                                 "processes at once (the pool's start-up included)"},
     }
 
 

@@ -418,10 +418,12 @@ __device__ __forceinline__ float from_bf16(uint16_t h) {
 // read of dz, and of X at each column group's tap: a group of 8 consecutive
 // k is one tap and 8 channels), writes them as [channel][voxel], and then
 // reads its A row / B column at 8 consecutive voxels as one 16-byte read.
-constexpr int WCH = 1024;  // voxels per wave
-constexpr int WNK = 4;     // 16-column k tiles per wave
+// A wave reduces wch voxels (a multiple of 32) before its atomics into the
+// gradient: longer chunks mean fewer atomics on the same gradient entries,
+// shorter ones more waves for small layers (chosen at launch).
+constexpr int WNK = 4;  // 16-column k tiles per wave
 template <int X0>
-__global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ dz, int cz,
+__global__ __launch_bounds__(64) void k_conv_wgrad(int wch, const uint16_t* __restrict__ dz, int cz,
                                                    const uint16_t* __restrict__ x0,
                                                    const uint16_t* __restrict__ x1, ConvGeom cg,
                                                    float* __restrict__ dw,
@@ -458,7 +460,7 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
     gto[t] = (gta[t] * cg.i1 + gtb[t]) * cg.i2 + gtc[t];
   }
   // coordinates of the staged voxel, advanced by 32 voxels per K step
-  const long long vstart = static_cast<long long>(blockIdx.x) * WCH + vl;
+  const long long vstart = static_cast<long long>(blockIdx.x) * wch + vl;
   const long long ov = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
   int s = 0, o0 = 0, o1 = 0, o2 = 0;
   if (vstart < cg.nvox) {
@@ -475,8 +477,8 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(const uint16_t* __restrict__ 
   // the bias gradient sum_v dz[v][co], from the staged dz of the first k tile
   const bool bias = db != nullptr && blockIdx.y == 0;
   float bacc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  for (int step = 0; step < WCH; step += 32) {
-    const long long vb = static_cast<long long>(blockIdx.x) * WCH + step;
+  for (int step = 0; step < wch; step += 32) {
+    const long long vb = static_cast<long long>(blockIdx.x) * wch + step;
     if (vb >= cg.nvox) break;  // uniform across the wave
     const long long v = vb + vl;
     const bool live = v < cg.nvox;
@@ -684,15 +686,21 @@ uint32_t grid_1d(long long count) { return static_cast<uint32_t>((count + kBlock
 void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uint16_t* x1,
                        const ConvGeom& cg, float* dw, float* db, hipStream_t st) {
   prof_begin(st, KC_MISC);
-  const dim3 grid(static_cast<uint32_t>((cg.nvox + WCH - 1) / WCH),
-                  static_cast<uint32_t>((cg.kpad + 16 * WNK - 1) / (16 * WNK)),
-                  static_cast<uint32_t>((cg.cout + 15) / 16));
+  const uint32_t gy = static_cast<uint32_t>((cg.kpad + 16 * WNK - 1) / (16 * WNK));
+  const uint32_t gz = static_cast<uint32_t>((cg.cout + 15) / 16);
+  // voxels per wave: doubled from 1024 up to 4096 while at least 2048
+  // waves (two per SIMD) remain (measured on the warm-start network at
+  // 96 x 112 x 96: longer chunks starve the low-resolution layers)
+  long long wch = 1024;
+  while (wch < 4096 && (cg.nvox + 2 * wch - 1) / (2 * wch) * gy * gz >= 2048) wch *= 2;
+  const dim3 grid(static_cast<uint32_t>((cg.nvox + wch - 1) / wch), gy, gz);
+  const int w = static_cast<int>(wch);
   if (cg.dil0)
-    hipLaunchKernelGGL((k_conv_wgrad<2>), grid, dim3(64), 0, st, dz, cz, x0, x1, cg, dw, db);
+    hipLaunchKernelGGL((k_conv_wgrad<2>), grid, dim3(64), 0, st, w, dz, cz, x0, x1, cg, dw, db);
   else if (cg.up0)
-    hipLaunchKernelGGL((k_conv_wgrad<1>), grid, dim3(64), 0, st, dz, cz, x0, x1, cg, dw, db);
+    hipLaunchKernelGGL((k_conv_wgrad<1>), grid, dim3(64), 0, st, w, dz, cz, x0, x1, cg, dw, db);
   else
-    hipLaunchKernelGGL((k_conv_wgrad<0>), grid, dim3(64), 0, st, dz, cz, x0, x1, cg, dw, db);
+    hipLaunchKernelGGL((k_conv_wgrad<0>), grid, dim3(64), 0, st, w, dz, cz, x0, x1, cg, dw, db);
   prof_end(st, KC_MISC);
 }
 

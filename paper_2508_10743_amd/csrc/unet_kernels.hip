@@ -19,6 +19,8 @@
 // 8 (l / 16) .. + 7 (loaded once and used by every row tile), and holds
 // output rows 4 (l / 16) .. + 3 of column l % 16.  FP32 accumulation;
 // bias, leaky ReLU and the BF16 rounding (to nearest even) in the epilogue.
+#include <type_traits>
+
 #include "darc_kernels.hpp"
 
 namespace darc {
@@ -376,6 +378,174 @@ __global__ __launch_bounds__(CNT) void k_conv3d_lds(const uint16_t* __restrict__
         const long long vo = (static_cast<long long>(z) * cg.o1 + y) * cg.o2 + x;
         const long long mo = s * per + vo;
         float val = acc[q2][t][i] + bb;
+        if (cg.act) val = val > 0.0f ? val : cg.slope * val;
+        if (y16) {
+          y16[mo * cg.cout + co] = to_bf16(val);
+        } else if (cg.ycl32) {
+          float* d = y32 + mo * cg.cout + co;
+          *d = cg.accum ? *d + val : val;
+        } else {
+          y32[(s * cg.cout + co) * per + vo] = val;
+        }
+      }
+    }
+  }
+}
+
+// Input gradients of the stride-2 layers: a stride-1 convolution over dz
+// placed on the even positions of the full grid, zeros between.  Split by
+// the parity of the output voxel p = 2q + par: along an axis with par 0 only
+// the centre tap meets an even position (dz at q), with par 1 the two outer
+// taps (dz at q and q + 1).  A block owns one parity class and a brick of
+// 4 x MT x 16 half-resolution positions q; it stages the 5 x (MT + 1) x 17
+// voxels of dz those outputs read (no zeros) and reduces over the class's
+// 1 to 8 valid taps only, an eighth of the products on average.
+template <int NT16, int MT, int CG>
+__global__ __launch_bounds__(CNT) void k_conv3d_sub(const uint16_t* __restrict__ dz,
+                                                    const uint16_t* __restrict__ w,
+                                                    uint16_t* __restrict__ y16,
+                                                    float* __restrict__ y32, ConvGeom cg,
+                                                    int nbz, int nby, int nbx) {
+  constexpr int NY = MT + 1, NX = LBX + 1;
+  constexpr int NVOX = (LBZ + 1) * NY * NX;
+  constexpr int SU = CG % 2 ? CG : CG + 1;  // voxel stride in 16-byte units (odd)
+  constexpr int MAXQ = 8 * CG;             // pairs of the largest class
+  constexpr int NUNIT = NVOX * CG;
+  constexpr int NU = (NUNIT + CNT - 1) / CNT;
+  static_assert(CNT % CG == 0, "a thread's staging units share one channel group");
+  __shared__ uint4 brick[NVOX * SU];
+  __shared__ int2 ktab[MAXQ + 3];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int r = lane & 15, kg = lane >> 4;
+  const int h0 = cg.i0 / 2, h1 = cg.i1 / 2, h2 = cg.i2 / 2;  // dz grid (even dims)
+  const long long hv = static_cast<long long>(h0) * h1 * h2;
+  const long long per = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
+  const long long nsub = cg.nvox / per;
+  const uint32_t nblk = static_cast<uint32_t>(8LL * nbz * nby * nbx * nsub);
+  // the eight parity classes of a brick are neighbouring blocks (one XCD)
+  uint32_t b = xcd_remap(blockIdx.x, nblk);
+  const int par = static_cast<int>(b % 8);
+  b /= 8;
+  const int bx = static_cast<int>(b % nbx);
+  b /= nbx;
+  const int by = static_cast<int>(b % nby);
+  b /= nby;
+  const int bz = static_cast<int>(b % nbz);
+  const int s = static_cast<int>(b / nbz);
+  const int pz = par >> 2, py = (par >> 1) & 1, px = par & 1;
+  const int oz = bz * LBZ, oy = by * MT, ox = bx * LBX;  // half-resolution origin
+  const uint16_t* sdz = dz + s * hv * cg.c0;
+  const int cvec = cg.c0 >> 3;
+  const int nco0 = blockIdx.y * 16 * NT16;
+  // valid taps of this class: per axis 1 (par 0: tap 1, dz at q) or 2
+  // (par 1: taps 0 and 2, dz at q and q + 1)
+  const int n0 = 1 + pz, n1 = 1 + py, n2 = 1 + px;
+  const int ntap = n0 * n1 * n2;
+  const int npair = ntap * CG, nstep = (npair + 3) / 4;
+  if (threadIdx.x < 4 * nstep) {
+    const int q = threadIdx.x;
+    int2 e = make_int2(0, -1);  // past the class's pairs: weight 0
+    if (q < npair) {
+      const int t = q / CG, g = q - t * CG;
+      const int t2 = t % n2, t1 = (t / n2) % n1, t0 = t / (n2 * n1);
+      // tap index per axis and its dz offset
+      const int a = pz ? 2 * t0 : 1, bb = py ? 2 * t1 : 1, c = px ? 2 * t2 : 1;
+      const int s0 = pz ? t0 : 0, s1 = py ? t1 : 0, s2 = px ? t2 : 0;
+      e = make_int2((((s0 * NY + s1) * NX + s2) * SU + g) * 16, (((a * 3 + bb) * 3 + c) * cvec + g) * 8);
+    }
+    ktab[q] = e;
+  }
+  // staging units: dz voxel (half resolution) and whether it exists
+  const int sg = threadIdx.x % CG;
+  int uv[NU];
+  unsigned ubits = 0u;
+#pragma unroll
+  for (int j = 0; j < NU; ++j) {
+    const int i = threadIdx.x + j * CNT;
+    const int vb = (i < NUNIT ? i : 0) / CG;
+    const int ex = vb % NX, rest = vb / NX;
+    const int ey = rest % NY, ez = rest / NY;
+    const int q0 = oz + ez, q1 = oy + ey, q2 = ox + ex;
+    const bool in = i < NUNIT && q0 < h0 && q1 < h1 && q2 < h2;
+    uv[j] = in ? (q0 * h1 + q1) * h2 + q2 : 0;
+    ubits |= (in ? 1u : 0u) << j;
+  }
+  const int slot0 = (threadIdx.x / CG) * SU + sg;
+  constexpr int SLOTJ = (CNT / CG) * SU;
+  const bool lastu = NU * CNT > NUNIT && threadIdx.x + (NU - 1) * CNT >= NUNIT;
+
+  f32x4 acc[MT][NT16];
+#pragma unroll
+  for (int q = 0; q < MT; ++q)
+#pragma unroll
+    for (int t = 0; t < NT16; ++t) acc[q][t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  const char* abase = reinterpret_cast<const char*>(brick) + ((wave * NY) * NX + r) * SU * 16;
+  const uint16_t* wrow[NT16];
+  bool cok[NT16];
+#pragma unroll
+  for (int t = 0; t < NT16; ++t) {
+    const int co = nco0 + t * 16 + r;
+    cok[t] = co < cg.cout;
+    wrow[t] = w + static_cast<long long>(cok[t] ? co : 0) * cg.kpad;
+  }
+  uint4 pre[NU];
+  auto load_chunk = [&](int cb) {
+    const int ch = (cb + sg) * 8;
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      pre[j] = make_uint4(0u, 0u, 0u, 0u);
+      if ((ubits >> j) & 1u)
+        pre[j] = *reinterpret_cast<const uint4*>(sdz + static_cast<long long>(uv[j]) * cg.c0 + ch);
+    }
+  };
+  load_chunk(0);
+  for (int cb = 0; cb < cvec; cb += CG) {
+#pragma unroll
+    for (int j = 0; j < NU; ++j) {
+      if (j == NU - 1 && lastu) break;
+      brick[slot0 + j * SLOTJ] = pre[j];
+    }
+    __syncthreads();
+    if (cb + CG < cvec) load_chunk(cb + CG);
+    for (int st = 0; st < nstep; ++st) {
+      const int2 kt = ktab[4 * st + kg];
+      bf16x8 bfrag[NT16];
+#pragma unroll
+      for (int t = 0; t < NT16; ++t) {
+        uint4 braw = make_uint4(0u, 0u, 0u, 0u);
+        if (cok[t] && kt.y >= 0) braw = *reinterpret_cast<const uint4*>(wrow[t] + cb * 8 + kt.y);
+        bfrag[t] = __builtin_bit_cast(bf16x8, braw);
+      }
+      const char* ap = abase + kt.x;
+#pragma unroll
+      for (int q2 = 0; q2 < MT; ++q2) {
+        const uint4 araw = *reinterpret_cast<const uint4*>(ap + q2 * NX * SU * 16);
+        const bf16x8 afrag = __builtin_bit_cast(bf16x8, araw);
+#pragma unroll
+        for (int t = 0; t < NT16; ++t)
+          acc[q2][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag[t], acc[q2][t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+  // epilogue: lane holds half-resolution d2 offsets 4 kg .. 4 kg + 3 of
+  // channel column r; output voxel p = 2 q + par
+  const int qz = oz + wave;
+#pragma unroll
+  for (int t = 0; t < NT16; ++t) {
+    const int co = nco0 + t * 16 + r;
+    if (co >= cg.cout) continue;
+#pragma unroll
+    for (int q2 = 0; q2 < MT; ++q2) {
+      const int qy = oy + q2;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int qx = ox + 4 * kg + i;
+        if (qz >= h0 || qy >= h1 || qx >= h2) continue;
+        const long long vo =
+            (static_cast<long long>(2 * qz + pz) * cg.o1 + 2 * qy + py) * cg.o2 + 2 * qx + px;
+        const long long mo = s * per + vo;
+        float val = acc[q2][t][i];
         if (cg.act) val = val > 0.0f ? val : cg.slope * val;
         if (y16) {
           y16[mo * cg.cout + co] = to_bf16(val);
@@ -797,7 +967,31 @@ void launch_conv3d(const uint16_t* x0, const uint16_t* x1, const uint16_t* w, co
   };
   prof_begin(st, KC_MISC);
   const int mode = cg.dil0 ? 2 : (cg.up0 ? 1 : 0);
-  if (cg.stride == 1 && cg.ntaps == 27) {
+  if (cg.stride == 1 && cg.ntaps == 27 && cg.dil0 && cg.c1 == 0 && !bias) {
+    // zero-dilated input (input gradients of stride-2 layers): one launch
+    // over the eight parity classes, valid taps only
+    const int nbz = (cg.o0 / 2 + LBZ - 1) / LBZ, nby = (cg.o1 / 2 + kLdsMT - 1) / kLdsMT;
+    const int nbx = (cg.o2 / 2 + LBX - 1) / LBX;
+    const long long per = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
+    const uint32_t gx =
+        static_cast<uint32_t>(8LL * nbz * nby * nbx * (cg.nvox / per));
+    const bool cg2 = (cg.c0 / 8) % 2 == 0;
+    auto go = [&](auto nt, uint32_t gy) {
+      constexpr int NT = decltype(nt)::value;
+      if (cg2)
+        hipLaunchKernelGGL((k_conv3d_sub<NT, kLdsMT, 2>), dim3(gx, gy), dim3(CNT), 0, st, x0, w,
+                           y16, y32, cg, nbz, nby, nbx);
+      else
+        hipLaunchKernelGGL((k_conv3d_sub<NT, kLdsMT, 1>), dim3(gx, gy), dim3(CNT), 0, st, x0, w,
+                           y16, y32, cg, nbz, nby, nbx);
+    };
+    if (cg.cout <= 16)
+      go(std::integral_constant<int, 1>{}, 1);
+    else if (cg.cout <= 32)
+      go(std::integral_constant<int, 2>{}, 1);
+    else
+      go(std::integral_constant<int, 4>{}, static_cast<uint32_t>((cg.cout + 63) / 64));
+  } else if (cg.stride == 1 && cg.ntaps == 27) {
     // input bricks staged in LDS
     const int nbz = (cg.o0 + LBZ - 1) / LBZ, nby = (cg.o1 + kLdsMT - 1) / kLdsMT;
     const int nbx = (cg.o2 + LBX - 1) / LBX;

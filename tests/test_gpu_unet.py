@@ -142,14 +142,19 @@ def test_warm_start_feeds_a_sweep(dev):
     assert np.isfinite(losses).all()
 
 
-@pytest.mark.parametrize("cin,cout,stride,up", [(16, 32, 1, False), (32, 64, 2, False),
-                                                (64, 128, 2, False), (96, 32, 1, True),
-                                                (16, 3, 1, False)])
-def test_conv3d_gradients(dev, cin, cout, stride, up):
+@pytest.mark.parametrize("cin,cout,stride,up,dims", [
+    (16, 32, 1, False, (6, 8, 10)), (32, 64, 2, False, (6, 8, 10)),
+    (64, 128, 2, False, (6, 8, 10)), (96, 32, 1, True, (6, 8, 10)),
+    (16, 3, 1, False, (6, 8, 10)),
+    # stride 2 over several half-resolution bricks (4 x 4 x 16) on every
+    # axis with ragged edges: 96 input channels (two column blocks of the
+    # input gradient) and 24 output channels (an odd number of channel groups)
+    (96, 32, 2, False, (18, 12, 36)), (16, 24, 2, False, (10, 14, 34))])
+def test_conv3d_gradients(dev, cin, cout, stride, up, dims):
     """One layer's weight, bias and input gradients from identical BF16
-    inputs: FP32 accumulation against exact sums."""
+    inputs: FP32 accumulation against exact sums.  Stride-2 input gradients
+    run per parity class of the output voxel over the valid taps only."""
     rng = np.random.default_rng(540 + cin + cout)
-    dims = (6, 8, 10)
     o = tuple((d - 1) // stride + 1 for d in dims)
     cz = (cout + 7) // 8 * 8
     dz = np.zeros((2, cz) + o)

@@ -63,17 +63,26 @@ __device__ __forceinline__ TileId tile_id(const TileGeom& tg) {
   return id;
 }
 
-__device__ __forceinline__ int wave_min(int x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x = min(x, __shfl_xor(x, m, 64));
-  return x;
+// Minimum or maximum over the 64 lanes of a wave (every lane active), by DPP
+// lane moves that need no LDS: shifts by 1, 2, 4 and 8 lanes within each
+// 16-lane row (a lane with no source lane takes the identity) leave each
+// row's extreme in its lane 15; broadcasting lane 15 into the next row and
+// lane 31 into rows 2 and 3 folds the four rows into lane 63.
+template <bool MAX>
+__device__ __forceinline__ int wave_extreme(int x) {
+  constexpr int kRowShr = 0x110, kBcast15 = 0x142, kBcast31 = 0x143;
+  constexpr int id = MAX ? INT_MIN : INT_MAX;
+  auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+  x = op(x, __builtin_amdgcn_update_dpp(id, x, kRowShr + 1, 0xf, 0xf, false));
+  x = op(x, __builtin_amdgcn_update_dpp(id, x, kRowShr + 2, 0xf, 0xf, false));
+  x = op(x, __builtin_amdgcn_update_dpp(id, x, kRowShr + 4, 0xf, 0xf, false));
+  x = op(x, __builtin_amdgcn_update_dpp(id, x, kRowShr + 8, 0xf, 0xf, false));
+  x = op(x, __builtin_amdgcn_update_dpp(id, x, kBcast15, 0xa, 0xf, false));
+  x = op(x, __builtin_amdgcn_update_dpp(id, x, kBcast31, 0xc, 0xf, false));
+  return __builtin_amdgcn_readlane(x, 63);
 }
-
-__device__ __forceinline__ int wave_max(int x) {
-#pragma unroll
-  for (int m = 32; m >= 1; m >>= 1) x = max(x, __shfl_xor(x, m, 64));
-  return x;
-}
+__device__ __forceinline__ int wave_min(int x) { return wave_extreme<false>(x); }
+__device__ __forceinline__ int wave_max(int x) { return wave_extreme<true>(x); }
 
 // Per-tile records used by the adjoint: boxes[(s * ntiles + tile) * 8 + {0,1,2}]
 // = min over the tile's voxels x of i_d(x) - x_d along d0, d1, d2 (i = cell
@@ -84,7 +93,7 @@ __device__ __forceinline__ int wave_max(int x) {
 // scatter (zeroed before).  Tiles are 32 (d2) x 8 (d1) x 8 (d0).
 __device__ __forceinline__ void write_record(int mn0, int mn1, int mn2, int mx0, int mx1, int mx2,
                                              int (*red)[ENT / 64], int* __restrict__ boxes,
-                                             int s, int tile, int ntiles, int (&rmax)[6]) {
+                                             int s, int tile, int ntiles, int& rmax) {
   mn0 = wave_min(mn0);
   mn1 = wave_min(mn1);
   mn2 = wave_min(mn2);
@@ -101,33 +110,24 @@ __device__ __forceinline__ void write_record(int mn0, int mn1, int mn2, int mx0,
     red[5][w] = mx2;
   }
   __syncthreads();
-  // thread 0 writes the box and folds the reaches into its running maxima
-  // (flush_reach issues them once per block): nothing here waits for memory,
-  // and no barrier follows, since `red` is rewritten only after the caller's
-  // next barrier
-  if (threadIdx.x == 0) {
-    int r[6];
-    for (int k = 0; k < 6; ++k) r[k] = red[k][0];
-    for (int i = 1; i < ENT / 64; ++i) {
-      for (int k = 0; k < 3; ++k) r[k] = min(r[k], red[k][i]);
-      for (int k = 3; k < 6; ++k) r[k] = max(r[k], red[k][i]);
-    }
-    int* bx = boxes + (static_cast<size_t>(s) * ntiles + tile) * 8;
-    for (int d = 0; d < 3; ++d) {
-      bx[d] = r[d];
-      bx[3 + d] = r[3 + d];
-      rmax[d] = max(rmax[d], max(0, -r[d]));
-      rmax[3 + d] = max(rmax[3 + d], max(0, r[3 + d] + 1));
-    }
+  // thread q < 6 writes entry q of the box and folds its reach into a running
+  // maximum (flush_reach issues it once per block): nothing here waits for
+  // memory, and no barrier follows, since `red` is rewritten only after the
+  // caller's next barrier
+  if (threadIdx.x < 6) {
+    const int q = threadIdx.x;
+    int r = red[q][0];
+#pragma unroll
+    for (int i = 1; i < ENT / 64; ++i) r = q < 3 ? min(r, red[q][i]) : max(r, red[q][i]);
+    boxes[(static_cast<size_t>(s) * ntiles + tile) * 8 + q] = r;
+    rmax = max(rmax, q < 3 ? -r : r + 1);
   }
 }
 
-// The block's reaches into the subject's (atomics only where they can raise it).
-__device__ __forceinline__ void flush_reach(const int (&rmax)[6], int* __restrict__ reach, int s) {
-  if (threadIdx.x == 0) {
-    for (int k = 0; k < 6; ++k)
-      if (rmax[k] > 0) atomicMax(reach + s * 8 + k, rmax[k]);
-  }
+// The block's reaches into the subject's (atomics only where they can raise
+// it): thread q < 6 holds entry q.
+__device__ __forceinline__ void flush_reach(int rmax, int* __restrict__ reach, int s) {
+  if (threadIdx.x < 6 && rmax > 0) atomicMax(reach + s * 8 + threadIdx.x, rmax);
 }
 
 // Records only (for an adjoint whose forward pass did not record them).
@@ -162,7 +162,7 @@ __global__ __launch_bounds__(ENT) void k_exp_rec(const float* __restrict__ src, 
       mx2 = max(mx2, bc.i2 - x2);
     }
   }
-  int rmax[6] = {0, 0, 0, 0, 0, 0};
+  int rmax = 0;
   write_record(mn0, mn1, mn2, mx0, mx1, mx2, red, boxes, id.s, id.tile, tg.ntiles, rmax);
   flush_reach(rmax, reach, id.s);
 }
@@ -285,7 +285,7 @@ __global__ __launch_bounds__(ENT) void k_exp_fwd(const float* __restrict__ src,
   const bool colv = (x2 < g.d2) && (x1 < g.d1);
   const int own = (ly + 1) * MHX + lx + 1;
   int mn0 = INT_MAX, mn1 = INT_MAX, mn2 = INT_MAX, mx0 = INT_MIN, mx1 = INT_MIN, mx2 = INT_MIN;
-  int rmax[6] = {0, 0, 0, 0, 0, 0};
+  int rmax = 0;
   for (int z = id.z0; z < id.z1; ++z) {
     store_plane(z + 1);
     __syncthreads();

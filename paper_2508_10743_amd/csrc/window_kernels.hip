@@ -232,11 +232,12 @@ __global__ __launch_bounds__(kNT) void k_lncc_fwd(const float* __restrict__ wimg
           const double ivar = S[2] - S[0] * S[0] * kInvN;
           const double jvar = S[3] - S[1] * S[1] * kInvN;
           const double den = ivar * jvar + eps;
-          const double cc = cross * cross / den;
+          const double rden = 1.0 / den;  // one division for the three quotients
+          const double cc = cross * cross * rden;
           acc += cc;
           if (FIELDS) {
-            const double alpha = 2.0 * cross / den;
-            const double beta = 2.0 * cross * cross * jvar / (den * den);
+            const double alpha = 2.0 * cross * rden;
+            const double beta = alpha * cross * jvar * rden;
             fv[0] = static_cast<float>(alpha);
             fv[1] = static_cast<float>(alpha * S[1] * kInvN);
             fv[2] = static_cast<float>(beta);

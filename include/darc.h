@@ -85,7 +85,11 @@ extern "C" {
 #define DARC_SGD_INIT_INITIAL 1 /* from A^0 of main: the mean of the unwarped subjects */
 
 /* Inner iterations in one launch each (persistent, grid-synchronised; MSE
- * and L1 without smoothing of v) instead of ~20 launches each. */
+ * and L1 without smoothing of v) instead of ~20 launches each.  The launch is
+ * sized to be resident on the whole device at once: a fused sweep must not
+ * overlap other work on the device (another stream's launches could keep
+ * some of its blocks waiting; its barrier waits then give up, see
+ * darc_fused_barrier_ticks). */
 #define DARC_FUSED_AUTO 0 /* the autotuner's choice for the shape; separate otherwise */
 #define DARC_FUSED_OFF 1  /* separate launches */
 #define DARC_FUSED_ON 2   /* fused; DARC_EUNSUPPORTED for LNCC or smoothing */

@@ -145,8 +145,10 @@ int darc_exp_svf(const float* v, float* u, float* ckpt, int n, int d0, int d1, i
  *         squaring steps, two fields of scratch instead of n_sq-1 stored).
  *   g_u   [n][3][V] in.   g_v [n][3][V] out (overwritten, not accumulated).
  *   ws    scratch of darc_exp_svf_bwd_ws_bytes(..., has_ckpt = ckpt != NULL).
- * The scatter term is summed with LDS floating-point atomics: results are
- * reproducible only up to FP32 summation order.
+ * The scatter term is summed in an order that varies between runs (sources
+ * take their cell's LDS slots by integer atomics, and sources beyond a
+ * cell's slots are added by LDS float atomics): results are reproducible
+ * only up to FP32 summation order, and so are sweeps built on them.
  * ---------------------------------------------------------------------- */
 size_t darc_exp_svf_bwd_ws_bytes(int n, int d0, int d1, int d2, int n_sq, int has_ckpt);
 int darc_exp_svf_bwd(const float* v, const float* ckpt, const float* g_u, float* g_v, int n,

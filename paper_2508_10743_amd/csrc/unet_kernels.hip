@@ -582,24 +582,37 @@ __device__ __forceinline__ float from_bf16(uint16_t h) {
 
 // dW tiles 16 (co) x 16 NK (k) of one wave over a chunk of output voxels:
 // C[co][k] = sum_v dz[v][co] X(v, k) with the 32 voxels of a K step as the
-// MFMA reduction.  The reduction runs over voxels while both operands are
-// stored channels-last, so each K step is transposed through a small LDS
-// tile of the wave: lane l loads 8 channels of voxel l % 32 (one 16-byte
-// read of dz, and of X at each column group's tap: a group of 8 consecutive
-// k is one tap and 8 channels), writes them as [channel][voxel], and then
-// reads its A row / B column at 8 consecutive voxels as one 16-byte read.
+// MFMA reduction.  Both operands are stored channels-last, while each lane's
+// MFMA fragment holds 8 consecutive voxels of one row or column.  A K step
+// stages them channels-last in LDS, lane l writing the 8 channels of voxel
+// l % 32 it loaded (one 16-byte write; for X, a group of 8 consecutive k is
+// one tap and 8 channels), and reads its fragments with the transposing LDS
+// read: within each 16-lane group, lane j points at the 4 channels
+// 4 (j % 4).. of voxel base + j / 4, and lane i receives channel i of the
+// voxels base.. base + 3, so two reads give a lane its 8 voxels.
 // A wave reduces wch voxels (a multiple of 32) before its atomics into the
 // gradient: longer chunks mean fewer atomics on the same gradient entries,
 // shorter ones more waves for small layers (chosen at launch).
 constexpr int WNK = 4;  // 16-column k tiles per wave
+// MFMA fragment of lane (g, r) from a [32 voxel][16] BF16 LDS tile: element
+// m of the result is tile[8 g + m][r] (two transposing reads of 4 voxels).
+typedef short v4i16 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ bf16x8 tr_frag(const uint16_t* tile, int g, int r) {
+  typedef __attribute__((address_space(3))) v4i16* lds_v4;
+  const uint16_t* p = tile + (8 * g + (r >> 2)) * 16 + 4 * (r & 3);
+  const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4)(p));
+  const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4)(p + 4 * 16));
+  return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
 template <int X0>
 __global__ __launch_bounds__(64) void k_conv_wgrad(int wch, const uint16_t* __restrict__ dz, int cz,
                                                    const uint16_t* __restrict__ x0,
                                                    const uint16_t* __restrict__ x1, ConvGeom cg,
                                                    float* __restrict__ dw,
                                                    float* __restrict__ db) {
-  __shared__ __align__(16) uint16_t at[16 * 32];       // dz^T: [co][voxel]
-  __shared__ __align__(16) uint16_t bt[WNK][16 * 32];  // X^T:  [k][voxel]
+  __shared__ __align__(16) uint16_t at[32 * 16];       // dz: [voxel][co]
+  __shared__ __align__(16) uint16_t bt[WNK][32 * 16];  // X:  [voxel][k]
   constexpr bool half = X0 != 0;  // x0 is stored at half resolution
   const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
   const int vl = lane & 31, h = lane >> 5;  // staged voxel, channel half
@@ -687,34 +700,24 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(int wch, const uint16_t* __re
 #pragma unroll
     for (int t = 0; t < WNK; ++t)
       if (!bin[t]) braw[t] = make_uint4(0u, 0u, 0u, 0u);
-    const uint32_t aw[4] = {araw.x, araw.y, araw.z, araw.w};
+    *reinterpret_cast<uint4*>(&at[vl * 16 + 8 * h]) = araw;
+    if (bias) {
+      const uint32_t aw[4] = {araw.x, araw.y, araw.z, araw.w};
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      at[(8 * h + 2 * j) * 32 + vl] = static_cast<uint16_t>(aw[j]);
-      at[(8 * h + 2 * j + 1) * 32 + vl] = static_cast<uint16_t>(aw[j] >> 16);
-      if (bias) {
+      for (int j = 0; j < 4; ++j) {
         bacc[2 * j] += __uint_as_float(aw[j] << 16);
         bacc[2 * j + 1] += __uint_as_float(aw[j] & 0xFFFF0000u);
       }
     }
 #pragma unroll
-    for (int t = 0; t < WNK; ++t) {
-      const uint32_t bw[4] = {braw[t].x, braw[t].y, braw[t].z, braw[t].w};
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        bt[t][(8 * h + 2 * j) * 32 + vl] = static_cast<uint16_t>(bw[j]);
-        bt[t][(8 * h + 2 * j + 1) * 32 + vl] = static_cast<uint16_t>(bw[j] >> 16);
-      }
-    }
+    for (int t = 0; t < WNK; ++t) *reinterpret_cast<uint4*>(&bt[t][vl * 16 + 8 * h]) = braw[t];
     // one wave: its LDS operations complete in order, so the reads below
     // see the writes above, and the next step's writes follow these reads
-    const bf16x8 afrag = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&at[r * 32 + 8 * g]));
+    const bf16x8 afrag = tr_frag(at, g, r);
 #pragma unroll
-    for (int t = 0; t < WNK; ++t) {
-      const bf16x8 bfrag =
-          __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&bt[t][r * 32 + 8 * g]));
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, acc[t], 0, 0, 0);
-    }
+    for (int t = 0; t < WNK; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, tr_frag(bt[t], g, r), acc[t], 0, 0,
+                                                         0);
     // advance the staged voxel by 32
     o2 += 32;
     while (o2 >= cg.o2) {

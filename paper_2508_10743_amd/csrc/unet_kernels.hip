@@ -660,22 +660,19 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(int wch, const uint16_t* __re
   // the bias gradient sum_v dz[v][co], from the staged dz of the first k tile
   const bool bias = db != nullptr && blockIdx.y == 0;
   float bacc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  for (int step = 0; step < wch; step += 32) {
-    const long long vb = static_cast<long long>(blockIdx.x) * wch + step;
-    if (vb >= cg.nvox) break;  // uniform across the wave
-    const long long v = vb + vl;
+  // The loads of one K step (every load issued, from x0 or dz itself where
+  // the value is zero; the padding is applied when staged), then the staged
+  // voxel's coordinates advanced by 32.  A step's loads are issued before
+  // the previous step's products, so they arrive while those run.
+  auto issue = [&](int step, uint4& araw, bool& ain, uint4 (&braw)[WNK], bool (&bin)[WNK]) {
+    const long long v = static_cast<long long>(blockIdx.x) * wch + step + vl;
     const bool live = v < cg.nvox;
-    // stage dz^T and X^T of these 32 voxels: every load issued (from x0
-    // itself where the input is zero), the zero padding applied afterwards
-    uint4 araw = make_uint4(0u, 0u, 0u, 0u);
-    if (live && co0 + 8 * h < cz)
-      araw = *reinterpret_cast<const uint4*>(dz + v * cz + co0 + 8 * h);
+    ain = live && co0 + 8 * h < cz;
+    araw = *reinterpret_cast<const uint4*>(ain ? dz + v * cz + co0 + 8 * h : dz);
     const int q0 = o0 * cg.stride - 1, q1 = o1 * cg.stride - 1, q2 = o2 * cg.stride - 1;
     const int lb = (q0 * cg.i1 + q1) * cg.i2 + q2;
     const uint16_t* t0 = x0 + s * vin0 * cg.c0;
     const uint16_t* t1 = x1 + s * vin1 * cg.c1 - cg.c0;  // x1 channels follow the c0 of x0
-    uint4 braw[WNK];
-    bool bin[WNK];
 #pragma unroll
     for (int t = 0; t < WNK; ++t) {
       const int p0 = q0 + gta[t], p1 = q1 + gtb[t], p2 = q2 + gtc[t];
@@ -697,28 +694,6 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(int wch, const uint16_t* __re
       bin[t] = ok;
       braw[t] = *reinterpret_cast<const uint4*>(ok ? src : x0);
     }
-#pragma unroll
-    for (int t = 0; t < WNK; ++t)
-      if (!bin[t]) braw[t] = make_uint4(0u, 0u, 0u, 0u);
-    *reinterpret_cast<uint4*>(&at[vl * 16 + 8 * h]) = araw;
-    if (bias) {
-      const uint32_t aw[4] = {araw.x, araw.y, araw.z, araw.w};
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        bacc[2 * j] += __uint_as_float(aw[j] << 16);
-        bacc[2 * j + 1] += __uint_as_float(aw[j] & 0xFFFF0000u);
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < WNK; ++t) *reinterpret_cast<uint4*>(&bt[t][vl * 16 + 8 * h]) = braw[t];
-    // one wave: its LDS operations complete in order, so the reads below
-    // see the writes above, and the next step's writes follow these reads
-    const bf16x8 afrag = tr_frag(at, g, r);
-#pragma unroll
-    for (int t = 0; t < WNK; ++t)
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, tr_frag(bt[t], g, r), acc[t], 0, 0,
-                                                         0);
-    // advance the staged voxel by 32
     o2 += 32;
     while (o2 >= cg.o2) {
       o2 -= cg.o2;
@@ -729,6 +704,48 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(int wch, const uint16_t* __re
           ++s;
         }
       }
+    }
+  };
+  uint4 ca, cb[WNK], na, nb[WNK];
+  bool cain, cbin[WNK], nain, nbin[WNK];
+  issue(0, ca, cain, cb, cbin);
+  for (int step = 0; step < wch; step += 32) {
+    const long long vb = static_cast<long long>(blockIdx.x) * wch + step;
+    if (vb >= cg.nvox) break;  // uniform across the wave
+    // zero padding by selects (a branch would wait for every load in flight)
+    auto keep = [](uint4 q, bool k) {
+      return make_uint4(k ? q.x : 0u, k ? q.y : 0u, k ? q.z : 0u, k ? q.w : 0u);
+    };
+    ca = keep(ca, cain);
+#pragma unroll
+    for (int t = 0; t < WNK; ++t) cb[t] = keep(cb[t], cbin[t]);
+    *reinterpret_cast<uint4*>(&at[vl * 16 + 8 * h]) = ca;
+    if (bias) {
+      const uint32_t aw[4] = {ca.x, ca.y, ca.z, ca.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        bacc[2 * j] += __uint_as_float(aw[j] << 16);
+        bacc[2 * j + 1] += __uint_as_float(aw[j] & 0xFFFF0000u);
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < WNK; ++t) *reinterpret_cast<uint4*>(&bt[t][vl * 16 + 8 * h]) = cb[t];
+    // the next step's loads (past the chunk or the volume: from clamped
+    // addresses, never staged)
+    issue(step + 32, na, nain, nb, nbin);
+    // one wave: its LDS operations complete in order, so the reads below
+    // see the writes above, and the next step's writes follow these reads
+    const bf16x8 afrag = tr_frag(at, g, r);
+#pragma unroll
+    for (int t = 0; t < WNK; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, tr_frag(bt[t], g, r), acc[t], 0, 0,
+                                                         0);
+    ca = na;
+    cain = nain;
+#pragma unroll
+    for (int t = 0; t < WNK; ++t) {
+      cb[t] = nb[t];
+      cbin[t] = nbin[t];
     }
   }
 #pragma unroll

@@ -156,8 +156,19 @@ __device__ __forceinline__ float tri_value(const float (&c)[8], float t0, float 
   return lerp(lerp(c00, c01, t1), lerp(c10, c11, t1), t0);
 }
 
+// Two consecutive elements from a 4-byte aligned address (one 8-byte load;
+// gfx9 global loads need only dword alignment).
+__device__ __forceinline__ float2 ld_pair(const float* __restrict__ p) {
+  float2 v;
+  __builtin_memcpy(&v, p, sizeof(v));
+  return v;
+}
+
 // The 8 corners of the cell at (i0, i1, i2) of an image, zero outside.
-// Loads use clamped (always valid) addresses and are then masked.
+// Along d2 each corner row is one 8-byte load of the in-range pair
+// (jj, jj + 1), jj = clamp(i2, 0, D2 - 2), which holds both corners when
+// they are inside (i2 = -1 and i2 = D2 - 1 select its other half); rows and
+// planes use clamped (always valid) positions, and masks apply the padding.
 __device__ __forceinline__ void corners_zero(const float* __restrict__ img, const Geom& g, int i0,
                                              int i1, int i2, float (&c)[8]) {
   const bool a0 = (i0 >= 0) & (i0 < g.d0), a1 = (i0 + 1 >= 0) & (i0 + 1 < g.d0);
@@ -165,17 +176,20 @@ __device__ __forceinline__ void corners_zero(const float* __restrict__ img, cons
   const bool e0 = (i2 >= 0) & (i2 < g.d2), e1 = (i2 + 1 >= 0) & (i2 + 1 < g.d2);
   const int j0 = min(max(i0, 0), g.d0 - 1), j0n = min(max(i0 + 1, 0), g.d0 - 1);
   const int j1 = min(max(i1, 0), g.d1 - 1), j1n = min(max(i1 + 1, 0), g.d1 - 1);
-  const int j2 = min(max(i2, 0), g.d2 - 1), j2n = min(max(i2 + 1, 0), g.d2 - 1);
-  const int r00 = (j0 * g.d1 + j1) * g.d2, r01 = (j0 * g.d1 + j1n) * g.d2;
-  const int r10 = (j0n * g.d1 + j1) * g.d2, r11 = (j0n * g.d1 + j1n) * g.d2;
-  c[0] = (a0 & b0 & e0) ? img[r00 + j2] : 0.0f;
-  c[1] = (a0 & b0 & e1) ? img[r00 + j2n] : 0.0f;
-  c[2] = (a0 & b1 & e0) ? img[r01 + j2] : 0.0f;
-  c[3] = (a0 & b1 & e1) ? img[r01 + j2n] : 0.0f;
-  c[4] = (a1 & b0 & e0) ? img[r10 + j2] : 0.0f;
-  c[5] = (a1 & b0 & e1) ? img[r10 + j2n] : 0.0f;
-  c[6] = (a1 & b1 & e0) ? img[r11 + j2] : 0.0f;
-  c[7] = (a1 & b1 & e1) ? img[r11 + j2n] : 0.0f;
+  const int jj = min(max(i2, 0), g.d2 - 2);
+  const bool s0 = i2 == jj, s1 = i2 + 1 == jj;  // which half holds corner e = 0 / e = 1
+  const float2 p00 = ld_pair(img + (j0 * g.d1 + j1) * g.d2 + jj);
+  const float2 p01 = ld_pair(img + (j0 * g.d1 + j1n) * g.d2 + jj);
+  const float2 p10 = ld_pair(img + (j0n * g.d1 + j1) * g.d2 + jj);
+  const float2 p11 = ld_pair(img + (j0n * g.d1 + j1n) * g.d2 + jj);
+  c[0] = (a0 & b0 & e0) ? (s0 ? p00.x : p00.y) : 0.0f;
+  c[1] = (a0 & b0 & e1) ? (s1 ? p00.x : p00.y) : 0.0f;
+  c[2] = (a0 & b1 & e0) ? (s0 ? p01.x : p01.y) : 0.0f;
+  c[3] = (a0 & b1 & e1) ? (s1 ? p01.x : p01.y) : 0.0f;
+  c[4] = (a1 & b0 & e0) ? (s0 ? p10.x : p10.y) : 0.0f;
+  c[5] = (a1 & b0 & e1) ? (s1 ? p10.x : p10.y) : 0.0f;
+  c[6] = (a1 & b1 & e0) ? (s0 ? p11.x : p11.y) : 0.0f;
+  c[7] = (a1 & b1 & e1) ? (s1 ? p11.x : p11.y) : 0.0f;
 }
 
 // Zero-padded trilinear sample of an image at x + u (value and gradient).

@@ -362,8 +362,9 @@ __global__ __launch_bounds__(kNT, W <= 9 ? 3 : 2) void k_lncc_bwd(
         const float eI = wimg[tl.chan * wstr + idx];
         // fused: the image corners around x + u (zero padding applied when
         // they are used), then u of the next plane's output voxel
-        float cr[8], ct[3];
-        unsigned cmask = 0u;
+        float2 cr[4];  // corner rows (a, b): the pair (jj, jj + 1) along d2
+        float ct[3];
+        unsigned cmask = 0u, chalf = 0u;
         if (FUSED) {
           const int zc = min(max(zo, tl.z0), g.d0 - 1);
           int ci[3];
@@ -380,11 +381,18 @@ __global__ __launch_bounds__(kNT, W <= 9 ? 3 : 2) void k_lncc_bwd(
             inl |= static_cast<unsigned>(ci[d] >= 0 && ci[d] < dims[d]) << d;
             inh |= static_cast<unsigned>(ci[d] + 1 >= 0 && ci[d] + 1 < dims[d]) << d;
           }
+          // one 8-byte load per corner row: jj = clamp(i2, 0, D2 - 2) holds
+          // both in-range corners; bit e of chalf picks the half of corner e
+          const int jj = min(max(ci[2], 0), g.d2 - 2);
+          chalf = static_cast<unsigned>(ci[2] != jj) | (static_cast<unsigned>(ci[2] + 1 != jj) << 1);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int j0 = (r >> 1) ? hi[0] : lo[0], j1 = (r & 1) ? hi[1] : lo[1];
+            cr[r] = ld_pair(Io + (j0 * g.d1 + j1) * g.d2 + jj);
+          }
 #pragma unroll
           for (int k = 0; k < 8; ++k) {
             const int ka = k >> 2, kb = (k >> 1) & 1, kc = k & 1;
-            const int j0 = ka ? hi[0] : lo[0], j1 = kb ? hi[1] : lo[1], j2 = kc ? hi[2] : lo[2];
-            cr[k] = Io[(j0 * g.d1 + j1) * g.d2 + j2];
             const bool ok = ((ka ? inh : inl) & 1u) && ((kb ? inh : inl) & 2u) &&
                             ((kc ? inh : inl) & 4u);
             cmask |= static_cast<unsigned>(ok) << k;
@@ -438,7 +446,11 @@ __global__ __launch_bounds__(kNT, W <= 9 ? 3 : 2) void k_lncc_bwd(
             const float* f = uf;
             float cv[8];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) cv[k] = ((cmask >> k) & 1u) ? cr[k] : 0.0f;
+            for (int k = 0; k < 8; ++k) {
+              const float2 pr = cr[k >> 1];
+              const float vk = ((chalf >> (k & 1)) & 1u) ? pr.y : pr.x;
+              cv[k] = ((cmask >> k) & 1u) ? vk : 0.0f;
+            }
             const Tri t = tri_eval(cv, ct[0], ct[1], ct[2]);
             float r0 = 0.0f, r1 = 0.0f, r2 = 0.0f;
             if (rw.on) {

@@ -417,11 +417,11 @@ __device__ __forceinline__ void exp_bwd_tiled_body(TiledBwdLds& L, uint32_t blk,
   const int L2 = min(ox + BTX, g.d2) - 1;
   const int lx = threadIdx.x % BTX, ly = (threadIdx.x / BTX) % BTY, lz = threadIdx.x / (BTX * BTY);
   {
-    // subjects with reach 1 everywhere are handled by the marching kernel:
-    // skip the rest of this subject's tiles
+    // subjects with reach 2 or less everywhere are handled by the marching
+    // kernels: skip the rest of this subject's tiles
     const int* rc = reach + s * 8;
-    if (!ALL && rc[0] <= 1 && rc[1] <= 1 && rc[2] <= 1 && rc[3] <= 1 && rc[4] <= 1 &&
-        rc[5] <= 1) {
+    if (!ALL && rc[0] <= 2 && rc[1] <= 2 && rc[2] <= 2 && rc[3] <= 2 && rc[4] <= 2 &&
+        rc[5] <= 2) {
       bid = static_cast<uint32_t>(s + 1) * bg.ntiles - 1;
       continue;
     }
@@ -1020,6 +1020,375 @@ __global__ __launch_bounds__(ENT, 4) void k_exp_bwd_march(const float* __restric
   }
 }
 
+// Adjoint of one squaring step, marching, for a subject whose cell offsets
+// lie in [-2, 1] on every axis and reach beyond [-1, 0] somewhere (reach 2:
+// roughly 1 <= max |u_t| < 2, the later squaring steps of moderate
+// deformations).  The reach-1 kernel's scheme with wider windows: a source
+// of plane p falls in cell planes p-2 .. p+1, so cell plane z is filled from
+// the sources of planes z-1 .. z+2, whose cells are computed once, when their
+// plane is staged, and kept in registers for four iterations; sources up to
+// two voxels outside the column can land in its cell region (a two-voxel halo
+// ring of 176 positions, one for each of the first 176 threads); the direct
+// term's corners lie in planes z-2 .. z+2 of the u ring.  Iteration z:
+// (i) clear the cell plane and target plane z+1's overflow, stage u of plane
+// z+2 and compute its sources' cells; (ii) bin the sources of planes
+// z-1 .. z+2 whose cell lies in plane z; (iii) the direct term of the plane-z
+// targets; (iv) the gather, finishing plane z and starting plane z+1.
+// Blocks of subjects with reach 1 everywhere (the reach-1 kernel's) or
+// beyond 2 (the tiled kernel's) return at once.
+constexpr int H2X = ETX + 4, H2Y = ETY + 4;  // staged plane with a two-voxel halo: 36 x 12
+constexpr int H2P = H2X * H2Y;               // 432 positions
+constexpr int H2RING = H2P - ENT;            // 176 halo positions
+
+// One source: its cell packed as r2 (6 bits: corner column in the staged
+// plane), r1 (4 bits: corner row), o0 + 2 (2 bits: cell plane - source
+// plane + 2), the three clamped flags and a valid bit (the source exists and
+// its cell's corners lie in the staged plane); fractions and g.
+struct Src2 {
+  int key;
+  float t0, t1, t2, g0, g1, g2;
+};
+constexpr int kSrcValid = 1 << 15;
+
+template <bool FIRST>
+__global__ __launch_bounds__(ENT, 3) void k_exp_bwd_march2(const float* __restrict__ ut,
+                                                            const float* __restrict__ gin,
+                                                            float* __restrict__ gout,
+                                                            MarchGeom m, float scale,
+                                                            float oscale,
+                                                            const int* __restrict__ reach) {
+  __shared__ float uring[5][3][H2P];  // u_t of planes z-2 .. z+2 (slot p % 5)
+  __shared__ int bcnt[MCP];           // the live cell plane
+  __shared__ float4 bd4[KSLOT][MCP];  // t0, t1, t2, g0 per binned source (0 if empty)
+  __shared__ float2 bd2[KSLOT][MCP];  // g1, g2
+  __shared__ float ovf[2][3][ENT];    // overflow into target planes, by parity
+  const Geom& g = m.rec.g;
+  const MarchId id = march_id(m);
+  {
+    const int* rc = reach + id.s * 8;
+    const int mr = max(max(max(rc[0], rc[1]), max(rc[2], rc[3])), max(rc[4], rc[5]));
+    if (mr != 2) return;
+  }
+  const size_t off = static_cast<size_t>(id.s) * 3 * g.V;
+  const float* f = ut + off;
+  const float* gi = gin + off;
+  float* go = gout + off;
+  const int lx = threadIdx.x % ETX, ly = threadIdx.x / ETX;
+  const float js = FIRST ? scale : 1.0f;
+
+  // staged positions: j = 0 the thread's own voxel, j = 1 a halo-ring voxel
+  int pe[2], py[2], px[2], poff[2];
+  bool puse[2], pin[2];
+  pe[0] = (ly + 2) * H2X + lx + 2;
+  py[0] = id.oy + ly;
+  px[0] = id.ox + lx;
+  puse[0] = true;
+  {
+    const int r = threadIdx.x;
+    int hy, hx;
+    if (r < 2 * H2X) {  // rows 0 and 1
+      hy = r / H2X;
+      hx = r - hy * H2X;
+    } else if (r < 4 * H2X) {  // rows H2Y - 2 and H2Y - 1
+      const int q = r - 2 * H2X;
+      hy = H2Y - 2 + q / H2X;
+      hx = q - (q / H2X) * H2X;
+    } else {  // columns 0, 1, H2X - 2, H2X - 1 of rows 2 .. H2Y - 3
+      const int q = min(r - 4 * H2X, 4 * ETY - 1);
+      hy = 2 + q / 4;
+      const int col = q % 4;
+      hx = col < 2 ? col : H2X - 4 + col;
+    }
+    puse[1] = r < H2RING;
+    pe[1] = hy * H2X + hx;
+    py[1] = id.oy - 2 + hy;
+    px[1] = id.ox - 2 + hx;
+  }
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    pin[j] = py[j] >= 0 && py[j] < g.d1 && px[j] >= 0 && px[j] < g.d2;
+    poff[j] = min(max(py[j], 0), g.d1 - 1) * g.d2 + min(max(px[j], 0), g.d2 - 1);
+  }
+  if (!puse[1]) poff[1] = poff[0];
+
+  const float* fc[3] = {f, f + g.V, f + 2 * static_cast<size_t>(g.V)};
+  const float* gc[3] = {gi, gi + g.V, gi + 2 * static_cast<size_t>(g.V)};
+  // two planes in flight (every lane loads, planes past the volume clamped)
+  float pu[2][3], pg[2][3], pu2[2][3], pg2[2][3];
+  auto load_plane = [&](int z, float (&lu)[2][3], float (&lg)[2][3]) {
+    const int zc = min(max(z, 0), g.d0 - 1);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const uint32_t lin = static_cast<uint32_t>(zc * g.plane + poff[j]);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        lu[j][c] = ld_at(fc[c], lin);
+        lg[j][c] = ld_at(gc[c], lin);
+      }
+    }
+  };
+  auto store_u = [&](int z, const float (&su_)[2][3]) {
+    const int sl = (z + 10) % 5;
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      if (puse[j]) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) uring[sl][c][pe[j]] = su_[j][c];
+      }
+  };
+  auto clear_cells = [&]() {
+    const float4 z4 = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    const float2 z2 = make_float2(0.0f, 0.0f);
+    for (int i = threadIdx.x; i < MCP; i += ENT) {
+      bcnt[i] = 0;
+#pragma unroll
+      for (int k = 0; k < KSLOT; ++k) {
+        bd4[k][i] = z4;
+        bd2[k][i] = z2;
+      }
+    }
+  };
+  auto clear_ovf = [&](int tplane) {
+    float* o = &ovf[tplane & 1][0][0];
+    for (int i = threadIdx.x; i < 3 * ENT; i += ENT) o[i] = 0.0f;
+  };
+  // cells of the staged sources of plane p
+  auto cells_of = [&](int p, const float (&vu)[2][3], const float (&vg)[2][3], Src2 (&S)[2]) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      S[j].key = 0;
+      S[j].t0 = S[j].t1 = S[j].t2 = 0.0f;
+      S[j].g0 = vg[j][0];
+      S[j].g1 = vg[j][1];
+      S[j].g2 = vg[j][2];
+      if (puse[j]) {
+        float u0 = vu[j][0], u1 = vu[j][1], u2 = vu[j][2];
+        if (FIRST) {
+          u0 *= scale;
+          u1 *= scale;
+          u2 *= scale;
+        }
+        const int pc = min(max(p, 0), g.d0 - 1);
+        const BorderCell bc = border_cell(g, pc, py[j], px[j], u0, u1, u2);
+        const int o0 = bc.i0 - pc, r1 = bc.i1 - id.oy + 2, r2 = bc.i2 - id.ox + 2;
+        const bool ok = pin[j] && p >= 0 && p < g.d0 && o0 >= -2 && o0 <= 1 && r1 >= 0 &&
+                        r1 + 1 < H2Y && r2 >= 0 && r2 + 1 < H2X;
+        S[j].key = ok ? (r2 | (r1 << 6) | ((o0 + 2) << 10) | (static_cast<int>(bc.k0) << 12) |
+                         (static_cast<int>(bc.k1) << 13) | (static_cast<int>(bc.k2) << 14) |
+                         kSrcValid)
+                      : 0;
+        S[j].t0 = bc.t0;
+        S[j].t1 = bc.t1;
+        S[j].t2 = bc.t2;
+      }
+    }
+  };
+  // bin source s of plane p if its cell lies in cell plane cz and in the
+  // column's cell region
+  auto bin_one = [&](int cz, int p, const Src2& sv) {
+    if (!(sv.key & kSrcValid)) return;
+    if (p + ((sv.key >> 10) & 3) - 2 != cz) return;
+    const int cy = ((sv.key >> 6) & 15) - 1, cx = (sv.key & 63) - 1;
+    if (cy < 0 || cy >= MCY || cx < 0 || cx >= MCX) return;
+    const int ci = cy * MCX + cx;
+    const int slot = atomicAdd(&bcnt[ci], 1);
+    if (slot < KSLOT) {
+      bd4[slot][ci] = make_float4(sv.t0, sv.t1, sv.t2, sv.g0);
+      bd2[slot][ci] = make_float2(sv.g1, sv.g2);
+    } else {
+      const float w0[2] = {1.0f - sv.t0, sv.t0};
+      const float w1[2] = {1.0f - sv.t1, sv.t1};
+      const float w2[2] = {1.0f - sv.t2, sv.t2};
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        const int tz = cz + a;  // target plane
+        if (tz < id.z0 || tz >= id.z1) continue;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+#pragma unroll
+          for (int ee = 0; ee < 2; ++ee) {
+            const int ty = cy + b - 1, tx = cx + ee - 1;
+            if (ty >= 0 && ty < ETY && tx >= 0 && tx < ETX) {
+              const float w = w0[a] * w1[b] * w2[ee];
+              float* ov = &ovf[tz & 1][0][0] + ty * ETX + tx;
+              atomicAdd(ov, w * sv.g0);
+              atomicAdd(ov + ENT, w * sv.g1);
+              atomicAdd(ov + 2 * ENT, w * sv.g2);
+            }
+          }
+        }
+      }
+    }
+  };
+  // one pass over the live cell plane (as in the reach-1 kernel)
+  auto gather = [&](float (&lo)[3], float (&up)[3], bool upper) {
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int ci = (ly + 1 - b) * MCX + (lx + 1 - e);
+#pragma unroll
+        for (int j = 0; j < KSLOT; ++j) {
+          const float4 q4 = bd4[j][ci];
+          const float2 q2 = bd2[j][ci];
+          const float w1 = b ? q4.y : 1.0f - q4.y;
+          const float w12 = e ? w1 * q4.z : fmaf(-w1, q4.z, w1);
+          const float wl = fmaf(-w12, q4.x, w12);
+          lo[0] += wl * q4.w;
+          lo[1] += wl * q2.x;
+          lo[2] += wl * q2.y;
+          if (upper) {
+            const float wu = w12 * q4.x;
+            up[0] += wu * q4.w;
+            up[1] += wu * q2.x;
+            up[2] += wu * q2.y;
+          }
+        }
+      }
+    }
+  };
+
+  const bool colv = pin[0];
+  Src2 R0[2], R1[2], R2[2], R3[2];  // sources of four consecutive planes
+  float accA[3] = {0.0f, 0.0f, 0.0f}, accB[3] = {0.0f, 0.0f, 0.0f};
+
+  // prologue: planes z0-2 .. z0+1 staged with their cells (in R3, R0, R1,
+  // R2), cell plane z0-1 filled, its a = 1 part of the plane-z0 targets;
+  // planes z0+2 and z0+3 in flight
+  clear_cells();
+  clear_ovf(id.z0);
+  load_plane(id.z0 - 2, pu, pg);
+  store_u(id.z0 - 2, pu);
+  cells_of(id.z0 - 2, pu, pg, R3);
+  load_plane(id.z0 - 1, pu, pg);
+  store_u(id.z0 - 1, pu);
+  cells_of(id.z0 - 1, pu, pg, R0);
+  load_plane(id.z0, pu, pg);
+  store_u(id.z0, pu);
+  cells_of(id.z0, pu, pg, R1);
+  load_plane(id.z0 + 1, pu, pg);
+  store_u(id.z0 + 1, pu);
+  cells_of(id.z0 + 1, pu, pg, R2);
+  load_plane(id.z0 + 2, pu, pg);
+  load_plane(id.z0 + 3, pu2, pg2);
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    bin_one(id.z0 - 1, id.z0 - 2, R3[j]);
+    bin_one(id.z0 - 1, id.z0 - 1, R0[j]);
+    bin_one(id.z0 - 1, id.z0, R1[j]);
+    bin_one(id.z0 - 1, id.z0 + 1, R2[j]);
+  }
+  __syncthreads();
+  {
+    float none[3] = {0.0f, 0.0f, 0.0f};
+    if (colv) gather(none, accA, true);
+  }
+  __syncthreads();
+
+  // one plane: Sm (plane z-1), S0 (z), S1 (z+1) hold their sources, Sn
+  // receives plane z+2's; (xu, xg) holds plane z+2 on entry and takes z+4;
+  // acc holds the plane-z targets' a = 1 part and nacc receives plane z+1's
+  auto step = [&](int z, Src2 (&Sm)[2], Src2 (&S0)[2], Src2 (&S1)[2], Src2 (&Sn)[2],
+                  float (&xu)[2][3], float (&xg)[2][3], float (&acc)[3], float (&nacc)[3]) {
+    // (i)
+    clear_cells();
+    clear_ovf(z + 1);
+    store_u(z + 2, xu);
+    cells_of(z + 2, xu, xg, Sn);
+    load_plane(z + 4, xu, xg);
+    __syncthreads();
+    // (ii)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      bin_one(z, z - 1, Sm[j]);
+      bin_one(z, z, S0[j]);
+      bin_one(z, z + 1, S1[j]);
+      bin_one(z, z + 2, Sn[j]);
+    }
+    // (iii) direct term of the plane-z targets: the own source's cell
+    float r[3] = {acc[0], acc[1], acc[2]};
+    if (colv) {
+      const Src2& sv = S0[0];
+      Tri t;
+      bool k0, k1, k2;
+      if (sv.key & kSrcValid) {
+        const int i0 = z + ((sv.key >> 10) & 3) - 2;
+        const int sa = (i0 + 10) % 5, sb = (i0 + 11) % 5;
+        const int pb = ((sv.key >> 6) & 15) * H2X + (sv.key & 63);
+        float h[8];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float gcv = c == 0 ? sv.g0 : (c == 1 ? sv.g1 : sv.g2);
+          const float cv[8] = {uring[sa][c][pb],       uring[sa][c][pb + 1],
+                               uring[sa][c][pb + H2X], uring[sa][c][pb + H2X + 1],
+                               uring[sb][c][pb],       uring[sb][c][pb + 1],
+                               uring[sb][c][pb + H2X], uring[sb][c][pb + H2X + 1]};
+#pragma unroll
+          for (int k = 0; k < 8; ++k) h[k] = c == 0 ? gcv * cv[k] : h[k] + gcv * cv[k];
+        }
+        t = tri_eval(h, sv.t0, sv.t1, sv.t2);
+        k0 = (sv.key >> 12) & 1;
+        k1 = (sv.key >> 13) & 1;
+        k2 = (sv.key >> 14) & 1;
+      } else {
+        // a cell outside the staged planes (not reached while every offset
+        // lies in [-2, 1]): corners from memory
+        float u0 = uring[(z + 10) % 5][0][pe[0]], u1 = uring[(z + 10) % 5][1][pe[0]],
+              u2 = uring[(z + 10) % 5][2][pe[0]];
+        if (FIRST) {
+          u0 *= scale;
+          u1 *= scale;
+          u2 *= scale;
+        }
+        const BorderCell bc = border_cell(g, z, py[0], px[0], u0, u1, u2);
+        t.v = 0.0f;
+        t.d0 = t.d1 = t.d2 = 0.0f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          const float gcv = c == 0 ? sv.g0 : (c == 1 ? sv.g1 : sv.g2);
+          float cv[8];
+          corners_border(fc[c], g, bc.base, cv);
+          const Tri tc = tri_eval(cv, bc.t0, bc.t1, bc.t2);
+          t.d0 += tc.d0 * gcv;
+          t.d1 += tc.d1 * gcv;
+          t.d2 += tc.d2 * gcv;
+        }
+        k0 = bc.k0;
+        k1 = bc.k1;
+        k2 = bc.k2;
+      }
+      r[0] += sv.g0 + (k0 ? 0.0f : t.d0 * js);
+      r[1] += sv.g1 + (k1 ? 0.0f : t.d1 * js);
+      r[2] += sv.g2 + (k2 ? 0.0f : t.d2 * js);
+    }
+    __syncthreads();
+    // (iv)
+#pragma unroll
+    for (int c = 0; c < 3; ++c) nacc[c] = 0.0f;
+    if (colv) {
+      gather(r, nacc, z + 1 < id.z1);
+      const float* ov = &ovf[z & 1][0][0];
+      r[0] += ov[threadIdx.x];
+      r[1] += ov[ENT + threadIdx.x];
+      r[2] += ov[2 * ENT + threadIdx.x];
+      const uint32_t lin = static_cast<uint32_t>(z * g.plane + py[0] * g.d2 + px[0]);
+      st_at(go, lin, r[0] * oscale);
+      st_at(go + g.V, lin, r[1] * oscale);
+      st_at(go + 2 * static_cast<size_t>(g.V), lin, r[2] * oscale);
+    }
+    __syncthreads();
+  };
+  // unrolled by four so that the source sets, prefetch buffers and partials
+  // keep their registers
+  for (int z = id.z0; z < id.z1; z += 4) {
+    step(z, R0, R1, R2, R3, pu, pg, accA, accB);
+    if (z + 1 < id.z1) step(z + 1, R1, R2, R3, R0, pu2, pg2, accB, accA);
+    if (z + 2 < id.z1) step(z + 2, R2, R3, R0, R1, pu, pg, accA, accB);
+    if (z + 3 < id.z1) step(z + 3, R3, R0, R1, R2, pu2, pg2, accB, accA);
+  }
+}
+
 // Blocks of the persistent tiled adjoint: enough to fill the chip several
 // times over; each walks total / grid tiles.
 uint32_t bwd_grid(const BwdGeom& bg) { return bg.total < 4096u ? bg.total : 4096u; }
@@ -1459,16 +1828,20 @@ void launch_bwd_step(const float* ut, const float* gin, float* gout, bool first,
     prof_end(st, KC_EXP_BWD);
     return;
   }
-  // each subject is handled by exactly one of the two kernels (decided on the
-  // device from its reach); the other one's blocks return at once
+  // each subject is handled by exactly one of the three kernels (decided on
+  // the device from its reach: 1, 2, beyond); the others' blocks return at once
   if (first) {
     hipLaunchKernelGGL((k_exp_bwd_march<true>), dim3(m.total), dim3(ENT), 0, st, ut, gin, gout, m,
                        scale, scale, rc);
+    hipLaunchKernelGGL((k_exp_bwd_march2<true>), dim3(m.total), dim3(ENT), 0, st, ut, gin, gout,
+                       m, scale, scale, rc);
     hipLaunchKernelGGL((k_exp_bwd<true, false>), dim3(bwd_grid(bg)), dim3(BNT), 0, st, ut, gin,
                        gout, bg, scale, scale, bx, rc);
   } else {
     hipLaunchKernelGGL((k_exp_bwd_march<false>), dim3(m.total), dim3(ENT), 0, st, ut, gin, gout, m,
                        1.0f, 1.0f, rc);
+    hipLaunchKernelGGL((k_exp_bwd_march2<false>), dim3(m.total), dim3(ENT), 0, st, ut, gin, gout,
+                       m, 1.0f, 1.0f, rc);
     hipLaunchKernelGGL((k_exp_bwd<false, false>), dim3(bwd_grid(bg)), dim3(BNT), 0, st, ut, gin,
                        gout, bg, 1.0f, 1.0f, bx, rc);
   }

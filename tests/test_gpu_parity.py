@@ -162,6 +162,40 @@ def test_exp_small_displacements(dev, dims, amp):
         assert rel_l2(gv[i], O.exp_svf_bwd(steps, gu[i].astype(np.float64))) <= TOL_GRAD
 
 
+def cell_offsets(u):
+    """Per axis, the border cell of x + u (floor clamped to [0, D - 2]) minus x."""
+    dims = u.shape[1:]
+    out = []
+    for d in range(3):
+        x = np.arange(dims[d]).reshape([-1 if k == d else 1 for k in range(3)])
+        out.append(np.clip(np.floor(x + u[d]), 0, dims[d] - 2) - x)
+    return out
+
+
+@pytest.mark.parametrize("dims,amp,corr", [((24, 20, 70), 3.5, 4.0), ((13, 37, 41), 3.0, 3.0)])
+def test_exp_adjoint_reach_two(dev, dims, amp, corr):
+    """Squaring steps whose cell offsets span [-2, 1] on some axis, the case of
+    the reach-2 marching adjoint (the others run on the reach-1 marching or
+    the tiled kernel): the adjoint against the oracle's adjoint of the GPU's
+    own squaring steps, and at least one step of the case is checked to be in
+    that regime."""
+    v = random_velocity(150, 2, dims, amp, corr_len=corr)
+    gu = random_volume(151, v.shape, -1.0, 1.0)
+    vd = g(v, dev)
+    u, ck = D.exp_svf(vd, 7)
+    gv = h(D.exp_svf_bwd(vd, ck, g(gu, dev), 7))
+    ck = h(ck)
+    reach2 = 0
+    for i in range(2):
+        own = [v[i].astype(np.float64) / 2 ** 7] + [ck[t, i].astype(np.float64) for t in range(6)]
+        for ut in own:
+            offs = cell_offsets(ut)
+            lo, hi = min(o.min() for o in offs), max(o.max() for o in offs)
+            reach2 += int(lo >= -2 and hi <= 1 and (lo < -1 or hi > 0))
+        assert rel_l2(gv[i], O.exp_svf_bwd(own, gu[i].astype(np.float64))) <= TOL_GRAD
+    assert reach2 >= 1
+
+
 # ------------------------------------------------------------------- warp
 
 

@@ -1113,8 +1113,9 @@ __global__ __launch_bounds__(ENT, 3) void k_exp_bwd_march2(const float* __restri
 
   const float* fc[3] = {f, f + g.V, f + 2 * static_cast<size_t>(g.V)};
   const float* gc[3] = {gi, gi + g.V, gi + 2 * static_cast<size_t>(g.V)};
-  // two planes in flight (every lane loads, planes past the volume clamped)
-  float pu[2][3], pg[2][3], pu2[2][3], pg2[2][3];
+  // the next plane to stage in flight (every lane loads, planes past the
+  // volume clamped; a second buffer measured slower at this register count)
+  float pu[2][3], pg[2][3];
   auto load_plane = [&](int z, float (&lu)[2][3], float (&lg)[2][3]) {
     const int zc = min(max(z, 0), g.d0 - 1);
 #pragma unroll
@@ -1254,7 +1255,7 @@ __global__ __launch_bounds__(ENT, 3) void k_exp_bwd_march2(const float* __restri
 
   // prologue: planes z0-2 .. z0+1 staged with their cells (in R3, R0, R1,
   // R2), cell plane z0-1 filled, its a = 1 part of the plane-z0 targets;
-  // planes z0+2 and z0+3 in flight
+  // plane z0+2 in flight
   clear_cells();
   clear_ovf(id.z0);
   load_plane(id.z0 - 2, pu, pg);
@@ -1270,7 +1271,6 @@ __global__ __launch_bounds__(ENT, 3) void k_exp_bwd_march2(const float* __restri
   store_u(id.z0 + 1, pu);
   cells_of(id.z0 + 1, pu, pg, R2);
   load_plane(id.z0 + 2, pu, pg);
-  load_plane(id.z0 + 3, pu2, pg2);
   __syncthreads();
 #pragma unroll
   for (int j = 0; j < 2; ++j) {
@@ -1287,7 +1287,7 @@ __global__ __launch_bounds__(ENT, 3) void k_exp_bwd_march2(const float* __restri
   __syncthreads();
 
   // one plane: Sm (plane z-1), S0 (z), S1 (z+1) hold their sources, Sn
-  // receives plane z+2's; (xu, xg) holds plane z+2 on entry and takes z+4;
+  // receives plane z+2's; (xu, xg) holds plane z+2 on entry and takes z+3;
   // acc holds the plane-z targets' a = 1 part and nacc receives plane z+1's
   auto step = [&](int z, Src2 (&Sm)[2], Src2 (&S0)[2], Src2 (&S1)[2], Src2 (&Sn)[2],
                   float (&xu)[2][3], float (&xg)[2][3], float (&acc)[3], float (&nacc)[3]) {
@@ -1296,7 +1296,7 @@ __global__ __launch_bounds__(ENT, 3) void k_exp_bwd_march2(const float* __restri
     clear_ovf(z + 1);
     store_u(z + 2, xu);
     cells_of(z + 2, xu, xg, Sn);
-    load_plane(z + 4, xu, xg);
+    load_plane(z + 3, xu, xg);
     __syncthreads();
     // (ii)
 #pragma unroll
@@ -1379,13 +1379,13 @@ __global__ __launch_bounds__(ENT, 3) void k_exp_bwd_march2(const float* __restri
     }
     __syncthreads();
   };
-  // unrolled by four so that the source sets, prefetch buffers and partials
-  // keep their registers
+  // unrolled by four so that the source sets and partials keep their
+  // registers
   for (int z = id.z0; z < id.z1; z += 4) {
     step(z, R0, R1, R2, R3, pu, pg, accA, accB);
-    if (z + 1 < id.z1) step(z + 1, R1, R2, R3, R0, pu2, pg2, accB, accA);
+    if (z + 1 < id.z1) step(z + 1, R1, R2, R3, R0, pu, pg, accB, accA);
     if (z + 2 < id.z1) step(z + 2, R2, R3, R0, R1, pu, pg, accA, accB);
-    if (z + 3 < id.z1) step(z + 3, R3, R0, R1, R2, pu2, pg2, accB, accA);
+    if (z + 3 < id.z1) step(z + 3, R3, R0, R1, R2, pu, pg, accB, accA);
   }
 }
 

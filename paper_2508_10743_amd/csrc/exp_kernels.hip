@@ -196,8 +196,7 @@ struct MarchId {
   int s, tx, ty, ox, oy, z0, z1;
 };
 
-__device__ __forceinline__ MarchId march_id(const MarchGeom& m) {
-  uint32_t b = xcd_remap(blockIdx.x, m.total);
+__device__ __forceinline__ MarchId march_id_at(const MarchGeom& m, uint32_t b) {
   MarchId id;
   id.tx = static_cast<int>(b % m.rec.ntx);
   b /= m.rec.ntx;
@@ -210,6 +209,10 @@ __device__ __forceinline__ MarchId march_id(const MarchGeom& m) {
   id.z0 = zc * m.tz;
   id.z1 = min(id.z0 + m.tz, m.rec.g.d0);
   return id;
+}
+
+__device__ __forceinline__ MarchId march_id(const MarchGeom& m) {
+  return march_id_at(m, xcd_remap(blockIdx.x, m.total));
 }
 
 // Halo positions of one plane handled by this thread: in-plane offset of the
@@ -1063,11 +1066,27 @@ __global__ __launch_bounds__(ENT, 3) void k_exp_bwd_march2(const float* __restri
   __shared__ float2 bd2[KSLOT][MCP];  // g1, g2
   __shared__ float ovf[2][3][ENT];    // overflow into target planes, by parity
   const Geom& g = m.rec.g;
-  const MarchId id = march_id(m);
+  {
+    // nothing to do unless some subject of the launch has reach 2
+    const int nsub = static_cast<int>(m.total / (static_cast<uint32_t>(m.rec.ntx) * m.rec.nty *
+                                                  m.nzc));
+    int mine = 0;
+    for (int q = threadIdx.x; q < nsub; q += ENT) {
+      const int* rc = reach + q * 8;
+      mine |= max(max(max(rc[0], rc[1]), max(rc[2], rc[3])), max(rc[4], rc[5])) == 2;
+    }
+    if (!__syncthreads_or(mine)) return;
+  }
+  // persistent: the blocks (all resident) step through the column chunks
+  // together, block v taking chunks v, v + grid, ..., so that the chunks in
+  // flight at once are neighbours (and those of one XCD a contiguous range);
+  // chunks of subjects that are not this kernel's are passed over
+  for (uint32_t bid = xcd_remap(blockIdx.x, gridDim.x); bid < m.total; bid += gridDim.x) {
+  const MarchId id = march_id_at(m, bid);
   {
     const int* rc = reach + id.s * 8;
     const int mr = max(max(max(rc[0], rc[1]), max(rc[2], rc[3])), max(rc[4], rc[5]));
-    if (mr != 2) return;
+    if (mr != 2) continue;
   }
   const size_t off = static_cast<size_t>(id.s) * 3 * g.V;
   const float* f = ut + off;
@@ -1387,6 +1406,28 @@ __global__ __launch_bounds__(ENT, 3) void k_exp_bwd_march2(const float* __restri
     if (z + 2 < id.z1) step(z + 2, R2, R3, R0, R1, pu, pg, accA, accB);
     if (z + 3 < id.z1) step(z + 3, R3, R0, R1, R2, pu, pg, accB, accA);
   }
+  }  // the last step's barrier lets the next chunk reuse the LDS
+}
+
+// Blocks of the persistent reach-2 marching adjoint: as many as are resident
+// at once on the current device (so that no block waits for a second round),
+// each taking every grid-th column chunk.
+uint32_t march2_grid(const MarchGeom& m) {
+  static int cap[64] = {};
+  int dev = 0;
+  uint32_t grid = 2048u;  // when the occupancy query fails
+  if (hipGetDevice(&dev) == hipSuccess && dev >= 0 && dev < 64) {
+    int& c = cap[dev];
+    if (c == 0) {
+      int per_cu = 0, cus = 0;
+      if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_exp_bwd_march2<false>, ENT,
+                                                       0) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess)
+        c = per_cu * cus;
+    }
+    if (c > 0) grid = static_cast<uint32_t>(c);
+  }
+  return m.total < grid ? m.total : grid;
 }
 
 // Blocks of the persistent tiled adjoint: enough to fill the chip several
@@ -1833,15 +1874,15 @@ void launch_bwd_step(const float* ut, const float* gin, float* gout, bool first,
   if (first) {
     hipLaunchKernelGGL((k_exp_bwd_march<true>), dim3(m.total), dim3(ENT), 0, st, ut, gin, gout, m,
                        scale, scale, rc);
-    hipLaunchKernelGGL((k_exp_bwd_march2<true>), dim3(m.total), dim3(ENT), 0, st, ut, gin, gout,
-                       m, scale, scale, rc);
+    hipLaunchKernelGGL((k_exp_bwd_march2<true>), dim3(march2_grid(m)), dim3(ENT), 0, st, ut, gin,
+                       gout, m, scale, scale, rc);
     hipLaunchKernelGGL((k_exp_bwd<true, false>), dim3(bwd_grid(bg)), dim3(BNT), 0, st, ut, gin,
                        gout, bg, scale, scale, bx, rc);
   } else {
     hipLaunchKernelGGL((k_exp_bwd_march<false>), dim3(m.total), dim3(ENT), 0, st, ut, gin, gout, m,
                        1.0f, 1.0f, rc);
-    hipLaunchKernelGGL((k_exp_bwd_march2<false>), dim3(m.total), dim3(ENT), 0, st, ut, gin, gout,
-                       m, 1.0f, 1.0f, rc);
+    hipLaunchKernelGGL((k_exp_bwd_march2<false>), dim3(march2_grid(m)), dim3(ENT), 0, st, ut, gin,
+                       gout, m, 1.0f, 1.0f, rc);
     hipLaunchKernelGGL((k_exp_bwd<false, false>), dim3(bwd_grid(bg)), dim3(BNT), 0, st, ut, gin,
                        gout, bg, 1.0f, 1.0f, bx, rc);
   }

@@ -196,6 +196,28 @@ def test_exp_adjoint_reach_two(dev, dims, amp, corr):
     assert reach2 >= 1
 
 
+def test_exp_adjoint_mixed_reach_in_one_launch(dev):
+    """Three subjects in one launch whose last squaring step has reach 1, 2
+    and beyond 2: each step runs the three adjoint kernels side by side, each
+    taking its own subjects (chosen on the device from the recorded reach)."""
+    dims = (22, 19, 45)
+    v = np.concatenate([random_velocity(160 + k, 1, dims, amp, corr_len=4.0)
+                        for k, amp in enumerate((0.6, 3.5, 10.0))])
+    gu = random_volume(163, v.shape, -1.0, 1.0)
+    vd = g(v, dev)
+    u, ck = D.exp_svf(vd, 7)
+    gv = h(D.exp_svf_bwd(vd, ck, g(gu, dev), 7))
+    ck = h(ck)
+    reaches = []
+    for i in range(3):
+        own = [v[i].astype(np.float64) / 2 ** 7] + [ck[t, i].astype(np.float64) for t in range(6)]
+        offs = cell_offsets(own[-1])
+        lo, hi = min(o.min() for o in offs), max(o.max() for o in offs)
+        reaches.append(int(max(-lo, hi + 1)))
+        assert rel_l2(gv[i], O.exp_svf_bwd(own, gu[i].astype(np.float64))) <= TOL_GRAD
+    assert reaches[0] == 1 and reaches[1] == 2 and reaches[2] > 2, reaches
+
+
 # ------------------------------------------------------------------- warp
 
 

@@ -877,9 +877,14 @@ void unet_run_backward(const uint16_t* wq, const float* w, const float* b, const
     g.ycl32 = 1;
     const Geom full = make_geom(g.i0, g.i1, g.i2);
     if (S.c1) {  // concatenated input: split into the deeper and the skip tensor
+      // layer 4 reads (e3, e2), layer 5 (d2, e1), layer 6 (d1, e0); the
+      // epilogue writes the skip channels straight into their gradient and
+      // the deeper tensor's channels compactly, whose 2 x 2 x 2 children are
+      // then summed to its half resolution
+      g.csplit = S.c0;
+      g.y32b = dy[6 - l];
       launch_conv3d(dz, nullptr, wt, nullptr, nullptr, dx, g, st);
-      // layer 4 reads (e3, e2), layer 5 (d2, e1), layer 6 (d1, e0)
-      launch_split_grad(dx, full, n, S.c0, S.c1, dy[l - 1], dy[6 - l], st);
+      launch_split_half(dx, full, n, S.c0, dy[l - 1], st);
     } else if (l == 7) {
       launch_conv3d(dz, nullptr, wt, nullptr, nullptr, dy[6], g, st);
     } else {  // stride-2 encoder layers: their input already holds the skip part

@@ -172,6 +172,8 @@ struct ConvGeom {
   int kpad, cout, act;
   float slope;
   int ycl32, accum;   // y32 channels-last [nvox][cout] instead of planar; add to y32
+  int csplit;         // > 0 (with ycl32): y32 takes channels [0, csplit) as [nvox][csplit]
+  float* y32b;        //   and y32b channels [csplit, cout) as [nvox][cout - csplit]
 };
 // Weight row length for cin input channels: ntaps * ceil(cin/8) * 8 rounded up to 32.
 int conv_kpad(int cin, int ntaps);
@@ -197,10 +199,11 @@ void launch_pack_wt(const float* w, int cin, int cout, int cz, int kpad_f, int k
 // [n][c][nvox/n] when planar), y the layer's BF16 output (ignored when !act).
 void launch_act_bwd(const float* dy, const uint16_t* y, long long nvox, int n, int c, int cz,
                     int act, int planar, float slope, uint16_t* dz, hipStream_t st);
-// Gradient of cat(up2(x0), x1) split: d0 [n][half][c0] = sum over the 8 children
-// of dx[..][0:c0]; d1 [n][full][c1] = dx[..][c0:c0+c1] (both overwritten).
-void launch_split_grad(const float* dx, const Geom& full, int n, int c0, int c1, float* d0,
-                       float* d1, hipStream_t st);
+// Gradient of cat(up2(x0), x1), x0's part: d0 [n][V/8][c0] (overwritten) = sum
+// over the 2 x 2 x 2 children of dx [n][V][c0] (the convolution writes x1's
+// part directly, ConvGeom::csplit).
+void launch_split_half(const float* dx, const Geom& full, int n, int c0, float* d0,
+                       hipStream_t st);
 // out = BF16(in), count values
 void launch_to_bf16(const float* in, uint16_t* out, long long count, hipStream_t st);
 // loss += sum (p - t)^2 / count (FP64), g = 2 (p - t) / count

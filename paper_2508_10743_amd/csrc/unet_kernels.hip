@@ -183,7 +183,9 @@ __global__ __launch_bounds__(CNT) void k_conv3d(const uint16_t* __restrict__ x0,
         if (y16) {
           y16[mo * cg.cout + co] = to_bf16(val);
         } else if (cg.ycl32) {
-          float* d = y32 + mo * cg.cout + co;
+          float* d = cg.csplit == 0 ? y32 + mo * cg.cout + co
+                     : co < cg.csplit ? y32 + mo * cg.csplit + co
+                                      : cg.y32b + mo * (cg.cout - cg.csplit) + (co - cg.csplit);
           *d = cg.accum ? *d + val : val;
         } else {
           const long long so = mo / ov;
@@ -382,7 +384,9 @@ __global__ __launch_bounds__(CNT) void k_conv3d_lds(const uint16_t* __restrict__
         if (y16) {
           y16[mo * cg.cout + co] = to_bf16(val);
         } else if (cg.ycl32) {
-          float* d = y32 + mo * cg.cout + co;
+          float* d = cg.csplit == 0 ? y32 + mo * cg.cout + co
+                     : co < cg.csplit ? y32 + mo * cg.csplit + co
+                                      : cg.y32b + mo * (cg.cout - cg.csplit) + (co - cg.csplit);
           *d = cg.accum ? *d + val : val;
         } else {
           y32[(s * cg.cout + co) * per + vo] = val;
@@ -550,7 +554,9 @@ __global__ __launch_bounds__(CNT) void k_conv3d_sub(const uint16_t* __restrict__
         if (y16) {
           y16[mo * cg.cout + co] = to_bf16(val);
         } else if (cg.ycl32) {
-          float* d = y32 + mo * cg.cout + co;
+          float* d = cg.csplit == 0 ? y32 + mo * cg.cout + co
+                     : co < cg.csplit ? y32 + mo * cg.csplit + co
+                                      : cg.y32b + mo * (cg.cout - cg.csplit) + (co - cg.csplit);
           *d = cg.accum ? *d + val : val;
         } else {
           y32[(s * cg.cout + co) * per + vo] = val;
@@ -810,8 +816,7 @@ __global__ __launch_bounds__(kBlock) void k_act_bwd(const float* __restrict__ dy
 }
 
 __global__ __launch_bounds__(kBlock) void k_split_half(const float* __restrict__ dx, Geom full,
-                                                       int n, int c0, int c1,
-                                                       float* __restrict__ d0) {
+                                                       int n, int c0, float* __restrict__ d0) {
   const int h0 = full.d0 / 2, h1 = full.d1 / 2, h2 = full.d2 / 2;
   const long long hv = static_cast<long long>(h0) * h1 * h2;
   const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
@@ -823,7 +828,6 @@ __global__ __launch_bounds__(kBlock) void k_split_half(const float* __restrict__
   const int q2 = rem % h2;
   rem /= h2;
   const int q1 = rem % h1, q0 = rem / h1;
-  const int ct = c0 + c1;
   float acc = 0.0f;
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -832,17 +836,9 @@ __global__ __launch_bounds__(kBlock) void k_split_half(const float* __restrict__
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
         const long long p = ((s * full.d0 + 2 * q0 + a) * full.d1 + 2 * q1 + b) * full.d2 + 2 * q2 + e;
-        acc += dx[p * ct + ch];
+        acc += dx[p * c0 + ch];
       }
   d0[i] = acc;
-}
-
-__global__ __launch_bounds__(kBlock) void k_split_skip(const float* __restrict__ dx, long long nv,
-                                                       int c0, int c1, float* __restrict__ d1) {
-  const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= nv * c1) return;
-  const long long v = i / c1;
-  d1[i] = dx[v * (c0 + c1) + c0 + (i - v * c1)];
 }
 
 __global__ __launch_bounds__(kBlock) void k_to_bf16(const float* __restrict__ in,
@@ -906,14 +902,11 @@ void launch_act_bwd(const float* dy, const uint16_t* y, long long nvox, int n, i
                      nvox / n, c, cz, act, planar, slope, dz);
 }
 
-void launch_split_grad(const float* dx, const Geom& full, int n, int c0, int c1, float* d0,
-                       float* d1, hipStream_t st) {
+void launch_split_half(const float* dx, const Geom& full, int n, int c0, float* d0,
+                       hipStream_t st) {
   const long long hv = static_cast<long long>(full.d0 / 2) * (full.d1 / 2) * (full.d2 / 2);
   hipLaunchKernelGGL(k_split_half, dim3(grid_1d(n * hv * c0)), dim3(kBlock), 0, st, dx, full, n,
-                     c0, c1, d0);
-  const long long nv = static_cast<long long>(n) * full.V;
-  hipLaunchKernelGGL(k_split_skip, dim3(grid_1d(nv * c1)), dim3(kBlock), 0, st, dx, nv, c0, c1,
-                     d1);
+                     c0, d0);
 }
 
 void launch_to_bf16(const float* in, uint16_t* out, long long count, hipStream_t st) {

@@ -699,11 +699,12 @@ const UnetLayer kUnet[8] = {{8, 16, 1, 1},   {16, 32, 2, 1}, {32, 64, 2, 1}, {64
                             {192, 64, 1, 1}, {96, 32, 1, 1}, {48, 16, 1, 1}, {16, 3, 1, 0}};
 
 // Scratch of the network: BF16 activations (forward), then for training the
-// prediction, its gradient, FP32 activation gradients, one BF16 output
-// gradient, one FP32 concatenated-input gradient and one BF16 weight pack.
+// prediction, its gradient, two BF16 output gradients, the FP32 gradient of a
+// concatenated input's upsampled part, one BF16 weight pack and the FP32
+// gradients of the skip outputs.
 struct UnetWs {
   size_t x, e0, e1, e2, e3, d2, d1, d0, fwd;                   // forward part
-  size_t vp, dv, dz, dx, wt, gd0, gd1, gd2, ge3, ge2, ge1, ge0, total;  // training part
+  size_t vp, dv, dz, dz2, dx, wt, ge2, ge1, ge0, total;  // training part
 };
 
 UnetWs unet_ws(int n, int d0, int d1, int d2) {
@@ -728,12 +729,10 @@ UnetWs unet_ws(int n, int d0, int d1, int d2) {
   L.vp = take(V * 3 * f);
   L.dv = take(V * 3 * f);
   L.dz = take(V * 16 * h);
-  L.dx = take(V * 48 * f);
+  L.dz2 = take(V * 16 * h);
+  L.dx = take(V * 32 * f);  // the upsampled part of a concatenated input's gradient
   L.wt = take(static_cast<size_t>(192) * conv_kpad(64, 27) * h);
-  L.gd0 = take(V * 16 * f);
-  L.gd1 = take(V / 8 * 32 * f);
-  L.gd2 = take(V / 64 * 64 * f);
-  L.ge3 = take(V / 512 * 128 * f);
+  // FP32 gradients of the skip outputs, accumulated from two convolutions
   L.ge2 = take(V / 64 * 64 * f);
   L.ge1 = take(V / 8 * 32 * f);
   L.ge0 = take(V * 16 * f);
@@ -842,17 +841,24 @@ void unet_run_backward(const uint16_t* wq, const float* w, const float* b, const
   launch_vec_mse(vp, target, static_cast<long long>(n) * 3 * V, loss, f32(L.dv), st);
   launch_fill_f32(dw, static_cast<long long>(unet_num_weights()), 0.0f, st);
   launch_fill_f32(db, unet_num_biases(), 0.0f, st);
-  // gradient with respect to each layer's output (FP32 channels-last)
-  float* dy[8] = {f32(L.ge0), f32(L.ge1), f32(L.ge2), f32(L.ge3),
-                  f32(L.gd2), f32(L.gd1), f32(L.gd0), f32(L.dv)};
-  uint16_t* dz = b16(L.dz);
+  // FP32 gradients where a layer's output gradient has two sources (the
+  // skip outputs e0, e1, e2) and of the prediction; the others pass to the
+  // next layer fused into BF16 (below)
+  float* dy[8] = {f32(L.ge0), f32(L.ge1), f32(L.ge2), nullptr, nullptr, nullptr, nullptr,
+                  f32(L.dv)};
+  // BF16 output gradients of consecutive layers alternate between two
+  // buffers: the input-gradient convolution of layer l reads layer l's and
+  // writes layer l-1's, the activation adjoint fused into its epilogue
+  uint16_t* dzb[2] = {b16(L.dz), b16(L.dz2)};
   uint16_t* wt = b16(L.wt);
   float* dx = f32(L.dx);
   for (int l = 7; l >= 0; --l) {
     const UnetStep& S = P[l];
     const UnetLayer& U = kUnet[l];
     const int cz = (U.cout + 7) / 8 * 8;
-    launch_act_bwd(dy[l], S.y, S.cg.nvox, n, U.cout, cz, U.act, l == 7, 0.2f, dz, st);
+    uint16_t* dz = dzb[(7 - l) & 1];
+    // the output layer's gradient comes from the loss (planar FP32)
+    if (l == 7) launch_act_bwd(dy[7], S.y, S.cg.nvox, n, U.cout, cz, U.act, 1, 0.2f, dz, st);
     launch_conv_wgrad(dz, cz, S.x0, S.x1, S.cg, dw + S.wo, db + S.bo, st);
     if (l == 0) break;
     // input gradient: a stride-1 convolution of dz (on the dilated grid for
@@ -875,20 +881,25 @@ void unet_run_backward(const uint16_t* wq, const float* w, const float* b, const
     g.kpad = kt;
     g.cout = U.cin;
     g.ycl32 = 1;
+    g.slope = 0.2f;  // of layer l-1's leaky ReLU (every layer before the output's has one)
+    uint16_t* dzn = dzb[(8 - l) & 1];
     const Geom full = make_geom(g.i0, g.i1, g.i2);
     if (S.c1) {  // concatenated input: split into the deeper and the skip tensor
       // layer 4 reads (e3, e2), layer 5 (d2, e1), layer 6 (d1, e0); the
       // epilogue writes the skip channels straight into their gradient and
       // the deeper tensor's channels compactly, whose 2 x 2 x 2 children are
-      // then summed to its half resolution
+      // then summed to its half resolution (layer l-1's output) and passed
+      // through its activation's adjoint
       g.csplit = S.c0;
       g.y32b = dy[6 - l];
       launch_conv3d(dz, nullptr, wt, nullptr, nullptr, dx, g, st);
-      launch_split_half(dx, full, n, S.c0, dy[l - 1], st);
-    } else if (l == 7) {
-      launch_conv3d(dz, nullptr, wt, nullptr, nullptr, dy[6], g, st);
-    } else {  // stride-2 encoder layers: their input already holds the skip part
-      g.accum = 1;
+      launch_split_half_act(dx, full, n, S.c0, P[l - 1].y, 0.2f, dzn, st);
+    } else {
+      // the output layer (its input is d0), or a stride-2 encoder layer,
+      // whose input's gradient already holds the skip part (accumulated)
+      g.accum = l != 7;
+      g.dz16 = dzn;
+      g.acty = P[l - 1].y;
       launch_conv3d(dz, nullptr, wt, nullptr, nullptr, dy[l - 1], g, st);
     }
   }

@@ -174,6 +174,12 @@ struct ConvGeom {
   int ycl32, accum;   // y32 channels-last [nvox][cout] instead of planar; add to y32
   int csplit;         // > 0 (with ycl32): y32 takes channels [0, csplit) as [nvox][csplit]
   float* y32b;        //   and y32b channels [csplit, cout) as [nvox][cout - csplit]
+  // non-null (with ycl32, csplit 0): the adjoint of the next layer's leaky
+  // ReLU fused, dz16 [nvox][cout] = BF16(g * (acty > 0 ? 1 : slope)), g the
+  // value (+ y32 when accum; y32 is then only read), acty that layer's
+  // forward output [nvox][cout]
+  uint16_t* dz16;
+  const uint16_t* acty;
 };
 // Weight row length for cin input channels: ntaps * ceil(cin/8) * 8 rounded up to 32.
 int conv_kpad(int cin, int ntaps);
@@ -204,6 +210,10 @@ void launch_act_bwd(const float* dy, const uint16_t* y, long long nvox, int n, i
 // part directly, ConvGeom::csplit).
 void launch_split_half(const float* dx, const Geom& full, int n, int c0, float* d0,
                        hipStream_t st);
+// The same sum, then the adjoint of the leaky ReLU whose output y [n][V/8][c0]
+// it is: dz [n][V/8][c0] = BF16(sum * (y > 0 ? 1 : slope)).
+void launch_split_half_act(const float* dx, const Geom& full, int n, int c0, const uint16_t* y,
+                           float slope, uint16_t* dz, hipStream_t st);
 // out = BF16(in), count values
 void launch_to_bf16(const float* in, uint16_t* out, long long count, hipStream_t st);
 // loss += sum (p - t)^2 / count (FP64), g = 2 (p - t) / count

@@ -41,6 +41,27 @@ __device__ __forceinline__ uint16_t to_bf16(float f) {
   return static_cast<uint16_t>(u >> 16);
 }
 
+__device__ __forceinline__ float from_bf16(uint16_t h) {
+  return __uint_as_float(static_cast<uint32_t>(h) << 16);
+}
+
+// One channels-last FP32 output element (ConvGeom: split channels, or the
+// next layer's activation adjoint fused into a BF16 output).
+__device__ __forceinline__ void store_cl32(const ConvGeom& cg, float* __restrict__ y32,
+                                           long long mo, int co, float val) {
+  if (cg.dz16) {
+    const long long i = mo * cg.cout + co;
+    float tot = cg.accum ? y32[i] + val : val;
+    if (!(from_bf16(cg.acty[i]) > 0.0f)) tot *= cg.slope;
+    cg.dz16[i] = to_bf16(tot);
+    return;
+  }
+  float* d = cg.csplit == 0 ? y32 + mo * cg.cout + co
+             : co < cg.csplit ? y32 + mo * cg.csplit + co
+                              : cg.y32b + mo * (cg.cout - cg.csplit) + (co - cg.csplit);
+  *d = cg.accum ? *d + val : val;
+}
+
 // X0: how x0 is read (0: full resolution; 1: half resolution, nearest
 // upsampled; 2: half resolution, zero-dilated), fixed per launch.
 template <int NT16, int MT, int X0>
@@ -183,10 +204,7 @@ __global__ __launch_bounds__(CNT) void k_conv3d(const uint16_t* __restrict__ x0,
         if (y16) {
           y16[mo * cg.cout + co] = to_bf16(val);
         } else if (cg.ycl32) {
-          float* d = cg.csplit == 0 ? y32 + mo * cg.cout + co
-                     : co < cg.csplit ? y32 + mo * cg.csplit + co
-                                      : cg.y32b + mo * (cg.cout - cg.csplit) + (co - cg.csplit);
-          *d = cg.accum ? *d + val : val;
+          store_cl32(cg, y32, mo, co, val);
         } else {
           const long long so = mo / ov;
           y32[(so * cg.cout + co) * ov + (mo - so * ov)] = val;
@@ -384,10 +402,7 @@ __global__ __launch_bounds__(CNT) void k_conv3d_lds(const uint16_t* __restrict__
         if (y16) {
           y16[mo * cg.cout + co] = to_bf16(val);
         } else if (cg.ycl32) {
-          float* d = cg.csplit == 0 ? y32 + mo * cg.cout + co
-                     : co < cg.csplit ? y32 + mo * cg.csplit + co
-                                      : cg.y32b + mo * (cg.cout - cg.csplit) + (co - cg.csplit);
-          *d = cg.accum ? *d + val : val;
+          store_cl32(cg, y32, mo, co, val);
         } else {
           y32[(s * cg.cout + co) * per + vo] = val;
         }
@@ -554,10 +569,7 @@ __global__ __launch_bounds__(CNT) void k_conv3d_sub(const uint16_t* __restrict__
         if (y16) {
           y16[mo * cg.cout + co] = to_bf16(val);
         } else if (cg.ycl32) {
-          float* d = cg.csplit == 0 ? y32 + mo * cg.cout + co
-                     : co < cg.csplit ? y32 + mo * cg.csplit + co
-                                      : cg.y32b + mo * (cg.cout - cg.csplit) + (co - cg.csplit);
-          *d = cg.accum ? *d + val : val;
+          store_cl32(cg, y32, mo, co, val);
         } else {
           y32[(s * cg.cout + co) * per + vo] = val;
         }
@@ -581,10 +593,6 @@ __global__ __launch_bounds__(kBlock) void k_pack_pair(const float* __restrict__ 
 }
 
 // ------------------------------------------------------------- training
-
-__device__ __forceinline__ float from_bf16(uint16_t h) {
-  return __uint_as_float(static_cast<uint32_t>(h) << 16);
-}
 
 // dW tiles 16 (co) x 16 NK (k) of one wave over a chunk of output voxels:
 // C[co][k] = sum_v dz[v][co] X(v, k) with the 32 voxels of a K step as the
@@ -815,8 +823,11 @@ __global__ __launch_bounds__(kBlock) void k_act_bwd(const float* __restrict__ dy
   dz[i] = to_bf16(d);
 }
 
+template <bool ACT>
 __global__ __launch_bounds__(kBlock) void k_split_half(const float* __restrict__ dx, Geom full,
-                                                       int n, int c0, float* __restrict__ d0) {
+                                                       int n, int c0, float* __restrict__ d0,
+                                                       const uint16_t* __restrict__ y,
+                                                       float slope, uint16_t* __restrict__ dz) {
   const int h0 = full.d0 / 2, h1 = full.d1 / 2, h2 = full.d2 / 2;
   const long long hv = static_cast<long long>(h0) * h1 * h2;
   const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
@@ -838,7 +849,12 @@ __global__ __launch_bounds__(kBlock) void k_split_half(const float* __restrict__
         const long long p = ((s * full.d0 + 2 * q0 + a) * full.d1 + 2 * q1 + b) * full.d2 + 2 * q2 + e;
         acc += dx[p * c0 + ch];
       }
-  d0[i] = acc;
+  if (ACT) {
+    if (!(from_bf16(y[i]) > 0.0f)) acc *= slope;
+    dz[i] = to_bf16(acc);
+  } else {
+    d0[i] = acc;
+  }
 }
 
 __global__ __launch_bounds__(kBlock) void k_to_bf16(const float* __restrict__ in,
@@ -905,8 +921,15 @@ void launch_act_bwd(const float* dy, const uint16_t* y, long long nvox, int n, i
 void launch_split_half(const float* dx, const Geom& full, int n, int c0, float* d0,
                        hipStream_t st) {
   const long long hv = static_cast<long long>(full.d0 / 2) * (full.d1 / 2) * (full.d2 / 2);
-  hipLaunchKernelGGL(k_split_half, dim3(grid_1d(n * hv * c0)), dim3(kBlock), 0, st, dx, full, n,
-                     c0, d0);
+  hipLaunchKernelGGL(k_split_half<false>, dim3(grid_1d(n * hv * c0)), dim3(kBlock), 0, st, dx,
+                     full, n, c0, d0, nullptr, 0.0f, nullptr);
+}
+
+void launch_split_half_act(const float* dx, const Geom& full, int n, int c0, const uint16_t* y,
+                           float slope, uint16_t* dz, hipStream_t st) {
+  const long long hv = static_cast<long long>(full.d0 / 2) * (full.d1 / 2) * (full.d2 / 2);
+  hipLaunchKernelGGL(k_split_half<true>, dim3(grid_1d(n * hv * c0)), dim3(kBlock), 0, st, dx,
+                     full, n, c0, nullptr, y, slope, dz);
 }
 
 void launch_to_bf16(const float* in, uint16_t* out, long long count, hipStream_t st) {

@@ -789,6 +789,147 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(int wch, const uint16_t* __re
   }
 }
 
+// Weight gradients of a 27-tap layer, all taps of one input channel group at
+// once: a wave takes a co tile of 16, one group of 8 input channels and a
+// run of K steps, a K step being a row segment of 32 output voxels along d2.
+// The input positions that the 27 taps read for the segment (3 x 3 rows of
+// NXP positions, 8 channels each) are staged in LDS once per step; each of
+// the 14 column tiles (taps 2t and 2t + 1, 8 channels each) then reads its B
+// fragment there through the transposing LDS read, lane j of a 16-lane group
+// pointing at the 4 channels 4 (j % 4).. of tile column group j % 4 at voxel
+// base + j / 4.  A step stages about 10 (stride 1) or 18 (stride 2) input
+// positions per output voxel where the tap-by-tap kernel above loads 27.
+template <int X0, int STRIDE>
+__global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
+                                                        const uint16_t* __restrict__ dz, int cz,
+                                                        const uint16_t* __restrict__ x0,
+                                                        const uint16_t* __restrict__ x1,
+                                                        ConvGeom cg, float* __restrict__ dw,
+                                                        float* __restrict__ db) {
+  constexpr int NXP = 31 * STRIDE + 3;  // input positions along d2 for 32 outputs
+  constexpr int NPOS = 9 * NXP;
+  constexpr int NLD = (NPOS + 63) / 64;  // staged positions per lane
+  constexpr int NTT = 14;                // column tiles: 27 taps (and one empty) x 8 channels
+  __shared__ __align__(16) uint16_t xs[NPOS * 8];  // [position][8 channels]
+  __shared__ __align__(16) uint16_t at[32 * 16];   // dz: [voxel][co]
+  const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
+  const int vl = lane & 31, h = lane >> 5;  // staged voxel of dz, channel half
+  const int co0 = blockIdx.z * 16;
+  const int grp = blockIdx.y;  // input channels 8 grp .. 8 grp + 7
+  const int cin = cg.c0 + cg.c1;
+  const bool from0 = grp * 8 < cg.c0;
+  const uint16_t* src = from0 ? x0 : x1;
+  const int cstr = from0 ? cg.c0 : cg.c1;  // channels per voxel of that tensor
+  const int coff = from0 ? grp * 8 : grp * 8 - cg.c0;
+  const bool half = X0 == 1 && from0;  // x0 at half resolution, nearest upsampled
+  const int hi0 = half ? cg.i0 / 2 : cg.i0, hi1 = half ? cg.i1 / 2 : cg.i1;
+  const int hi2 = half ? cg.i2 / 2 : cg.i2;
+  const long long vin = static_cast<long long>(hi0) * hi1 * hi2;
+  // per lane: the B row (position, channel half) of each column tile, as an
+  // LDS element offset from its voxel's first position
+  int toff[NTT];
+#pragma unroll
+  for (int t = 0; t < NTT; ++t) {
+    const int tap = min(2 * t + ((r & 3) >> 1), 26);  // tap 27 (empty columns): any valid row
+    toff[t] = (((tap / 9) * 3 + (tap / 3) % 3) * NXP + tap % 3) * 8 + (r & 1) * 4;
+  }
+  const int vrow = (8 * g + (r >> 2)) * STRIDE * 8;  // voxel 8 g + j / 4 of the segment
+  const int nseg = (cg.o2 + 31) / 32;
+  const long long nsteps = static_cast<long long>(cg.nvox / cg.o2) * nseg;
+  f32x4 acc[NTT];
+#pragma unroll
+  for (int t = 0; t < NTT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  const bool bias = db != nullptr && grp == 0;
+  float bacc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  const long long s0 = static_cast<long long>(blockIdx.x) * wsteps;
+  const long long s1 = min(s0 + wsteps, nsteps);
+  for (long long step = s0; step < s1; ++step) {
+    const long long row = step / nseg;
+    const int x0v = static_cast<int>(step - row * nseg) * 32;
+    const int oy = static_cast<int>(row % cg.o1);
+    const long long rz = row / cg.o1;
+    const int oz = static_cast<int>(rz % cg.o0);
+    const int s = static_cast<int>(rz / cg.o0);
+    // dz of the segment's 32 voxels (zero past the row end)
+    {
+      const bool ok = x0v + vl < cg.o2 && co0 + 8 * h < cz;
+      const long long v = row * cg.o2 + x0v + vl;
+      uint4 a = *reinterpret_cast<const uint4*>(ok ? dz + v * cz + co0 + 8 * h : dz);
+      if (!ok) a = make_uint4(0u, 0u, 0u, 0u);
+      *reinterpret_cast<uint4*>(&at[vl * 16 + 8 * h]) = a;
+      if (bias) {
+        const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          bacc[2 * j] += __uint_as_float(aw[j] << 16);
+          bacc[2 * j + 1] += __uint_as_float(aw[j] & 0xFFFF0000u);
+        }
+      }
+    }
+    // the input positions every tap reads (zero padding outside the volume)
+    const int qz = oz * STRIDE - 1, qy = oy * STRIDE - 1, qx = x0v * STRIDE - 1;
+    const uint16_t* base = src + static_cast<long long>(s) * vin * cstr + coff;
+    uint4 xv[NLD];
+    bool xin[NLD];
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int i = lane + 64 * k;
+      const int a = i / (3 * NXP), b = (i / NXP) % 3, xi = i % NXP;
+      const int pz = qz + a, py = qy + b, px = qx + xi;
+      xin[k] = i < NPOS && static_cast<unsigned>(pz) < static_cast<unsigned>(cg.i0) &&
+               static_cast<unsigned>(py) < static_cast<unsigned>(cg.i1) &&
+               static_cast<unsigned>(px) < static_cast<unsigned>(cg.i2);
+      const long long pv = half ? (static_cast<long long>(pz >> 1) * hi1 + (py >> 1)) * hi2 + (px >> 1)
+                                : (static_cast<long long>(pz) * hi1 + py) * hi2 + px;
+      xv[k] = *reinterpret_cast<const uint4*>(xin[k] ? base + pv * cstr : x0);
+    }
+#pragma unroll
+    for (int k = 0; k < NLD; ++k) {
+      const int i = lane + 64 * k;
+      if (i < NPOS)
+        *reinterpret_cast<uint4*>(&xs[i * 8]) =
+            xin[k] ? xv[k] : make_uint4(0u, 0u, 0u, 0u);
+    }
+    // one wave: its LDS operations complete in order
+    const bf16x8 afrag = tr_frag(at, g, r);
+    typedef __attribute__((address_space(3))) v4i16* lds_v4;
+#pragma unroll
+    for (int t = 0; t < NTT; ++t) {
+      const uint16_t* p = xs + vrow + toff[t];
+      const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4)(p));
+      const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4)(p + 4 * STRIDE * 8));
+      const bf16x8 bfrag =
+          __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, acc[t], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < NTT; ++t) {
+    const int tap = 2 * t + (r >> 3);
+    if (tap > 26) continue;
+    const int kcol = tap * cin + grp * 8 + (r & 7);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = co0 + 4 * g + i;
+      if (co < cg.cout) atomicAdd(dw + static_cast<long long>(co) * cg.kpad + kcol, acc[t][i]);
+    }
+  }
+  if (bias) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+#pragma unroll
+      for (int m = 16; m >= 1; m >>= 1) bacc[j] += __shfl_xor(bacc[j], m, 64);
+    }
+    if (vl == 0) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int co = co0 + 8 * h + j;
+        if (co < cg.cout) atomicAdd(db + co, bacc[j]);
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_pack_wt(const float* __restrict__ w, int cin, int cout,
                                                     int cz, int kpad_f, int kpad_t,
                                                     uint16_t* __restrict__ wt) {
@@ -893,6 +1034,28 @@ void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uin
   // voxels per wave: doubled from 1024 up to 4096 while at least 2048
   // waves (two per SIMD) remain (measured on the warm-start network at
   // 96 x 112 x 96: longer chunks starve the low-resolution layers)
+  if (cg.ntaps == 27 && cg.stride == 1 && !cg.dil0 && cg.c0 + cg.c1 >= 48) {
+    // all taps of a channel group per wave (measured faster on the layers
+    // with six or more channel groups and full-resolution rows: 0.68-0.89x
+    // the tap-by-tap kernel's time on the decoder layers of the warm-start
+    // network, 1.2-3x on its encoder and output layers); K steps (32-voxel
+    // row segments) per wave doubled from 8 up to 128 while at least 2048
+    // waves remain
+    const uint32_t ngrp = static_cast<uint32_t>((cg.c0 + cg.c1) / 8);
+    const long long nsteps = cg.nvox / cg.o2 * ((cg.o2 + 31) / 32);
+    long long ws = 8;
+    while (ws < 128 && (nsteps + 2 * ws - 1) / (2 * ws) * ngrp * gz >= 2048) ws *= 2;
+    const dim3 grid(static_cast<uint32_t>((nsteps + ws - 1) / ws), ngrp, gz);
+    const int w = static_cast<int>(ws);
+    if (cg.up0)
+      hipLaunchKernelGGL((k_conv_wgrad_rows<1, 1>), grid, dim3(64), 0, st, w, dz, cz, x0, x1, cg, dw,
+                         db);
+    else
+      hipLaunchKernelGGL((k_conv_wgrad_rows<0, 1>), grid, dim3(64), 0, st, w, dz, cz, x0, x1, cg, dw,
+                         db);
+    prof_end(st, KC_MISC);
+    return;
+  }
   long long wch = 1024;
   while (wch < 4096 && (cg.nvox + 2 * wch - 1) / (2 * wch) * gy * gz >= 2048) wch *= 2;
   const dim3 grid(static_cast<uint32_t>((cg.nvox + wch - 1) / wch), gy, gz);

@@ -843,39 +843,28 @@ __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
   float bacc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   const long long s0 = static_cast<long long>(blockIdx.x) * wsteps;
   const long long s1 = min(s0 + wsteps, nsteps);
-  for (long long step = s0; step < s1; ++step) {
-    const long long row = step / nseg;
-    const int x0v = static_cast<int>(step - row * nseg) * 32;
+  // The loads of one K step (every load issued, from dz or x0 itself where
+  // the value is zero; the padding is applied when staged).  A step's loads
+  // are issued before the previous step's products; past the run the last
+  // step is loaded again and never staged.
+  auto issue = [&](long long step, uint4& a, bool& aok, uint4 (&xv)[NLD], bool (&xin)[NLD]) {
+    const long long st = min(step, s1 - 1);
+    const long long row = st / nseg;
+    const int x0v = static_cast<int>(st - row * nseg) * 32;
     const int oy = static_cast<int>(row % cg.o1);
     const long long rz = row / cg.o1;
     const int oz = static_cast<int>(rz % cg.o0);
     const int s = static_cast<int>(rz / cg.o0);
-    // dz of the segment's 32 voxels (zero past the row end)
-    {
-      const bool ok = x0v + vl < cg.o2 && co0 + 8 * h < cz;
-      const long long v = row * cg.o2 + x0v + vl;
-      uint4 a = *reinterpret_cast<const uint4*>(ok ? dz + v * cz + co0 + 8 * h : dz);
-      if (!ok) a = make_uint4(0u, 0u, 0u, 0u);
-      *reinterpret_cast<uint4*>(&at[vl * 16 + 8 * h]) = a;
-      if (bias) {
-        const uint32_t aw[4] = {a.x, a.y, a.z, a.w};
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          bacc[2 * j] += __uint_as_float(aw[j] << 16);
-          bacc[2 * j + 1] += __uint_as_float(aw[j] & 0xFFFF0000u);
-        }
-      }
-    }
-    // the input positions every tap reads (zero padding outside the volume)
+    aok = x0v + vl < cg.o2 && co0 + 8 * h < cz;
+    a = *reinterpret_cast<const uint4*>(aok ? dz + (row * cg.o2 + x0v + vl) * cz + co0 + 8 * h
+                                            : dz);
     const int qz = oz * STRIDE - 1, qy = oy * STRIDE - 1, qx = x0v * STRIDE - 1;
     const uint16_t* base = src + static_cast<long long>(s) * vin * cstr + coff;
-    uint4 xv[NLD];
-    bool xin[NLD];
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
       const int i = lane + 64 * k;
-      const int a = i / (3 * NXP), b = (i / NXP) % 3, xi = i % NXP;
-      const int pz = qz + a, py = qy + b, px = qx + xi;
+      const int pa = i / (3 * NXP), pb = (i / NXP) % 3, xi = i % NXP;
+      const int pz = qz + pa, py = qy + pb, px = qx + xi;
       xin[k] = i < NPOS && static_cast<unsigned>(pz) < static_cast<unsigned>(cg.i0) &&
                static_cast<unsigned>(py) < static_cast<unsigned>(cg.i1) &&
                static_cast<unsigned>(px) < static_cast<unsigned>(cg.i2);
@@ -883,13 +872,32 @@ __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
                                 : (static_cast<long long>(pz) * hi1 + py) * hi2 + px;
       xv[k] = *reinterpret_cast<const uint4*>(xin[k] ? base + pv * cstr : x0);
     }
+  };
+  auto keep = [](uint4 q, bool kp) {
+    return make_uint4(kp ? q.x : 0u, kp ? q.y : 0u, kp ? q.z : 0u, kp ? q.w : 0u);
+  };
+  uint4 ca, na, cx[NLD], nx[NLD];
+  bool caok, naok, cxin[NLD], nxin[NLD];
+  if (s0 < s1) issue(s0, ca, caok, cx, cxin);
+  for (long long step = s0; step < s1; ++step) {
+    // stage dz of the segment's 32 voxels (zero past the row end) and the
+    // input positions every tap reads (zero padding outside the volume)
+    ca = keep(ca, caok);
+    *reinterpret_cast<uint4*>(&at[vl * 16 + 8 * h]) = ca;
+    if (bias) {
+      const uint32_t aw[4] = {ca.x, ca.y, ca.z, ca.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        bacc[2 * j] += __uint_as_float(aw[j] << 16);
+        bacc[2 * j + 1] += __uint_as_float(aw[j] & 0xFFFF0000u);
+      }
+    }
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
       const int i = lane + 64 * k;
-      if (i < NPOS)
-        *reinterpret_cast<uint4*>(&xs[i * 8]) =
-            xin[k] ? xv[k] : make_uint4(0u, 0u, 0u, 0u);
+      if (i < NPOS) *reinterpret_cast<uint4*>(&xs[i * 8]) = keep(cx[k], cxin[k]);
     }
+    issue(step + 1, na, naok, nx, nxin);
     // one wave: its LDS operations complete in order
     const bf16x8 afrag = tr_frag(at, g, r);
     typedef __attribute__((address_space(3))) v4i16* lds_v4;
@@ -901,6 +909,13 @@ __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
       const bf16x8 bfrag =
           __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, acc[t], 0, 0, 0);
+    }
+    ca = na;
+    caok = naok;
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      cx[q] = nx[q];
+      cxin[q] = nxin[q];
     }
   }
 #pragma unroll

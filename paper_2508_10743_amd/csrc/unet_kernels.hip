@@ -814,9 +814,17 @@ __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
   __shared__ __align__(16) uint16_t at[32 * 16];   // dz: [voxel][co]
   const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
   const int vl = lane & 31, h = lane >> 5;  // staged voxel of dz, channel half
-  const int co0 = blockIdx.z * 16;
-  const int grp = blockIdx.y;  // input channels 8 grp .. 8 grp + 7
+  // The waves of one run of K steps (every channel group and co tile) are
+  // consecutive on one XCD, so that its dz and input rows are read there
+  // from L2 after the first of them.
   const int cin = cg.c0 + cg.c1;
+  const uint32_t wid = xcd_remap(blockIdx.x, gridDim.x);
+  const int ngrp = cin / 8;
+  const int grp = static_cast<int>(wid % ngrp);  // input channels 8 grp .. 8 grp + 7
+  const uint32_t wrest = wid / ngrp;
+  const int ntz = (cg.cout + 15) / 16;
+  const int co0 = static_cast<int>(wrest % ntz) * 16;
+  const uint32_t chunk = wrest / ntz;
   const bool from0 = grp * 8 < cg.c0;
   const uint16_t* src = from0 ? x0 : x1;
   const int cstr = from0 ? cg.c0 : cg.c1;  // channels per voxel of that tensor
@@ -841,25 +849,41 @@ __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
   for (int t = 0; t < NTT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   const bool bias = db != nullptr && grp == 0;
   float bacc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
-  const long long s0 = static_cast<long long>(blockIdx.x) * wsteps;
+  const long long s0 = static_cast<long long>(chunk) * wsteps;
   const long long s1 = min(s0 + wsteps, nsteps);
-  // The loads of one K step (every load issued, from dz or x0 itself where
-  // the value is zero; the padding is applied when staged).  A step's loads
-  // are issued before the previous step's products; past the run the last
-  // step is loaded again and never staged.
-  auto issue = [&](long long step, uint4& a, bool& aok, uint4 (&xv)[NLD], bool (&xin)[NLD]) {
-    const long long st = min(step, s1 - 1);
-    const long long row = st / nseg;
-    const int x0v = static_cast<int>(st - row * nseg) * 32;
-    const int oy = static_cast<int>(row % cg.o1);
-    const long long rz = row / cg.o1;
-    const int oz = static_cast<int>(rz % cg.o0);
-    const int s = static_cast<int>(rz / cg.o0);
+  // The loads of one K step (every load issued, from dz or the subject's
+  // first input voxel where the value is zero; the padding is applied when
+  // staged).  A step's loads are issued before the previous step's
+  // products; past the run the last step is loaded again and never staged.
+  // The step's row (subject sj, output voxel oz, oy) and segment are kept as
+  // counters (wave-uniform, advanced once per step: no division in the
+  // loop), and the per-lane offsets are 32-bit (the launch checks that every
+  // input tensor's subject holds fewer than 2^31 elements).
+  long long row = s0 / nseg;
+  int seg = static_cast<int>(s0 - row * nseg);
+  int oy = static_cast<int>(row % cg.o1);
+  int oz = static_cast<int>((row / cg.o1) % cg.o0);
+  int sj = static_cast<int>(row / cg.o1 / cg.o0);
+  auto advance = [&]() {
+    if (++seg == nseg) {
+      seg = 0;
+      ++row;
+      if (++oy == cg.o1) {
+        oy = 0;
+        if (++oz == cg.o0) {
+          oz = 0;
+          ++sj;
+        }
+      }
+    }
+  };
+  auto issue = [&](uint4& a, bool& aok, uint4 (&xv)[NLD], bool (&xin)[NLD]) {
+    const int x0v = seg * 32;
     aok = x0v + vl < cg.o2 && co0 + 8 * h < cz;
-    a = *reinterpret_cast<const uint4*>(aok ? dz + (row * cg.o2 + x0v + vl) * cz + co0 + 8 * h
-                                            : dz);
+    const uint16_t* drow = dz + row * cg.o2 * cz;
+    a = *reinterpret_cast<const uint4*>(drow + (aok ? (x0v + vl) * cz + co0 + 8 * h : 0));
     const int qz = oz * STRIDE - 1, qy = oy * STRIDE - 1, qx = x0v * STRIDE - 1;
-    const uint16_t* base = src + static_cast<long long>(s) * vin * cstr + coff;
+    const uint16_t* base = src + static_cast<long long>(sj) * vin * cstr + coff;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
       const int i = lane + 64 * k;
@@ -868,9 +892,8 @@ __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
       xin[k] = i < NPOS && static_cast<unsigned>(pz) < static_cast<unsigned>(cg.i0) &&
                static_cast<unsigned>(py) < static_cast<unsigned>(cg.i1) &&
                static_cast<unsigned>(px) < static_cast<unsigned>(cg.i2);
-      const long long pv = half ? (static_cast<long long>(pz >> 1) * hi1 + (py >> 1)) * hi2 + (px >> 1)
-                                : (static_cast<long long>(pz) * hi1 + py) * hi2 + px;
-      xv[k] = *reinterpret_cast<const uint4*>(xin[k] ? base + pv * cstr : x0);
+      const int pv = half ? ((pz >> 1) * hi1 + (py >> 1)) * hi2 + (px >> 1) : (pz * hi1 + py) * hi2 + px;
+      xv[k] = *reinterpret_cast<const uint4*>(base + static_cast<uint32_t>(xin[k] ? pv * cstr : 0));
     }
   };
   auto keep = [](uint4 q, bool kp) {
@@ -878,7 +901,7 @@ __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
   };
   uint4 ca, na, cx[NLD], nx[NLD];
   bool caok, naok, cxin[NLD], nxin[NLD];
-  if (s0 < s1) issue(s0, ca, caok, cx, cxin);
+  if (s0 < s1) issue(ca, caok, cx, cxin);
   for (long long step = s0; step < s1; ++step) {
     // stage dz of the segment's 32 voxels (zero past the row end) and the
     // input positions every tap reads (zero padding outside the volume)
@@ -897,7 +920,8 @@ __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
       const int i = lane + 64 * k;
       if (i < NPOS) *reinterpret_cast<uint4*>(&xs[i * 8]) = keep(cx[k], cxin[k]);
     }
-    issue(step + 1, na, naok, nx, nxin);
+    if (step + 1 < s1) advance();
+    issue(na, naok, nx, nxin);
     // one wave: its LDS operations complete in order
     const bf16x8 afrag = tr_frag(at, g, r);
     typedef __attribute__((address_space(3))) v4i16* lds_v4;
@@ -1049,7 +1073,9 @@ void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uin
   // voxels per wave: doubled from 1024 up to 4096 while at least 2048
   // waves (two per SIMD) remain (measured on the warm-start network at
   // 96 x 112 x 96: longer chunks starve the low-resolution layers)
-  if (cg.ntaps == 27 && cg.stride == 1 && !cg.dil0 && cg.c0 + cg.c1 >= 48) {
+  const long long vfull = static_cast<long long>(cg.i0) * cg.i1 * cg.i2;
+  if (cg.ntaps == 27 && cg.stride == 1 && !cg.dil0 && cg.c0 + cg.c1 >= 48 &&
+      vfull * std::max(cg.c0, cg.c1) < (1LL << 31)) {
     // all taps of a channel group per wave (measured faster on the layers
     // with six or more channel groups and full-resolution rows: 0.68-0.89x
     // the tap-by-tap kernel's time on the decoder layers of the warm-start
@@ -1060,7 +1086,7 @@ void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uin
     const long long nsteps = cg.nvox / cg.o2 * ((cg.o2 + 31) / 32);
     long long ws = 8;
     while (ws < 128 && (nsteps + 2 * ws - 1) / (2 * ws) * ngrp * gz >= 2048) ws *= 2;
-    const dim3 grid(static_cast<uint32_t>((nsteps + ws - 1) / ws), ngrp, gz);
+    const dim3 grid(static_cast<uint32_t>((nsteps + ws - 1) / ws * ngrp * gz));
     const int w = static_cast<int>(ws);
     if (cg.up0)
       hipLaunchKernelGGL((k_conv_wgrad_rows<1, 1>), grid, dim3(64), 0, st, w, dz, cz, x0, x1, cg, dw,

@@ -631,8 +631,16 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(int wch, const uint16_t* __re
   const int lane = threadIdx.x, r = lane & 15, g = lane >> 4;
   const int vl = lane & 31, h = lane >> 5;  // staged voxel, channel half
   const int cvec = (cg.c0 + cg.c1) >> 3;
-  const int co0 = blockIdx.z * 16;
-  const int kb = blockIdx.y * 16 * WNK;  // first k column of the wave
+  // the waves of one voxel chunk (every k group and co tile) are
+  // consecutive on one XCD, so that its dz and input rows are read there
+  // from L2 after the first of them
+  const uint32_t ngk = (cg.kpad + 16 * WNK - 1) / (16 * WNK);
+  const uint32_t wid = xcd_remap(blockIdx.x, gridDim.x);
+  const uint32_t kgrp = wid % ngk, wrest = wid / ngk;
+  const uint32_t ntz = (cg.cout + 15) / 16;
+  const int co0 = static_cast<int>(wrest % ntz) * 16;
+  const uint32_t chunk = wrest / ntz;
+  const int kb = static_cast<int>(kgrp) * 16 * WNK;  // first k column of the wave
   const int h0 = half ? cg.i0 / 2 : cg.i0, h1 = half ? cg.i1 / 2 : cg.i1;
   const int h2 = half ? cg.i2 / 2 : cg.i2;
   const long long vin0 = static_cast<long long>(h0) * h1 * h2;
@@ -657,7 +665,7 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(int wch, const uint16_t* __re
     gto[t] = (gta[t] * cg.i1 + gtb[t]) * cg.i2 + gtc[t];
   }
   // coordinates of the staged voxel, advanced by 32 voxels per K step
-  const long long vstart = static_cast<long long>(blockIdx.x) * wch + vl;
+  const long long vstart = static_cast<long long>(chunk) * wch + vl;
   const long long ov = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
   int s = 0, o0 = 0, o1 = 0, o2 = 0;
   if (vstart < cg.nvox) {
@@ -672,14 +680,14 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(int wch, const uint16_t* __re
 #pragma unroll
   for (int t = 0; t < WNK; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   // the bias gradient sum_v dz[v][co], from the staged dz of the first k tile
-  const bool bias = db != nullptr && blockIdx.y == 0;
+  const bool bias = db != nullptr && kgrp == 0;
   float bacc[8] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
   // The loads of one K step (every load issued, from x0 or dz itself where
   // the value is zero; the padding is applied when staged), then the staged
   // voxel's coordinates advanced by 32.  A step's loads are issued before
   // the previous step's products, so they arrive while those run.
   auto issue = [&](int step, uint4& araw, bool& ain, uint4 (&braw)[WNK], bool (&bin)[WNK]) {
-    const long long v = static_cast<long long>(blockIdx.x) * wch + step + vl;
+    const long long v = static_cast<long long>(chunk) * wch + step + vl;
     const bool live = v < cg.nvox;
     ain = live && co0 + 8 * h < cz;
     araw = *reinterpret_cast<const uint4*>(ain ? dz + v * cz + co0 + 8 * h : dz);
@@ -724,7 +732,7 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(int wch, const uint16_t* __re
   bool cain, cbin[WNK], nain, nbin[WNK];
   issue(0, ca, cain, cb, cbin);
   for (int step = 0; step < wch; step += 32) {
-    const long long vb = static_cast<long long>(blockIdx.x) * wch + step;
+    const long long vb = static_cast<long long>(chunk) * wch + step;
     if (vb >= cg.nvox) break;  // uniform across the wave
     // zero padding by selects (a branch would wait for every load in flight)
     auto keep = [](uint4 q, bool k) {
@@ -1076,12 +1084,12 @@ void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uin
   const long long vfull = static_cast<long long>(cg.i0) * cg.i1 * cg.i2;
   if (cg.ntaps == 27 && cg.stride == 1 && !cg.dil0 && cg.c0 + cg.c1 >= 48 &&
       vfull * std::max(cg.c0, cg.c1) < (1LL << 31)) {
-    // all taps of a channel group per wave (measured faster on the layers
-    // with six or more channel groups and full-resolution rows: 0.68-0.89x
-    // the tap-by-tap kernel's time on the decoder layers of the warm-start
-    // network, 1.2-3x on its encoder and output layers); K steps (32-voxel
-    // row segments) per wave doubled from 8 up to 128 while at least 2048
-    // waves remain
+    // all taps of a channel group per wave (measured on the warm-start
+    // network at 96 x 112 x 96: faster than the tap-by-tap kernel on its
+    // decoder layers, six or more channel groups; as fast on its output
+    // layer, two groups; slower on its first layer, one group of 8 channels
+    // of which two are used); K steps (32-voxel row segments) per wave
+    // doubled from 8 up to 128 while at least 2048 waves remain
     const uint32_t ngrp = static_cast<uint32_t>((cg.c0 + cg.c1) / 8);
     const long long nsteps = cg.nvox / cg.o2 * ((cg.o2 + 31) / 32);
     long long ws = 8;
@@ -1099,7 +1107,7 @@ void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uin
   }
   long long wch = 1024;
   while (wch < 4096 && (cg.nvox + 2 * wch - 1) / (2 * wch) * gy * gz >= 2048) wch *= 2;
-  const dim3 grid(static_cast<uint32_t>((cg.nvox + wch - 1) / wch), gy, gz);
+  const dim3 grid(static_cast<uint32_t>((cg.nvox + wch - 1) / wch * gy * gz));
   const int w = static_cast<int>(wch);
   if (cg.dil0)
     hipLaunchKernelGGL((k_conv_wgrad<2>), grid, dim3(64), 0, st, w, dz, cz, x0, x1, cg, dw, db);

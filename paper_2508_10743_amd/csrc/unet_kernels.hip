@@ -1245,10 +1245,16 @@ void launch_conv3d(const uint16_t* x0, const uint16_t* x1, const uint16_t* w, co
     const int nbx = (cg.o2 + LBX - 1) / LBX;
     const long long per = static_cast<long long>(cg.o0) * cg.o1 * cg.o2;
     const uint32_t gx = static_cast<uint32_t>(static_cast<long long>(nbz) * nby * nbx * (cg.nvox / per));
+    // column tiles per wave: 48 channels where they divide cout and 64 do
+    // not (the input gradients of concatenated layers: 48, 96), so that no
+    // tile is computed for channels past cout
     if (cg.cout <= 16)
       conv3d_lds_cg<1>(mode, dim3(gx, 1), x0, x1, w, bias, y16, y32, cg, nbz, nby, nbx, st);
     else if (cg.cout <= 32)
       conv3d_lds_cg<2>(mode, dim3(gx, 1), x0, x1, w, bias, y16, y32, cg, nbz, nby, nbx, st);
+    else if (cg.cout % 64 != 0 && cg.cout % 48 == 0)
+      conv3d_lds_cg<3>(mode, dim3(gx, static_cast<uint32_t>(cg.cout / 48)), x0, x1, w, bias, y16,
+                       y32, cg, nbz, nby, nbx, st);
     else
       conv3d_lds_cg<4>(mode, dim3(gx, static_cast<uint32_t>((cg.cout + 63) / 64)), x0, x1, w,
                        bias, y16, y32, cg, nbz, nby, nbx, st);

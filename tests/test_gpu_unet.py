@@ -77,9 +77,11 @@ def test_pointwise_conv_is_a_gemm(dev):
     (16, 32, 1, (6, 7, 9)), (16, 32, 2, (8, 6, 10)), (64, 128, 2, (6, 8, 6)),
     (8, 16, 1, (5, 9, 7)), (48, 16, 1, (4, 6, 8)),
     # several LDS input bricks (4 x 4 x 16 outputs) along every axis, each
-    # with a ragged last one; 96 output channels leave the second column
-    # block of 64 half empty
-    (48, 16, 1, (9, 10, 35)), (32, 96, 1, (5, 13, 18)), (8, 16, 1, (12, 9, 33))])
+    # with a ragged last one; 96 and 48 output channels take column blocks
+    # of 48 (the second with two chunked channel groups, the third with an
+    # odd number of input channel groups)
+    (48, 16, 1, (9, 10, 35)), (32, 96, 1, (5, 13, 18)), (8, 16, 1, (12, 9, 33)),
+    (24, 48, 1, (5, 6, 18))])
 def test_conv3d_bf16_out(dev, cin, cout, stride, dims):
     rng = np.random.default_rng(501 + cin + stride)
     x = rand_bf16(rng, (2, cin) + dims)

@@ -699,12 +699,11 @@ const UnetLayer kUnet[8] = {{8, 16, 1, 1},   {16, 32, 2, 1}, {32, 64, 2, 1}, {64
                             {192, 64, 1, 1}, {96, 32, 1, 1}, {48, 16, 1, 1}, {16, 3, 1, 0}};
 
 // Scratch of the network: BF16 activations (forward), then for training the
-// prediction, its gradient, two BF16 output gradients, the FP32 gradient of a
-// concatenated input's upsampled part, one BF16 weight pack and the FP32
-// gradients of the skip outputs.
+// prediction, its gradient, two BF16 output gradients, one BF16 weight pack
+// and the FP32 gradients of the skip outputs.
 struct UnetWs {
   size_t x, e0, e1, e2, e3, d2, d1, d0, fwd;                   // forward part
-  size_t vp, dv, dz, dz2, dx, wt, ge2, ge1, ge0, total;  // training part
+  size_t vp, dv, dz, dz2, wt, ge2, ge1, ge0, total;  // training part
 };
 
 UnetWs unet_ws(int n, int d0, int d1, int d2) {
@@ -730,7 +729,6 @@ UnetWs unet_ws(int n, int d0, int d1, int d2) {
   L.dv = take(V * 3 * f);
   L.dz = take(V * 16 * h);
   L.dz2 = take(V * 16 * h);
-  L.dx = take(V * 32 * f);  // the upsampled part of a concatenated input's gradient
   L.wt = take(static_cast<size_t>(192) * conv_kpad(64, 27) * h);
   // FP32 gradients of the skip outputs, accumulated from two convolutions
   L.ge2 = take(V / 64 * 64 * f);
@@ -851,7 +849,6 @@ void unet_run_backward(const uint16_t* wq, const float* w, const float* b, const
   // writes layer l-1's, the activation adjoint fused into its epilogue
   uint16_t* dzb[2] = {b16(L.dz), b16(L.dz2)};
   uint16_t* wt = b16(L.wt);
-  float* dx = f32(L.dx);
   for (int l = 7; l >= 0; --l) {
     const UnetStep& S = P[l];
     const UnetLayer& U = kUnet[l];
@@ -883,17 +880,18 @@ void unet_run_backward(const uint16_t* wq, const float* w, const float* b, const
     g.ycl32 = 1;
     g.slope = 0.2f;  // of layer l-1's leaky ReLU (every layer before the output's has one)
     uint16_t* dzn = dzb[(8 - l) & 1];
-    const Geom full = make_geom(g.i0, g.i1, g.i2);
     if (S.c1) {  // concatenated input: split into the deeper and the skip tensor
       // layer 4 reads (e3, e2), layer 5 (d2, e1), layer 6 (d1, e0); the
       // epilogue writes the skip channels straight into their gradient and
-      // the deeper tensor's channels compactly, whose 2 x 2 x 2 children are
-      // then summed to its half resolution (layer l-1's output) and passed
-      // through its activation's adjoint
+      // sums the deeper tensor's channels over the 2 x 2 x 2 children of
+      // each voxel of its half resolution (layer l-1's output), passed
+      // through that layer's activation adjoint
       g.csplit = S.c0;
       g.y32b = dy[6 - l];
-      launch_conv3d(dz, nullptr, wt, nullptr, nullptr, dx, g, st);
-      launch_split_half_act(dx, full, n, S.c0, P[l - 1].y, 0.2f, dzn, st);
+      g.hpool = 1;
+      g.dz16 = dzn;
+      g.acty = P[l - 1].y;
+      launch_conv3d(dz, nullptr, wt, nullptr, nullptr, nullptr, g, st);
     } else {
       // the output layer (its input is d0), or a stride-2 encoder layer,
       // whose input's gradient already holds the skip part (accumulated)

@@ -180,6 +180,13 @@ struct ConvGeom {
   // forward output [nvox][cout]
   uint16_t* dz16;
   const uint16_t* acty;
+  // non-zero (with csplit, stride 1, 27 taps, even output dims; LDS-staged
+  // kernel only): channels [0, csplit) are summed over the 2 x 2 x 2
+  // children of each half-resolution voxel and written with the adjoint
+  // fused, dz16 [n][o/2][csplit] = BF16(sum * (acty > 0 ? 1 : slope)), acty
+  // [n][o/2][csplit] (the adjoint of nearest upsampling, then of the leaky
+  // ReLU that made the half-resolution tensor); y32 is then unused
+  int hpool;
 };
 // Weight row length for cin input channels: ntaps * ceil(cin/8) * 8 rounded up to 32.
 int conv_kpad(int cin, int ntaps);
@@ -205,15 +212,6 @@ void launch_pack_wt(const float* w, int cin, int cout, int cz, int kpad_f, int k
 // [n][c][nvox/n] when planar), y the layer's BF16 output (ignored when !act).
 void launch_act_bwd(const float* dy, const uint16_t* y, long long nvox, int n, int c, int cz,
                     int act, int planar, float slope, uint16_t* dz, hipStream_t st);
-// Gradient of cat(up2(x0), x1), x0's part: d0 [n][V/8][c0] (overwritten) = sum
-// over the 2 x 2 x 2 children of dx [n][V][c0] (the convolution writes x1's
-// part directly, ConvGeom::csplit).
-void launch_split_half(const float* dx, const Geom& full, int n, int c0, float* d0,
-                       hipStream_t st);
-// The same sum, then the adjoint of the leaky ReLU whose output y [n][V/8][c0]
-// it is: dz [n][V/8][c0] = BF16(sum * (y > 0 ? 1 : slope)).
-void launch_split_half_act(const float* dx, const Geom& full, int n, int c0, const uint16_t* y,
-                           float slope, uint16_t* dz, hipStream_t st);
 // out = BF16(in), count values
 void launch_to_bf16(const float* in, uint16_t* out, long long count, hipStream_t st);
 // loss += sum (p - t)^2 / count (FP64), g = 2 (p - t) / count

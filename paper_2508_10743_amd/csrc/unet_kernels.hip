@@ -45,11 +45,12 @@ __device__ __forceinline__ float from_bf16(uint16_t h) {
   return __uint_as_float(static_cast<uint32_t>(h) << 16);
 }
 
-// One channels-last FP32 output element (ConvGeom: split channels, or the
+// One channels-last FP32 output element (ConvGeom: split channels, the skip
+// channels of a pooled split, or the
 // next layer's activation adjoint fused into a BF16 output).
 __device__ __forceinline__ void store_cl32(const ConvGeom& cg, float* __restrict__ y32,
                                            long long mo, int co, float val) {
-  if (cg.dz16) {
+  if (cg.dz16 && !cg.hpool) {
     const long long i = mo * cg.cout + co;
     float tot = cg.accum ? y32[i] + val : val;
     if (!(from_bf16(cg.acty[i]) > 0.0f)) tot *= cg.slope;
@@ -383,10 +384,53 @@ __global__ __launch_bounds__(CNT) void k_conv3d_lds(const uint16_t* __restrict__
   }
   // epilogue: lane holds d2 offsets 4 kg .. 4 kg + 3 of channel column r
   const int z = oz + wave;
+  if (cg.hpool) {
+    // channels below csplit to half resolution: the lane's 2 (d1) x 2 (d2)
+    // children of each pair of its row tiles and d2 offsets summed in
+    // registers, then the odd wave's sums (plane z + 1) passed to the even
+    // wave through the LDS brick, free since the loop's last barrier; the
+    // brick origin is even on every axis, so no pair spans two blocks
+    static_assert(2 * NT16 * MT * 64 * sizeof(float) <= sizeof(brick), "pair sums fit the brick");
+    static_assert(MT % 2 == 0 && LBZ % 2 == 0, "row tiles and planes pair up");
+    float hp[NT16][MT / 2][2];
+#pragma unroll
+    for (int t = 0; t < NT16; ++t)
+#pragma unroll
+      for (int yp = 0; yp < MT / 2; ++yp)
+#pragma unroll
+        for (int xp = 0; xp < 2; ++xp)
+          hp[t][yp][xp] = (acc[2 * yp][t][2 * xp] + acc[2 * yp][t][2 * xp + 1]) +
+                          (acc[2 * yp + 1][t][2 * xp] + acc[2 * yp + 1][t][2 * xp + 1]);
+    float* xch = reinterpret_cast<float*>(brick) + (wave >> 1) * (NT16 * MT * 64);
+    if (wave & 1) {
+#pragma unroll
+      for (int t = 0; t < NT16; ++t)
+#pragma unroll
+        for (int j = 0; j < MT; ++j) xch[(t * MT + j) * 64 + lane] = hp[t][j >> 1][j & 1];
+    }
+    __syncthreads();
+    if (!(wave & 1) && z < cg.o0) {
+      const int H0 = cg.o0 / 2, H1 = cg.o1 / 2, H2 = cg.o2 / 2;
+#pragma unroll
+      for (int t = 0; t < NT16; ++t) {
+        const int co = nco0 + t * 16 + r;
+        if (co >= cg.csplit) continue;
+#pragma unroll
+        for (int j = 0; j < MT; ++j) {
+          const int y = oy + 2 * (j >> 1), x = ox + 4 * kg + 2 * (j & 1);
+          if (y >= cg.o1 || x >= cg.o2) continue;
+          const long long q = ((static_cast<long long>(s) * H0 + (z >> 1)) * H1 + (y >> 1)) * H2 + (x >> 1);
+          float tot = hp[t][j >> 1][j & 1] + xch[(t * MT + j) * 64 + lane];
+          if (!(from_bf16(cg.acty[q * cg.csplit + co]) > 0.0f)) tot *= cg.slope;
+          cg.dz16[q * cg.csplit + co] = to_bf16(tot);
+        }
+      }
+    }
+  }
 #pragma unroll
   for (int t = 0; t < NT16; ++t) {
     const int co = nco0 + t * 16 + r;
-    if (co >= cg.cout) continue;
+    if (co >= cg.cout || (cg.hpool && co < cg.csplit)) continue;
     const float bb = bias ? bias[co] : 0.0f;
 #pragma unroll
     for (int q2 = 0; q2 < MT; ++q2) {
@@ -1011,40 +1055,6 @@ __global__ __launch_bounds__(kBlock) void k_act_bwd(const float* __restrict__ dy
   dz[i] = to_bf16(d);
 }
 
-template <bool ACT>
-__global__ __launch_bounds__(kBlock) void k_split_half(const float* __restrict__ dx, Geom full,
-                                                       int n, int c0, float* __restrict__ d0,
-                                                       const uint16_t* __restrict__ y,
-                                                       float slope, uint16_t* __restrict__ dz) {
-  const int h0 = full.d0 / 2, h1 = full.d1 / 2, h2 = full.d2 / 2;
-  const long long hv = static_cast<long long>(h0) * h1 * h2;
-  const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= n * hv * c0) return;
-  const long long q = i / c0;
-  const int ch = static_cast<int>(i - q * c0);
-  const long long s = q / hv;
-  int rem = static_cast<int>(q - s * hv);
-  const int q2 = rem % h2;
-  rem /= h2;
-  const int q1 = rem % h1, q0 = rem / h1;
-  float acc = 0.0f;
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int e = 0; e < 2; ++e) {
-        const long long p = ((s * full.d0 + 2 * q0 + a) * full.d1 + 2 * q1 + b) * full.d2 + 2 * q2 + e;
-        acc += dx[p * c0 + ch];
-      }
-  if (ACT) {
-    if (!(from_bf16(y[i]) > 0.0f)) acc *= slope;
-    dz[i] = to_bf16(acc);
-  } else {
-    d0[i] = acc;
-  }
-}
-
 __global__ __launch_bounds__(kBlock) void k_to_bf16(const float* __restrict__ in,
                                                     uint16_t* __restrict__ out, long long count) {
   const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
@@ -1128,20 +1138,6 @@ void launch_act_bwd(const float* dy, const uint16_t* y, long long nvox, int n, i
                     int act, int planar, float slope, uint16_t* dz, hipStream_t st) {
   hipLaunchKernelGGL(k_act_bwd, dim3(grid_1d(nvox * cz)), dim3(kBlock), 0, st, dy, y, nvox,
                      nvox / n, c, cz, act, planar, slope, dz);
-}
-
-void launch_split_half(const float* dx, const Geom& full, int n, int c0, float* d0,
-                       hipStream_t st) {
-  const long long hv = static_cast<long long>(full.d0 / 2) * (full.d1 / 2) * (full.d2 / 2);
-  hipLaunchKernelGGL(k_split_half<false>, dim3(grid_1d(n * hv * c0)), dim3(kBlock), 0, st, dx,
-                     full, n, c0, d0, nullptr, 0.0f, nullptr);
-}
-
-void launch_split_half_act(const float* dx, const Geom& full, int n, int c0, const uint16_t* y,
-                           float slope, uint16_t* dz, hipStream_t st) {
-  const long long hv = static_cast<long long>(full.d0 / 2) * (full.d1 / 2) * (full.d2 / 2);
-  hipLaunchKernelGGL(k_split_half<true>, dim3(grid_1d(n * hv * c0)), dim3(kBlock), 0, st, dx,
-                     full, n, c0, nullptr, y, slope, dz);
 }
 
 void launch_to_bf16(const float* in, uint16_t* out, long long count, hipStream_t st) {

@@ -193,15 +193,17 @@ def _oracle_params(net):
             for nm, w, b in zip(names, net.weights, net.biases)}
 
 
-def test_unet_backward_matches_oracle(dev):
-    """The whole network's weight gradients.  Each layer's gradients are
+@pytest.mark.parametrize("dims", [(16, 16, 32), (8, 24, 40)])
+def test_unet_backward_matches_oracle(dev, dims):
+    """The whole network's weight gradients (the second shape leaves ragged
+    LDS bricks, 4 x 4 x 16 outputs, at every level on d1 and d2).  Each layer's gradients are
     exact up to FP32 accumulation (test_conv3d_gradients); across the
     network the forward activations already differ from the oracle's by
     ~1e-3 (BF16 storage after FP32 versus exact accumulation, see
     test_unet_forward), and the backward reads those activations, so the
-    weight gradients agree within a few 1e-2 (rel-L2; the deep layers see
-    the fewest voxels and average least)."""
-    dims = (16, 16, 32)
+    weight gradients agree within 1e-2 (rel-L2; measured up to 1.5e-3, the
+    deep layers, which see the fewest voxels and average least, the
+    farthest)."""
     imgs = make_cohort(WORKLOADS["blobs-4x32^3-mse"], n=2, dims=dims, seed=530)
     atlas = imgs.mean(0).astype(np.float32)
     tgt = (np.random.default_rng(531).normal(0, 0.5, (2, 3) + dims)).astype(np.float32)
@@ -216,7 +218,7 @@ def test_unet_backward_matches_oracle(dev):
         ew = np.linalg.norm(dw - rg[name][0]) / np.linalg.norm(rg[name][0])
         eb = np.linalg.norm(db - rg[name][1]) / max(np.linalg.norm(rg[name][1]), 1e-30)
         print(f"{name}: dw rel-L2 {ew:.2e}, db rel-L2 {eb:.2e}")
-        assert ew <= 3e-2 and eb <= 3e-2, name
+        assert ew <= 1e-2 and eb <= 1e-2, name
 
 
 def test_training_reduces_the_loss(dev):

@@ -699,11 +699,11 @@ const UnetLayer kUnet[8] = {{8, 16, 1, 1},   {16, 32, 2, 1}, {32, 64, 2, 1}, {64
                             {192, 64, 1, 1}, {96, 32, 1, 1}, {48, 16, 1, 1}, {16, 3, 1, 0}};
 
 // Scratch of the network: BF16 activations (forward), then for training the
-// prediction, its gradient, two BF16 output gradients, one BF16 weight pack
-// and the FP32 gradients of the skip outputs.
+// prediction, two BF16 output gradients, one BF16 weight pack and the FP32
+// gradients of the skip outputs.
 struct UnetWs {
   size_t x, e0, e1, e2, e3, d2, d1, d0, fwd;                   // forward part
-  size_t vp, dv, dz, dz2, wt, ge2, ge1, ge0, total;  // training part
+  size_t vp, dz, dz2, wt, ge2, ge1, ge0, total;  // training part
 };
 
 UnetWs unet_ws(int n, int d0, int d1, int d2) {
@@ -726,7 +726,6 @@ UnetWs unet_ws(int n, int d0, int d1, int d2) {
   L.d0 = take(V * 16 * h);
   L.fwd = off;
   L.vp = take(V * 3 * f);
-  L.dv = take(V * 3 * f);
   L.dz = take(V * 16 * h);
   L.dz2 = take(V * 16 * h);
   L.wt = take(static_cast<size_t>(192) * conv_kpad(64, 27) * h);
@@ -836,14 +835,12 @@ void unet_run_backward(const uint16_t* wq, const float* w, const float* b, const
   float* vp = vpred ? vpred : f32(L.vp);
   unet_run_forward(wq, b, atlas, images, vp, n, d0, d1, d2, base, L, P, st);
   const long long V = static_cast<long long>(d0) * d1 * d2;
-  launch_vec_mse(vp, target, static_cast<long long>(n) * 3 * V, loss, f32(L.dv), st);
   launch_fill_f32(dw, static_cast<long long>(unet_num_weights()), 0.0f, st);
   launch_fill_f32(db, unet_num_biases(), 0.0f, st);
   // FP32 gradients where a layer's output gradient has two sources (the
-  // skip outputs e0, e1, e2) and of the prediction; the others pass to the
-  // next layer fused into BF16 (below)
-  float* dy[8] = {f32(L.ge0), f32(L.ge1), f32(L.ge2), nullptr, nullptr, nullptr, nullptr,
-                  f32(L.dv)};
+  // skip outputs e0, e1, e2); the others pass to the next layer fused into
+  // BF16 (below)
+  float* dy[7] = {f32(L.ge0), f32(L.ge1), f32(L.ge2), nullptr, nullptr, nullptr, nullptr};
   // BF16 output gradients of consecutive layers alternate between two
   // buffers: the input-gradient convolution of layer l reads layer l's and
   // writes layer l-1's, the activation adjoint fused into its epilogue
@@ -854,8 +851,9 @@ void unet_run_backward(const uint16_t* wq, const float* w, const float* b, const
     const UnetLayer& U = kUnet[l];
     const int cz = (U.cout + 7) / 8 * 8;
     uint16_t* dz = dzb[(7 - l) & 1];
-    // the output layer's gradient comes from the loss (planar FP32)
-    if (l == 7) launch_act_bwd(dy[7], S.y, S.cg.nvox, n, U.cout, cz, U.act, 1, 0.2f, dz, st);
+    // the output layer's gradient comes from the loss, written as BF16 by
+    // the loss kernel (the output layer has no activation)
+    if (l == 7) launch_mse_dz(vp, target, n, V, U.cout, cz, loss, dz, st);
     launch_conv_wgrad(dz, cz, S.x0, S.x1, S.cg, dw + S.wo, db + S.bo, st);
     if (l == 0) break;
     // input gradient: a stride-1 convolution of dz (on the dilated grid for

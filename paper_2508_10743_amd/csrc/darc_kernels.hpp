@@ -208,15 +208,13 @@ void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uin
 // FP32 master weights w [cout][kpad_f]; zero for co >= cout, tap' >= 27.
 void launch_pack_wt(const float* w, int cin, int cout, int cz, int kpad_f, int kpad_t,
                     uint16_t* wt, hipStream_t st);
-// dz = BF16(dy * act'(y)) channels-last [nvox][cz], dy FP32 [nvox][c] (planar
-// [n][c][nvox/n] when planar), y the layer's BF16 output (ignored when !act).
-void launch_act_bwd(const float* dy, const uint16_t* y, long long nvox, int n, int c, int cz,
-                    int act, int planar, float slope, uint16_t* dz, hipStream_t st);
 // out = BF16(in), count values
 void launch_to_bf16(const float* in, uint16_t* out, long long count, hipStream_t st);
-// loss += sum (p - t)^2 / count (FP64), g = 2 (p - t) / count
-void launch_vec_mse(const float* p, const float* t, long long count, double* loss, float* g,
-                    hipStream_t st);
+// p, t [n][c][V]: loss += sum (p - t)^2 / count (FP64, count = n c V) and
+// dz [n V][cz] channels-last BF16 = 2 (p - t) / count below channel c, zero
+// from c to cz (c <= cz, cz a multiple of 8)
+void launch_mse_dz(const float* p, const float* t, int n, long long V, int c, int cz,
+                   double* loss, uint16_t* dz, hipStream_t st);
 
 // --- small helpers --------------------------------------------------------
 void launch_fill_f32(float* p, long long count, float value, hipStream_t st);

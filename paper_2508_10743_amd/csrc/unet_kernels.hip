@@ -1033,51 +1033,47 @@ __global__ __launch_bounds__(kBlock) void k_pack_wt(const float* __restrict__ w,
   wt[i] = to_bf16(val);
 }
 
-__global__ __launch_bounds__(kBlock) void k_act_bwd(const float* __restrict__ dy,
-                                                    const uint16_t* __restrict__ y, long long nvox,
-                                                    long long vps, int c, int cz, int act,
-                                                    int planar, float slope,
-                                                    uint16_t* __restrict__ dz) {
-  const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
-  if (i >= nvox * cz) return;
-  const long long v = i / cz;
-  const int ch = static_cast<int>(i - v * cz);
-  float d = 0.0f;
-  if (ch < c) {
-    if (planar) {
-      const long long s = v / vps;
-      d = dy[(s * c + ch) * vps + (v - s * vps)];
-    } else {
-      d = dy[v * c + ch];
-    }
-    if (act && !(from_bf16(y[v * c + ch]) > 0.0f)) d *= slope;
-  }
-  dz[i] = to_bf16(d);
-}
-
 __global__ __launch_bounds__(kBlock) void k_to_bf16(const float* __restrict__ in,
                                                     uint16_t* __restrict__ out, long long count) {
   const long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x;
   if (i < count) out[i] = to_bf16(in[i]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_vec_mse(const float* __restrict__ p,
-                                                    const float* __restrict__ t, long long count,
-                                                    double inv, double* __restrict__ loss,
-                                                    float* __restrict__ g) {
+// The loss of the prediction p [n][c][V] against t (same layout) and its
+// gradient as the output layer's BF16 output gradient: loss += sum (p - t)^2
+// / count (FP64, count = n c V), dz [n V][cz] channels-last = BF16(2 (p - t)
+// / count) for channels below c, zero above (the output layer has no
+// activation).  One thread per voxel, grid-stride within subject
+// blockIdx.y; one loss atomic per block.
+__global__ __launch_bounds__(kBlock) void k_mse_dz(const float* __restrict__ p,
+                                                   const float* __restrict__ t, long long V,
+                                                   int c, int cz, double inv,
+                                                   double* __restrict__ loss,
+                                                   uint16_t* __restrict__ dz) {
   __shared__ double red[kBlock / 64];
-  // grid-stride over a bounded grid: one loss atomic per block
+  const long long sub = blockIdx.y;
+  const float* ps = p + sub * c * V;
+  const float* ts = t + sub * c * V;
+  uint16_t* ds = dz + sub * V * cz;
   double acc = 0.0;
   const long long stride = static_cast<long long>(gridDim.x) * kBlock;
-  for (long long i = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x; i < count;
-       i += stride) {
-    const double d = static_cast<double>(p[i]) - static_cast<double>(t[i]);
-    acc += d * d * inv;
-    g[i] = static_cast<float>(2.0 * d * inv);
+  for (long long v = static_cast<long long>(blockIdx.x) * kBlock + threadIdx.x; v < V; v += stride) {
+    for (int c8 = 0; c8 < cz; c8 += 8) {
+      uint32_t wd[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        if (c8 + j >= c) break;
+        const double d = static_cast<double>(ps[(c8 + j) * V + v]) - static_cast<double>(ts[(c8 + j) * V + v]);
+        acc += d * d * inv;
+        wd[j >> 1] |= static_cast<uint32_t>(to_bf16(static_cast<float>(2.0 * d * inv))) << (16 * (j & 1));
+      }
+      *reinterpret_cast<uint4*>(ds + v * cz + c8) = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+    }
   }
   const double tot = block_sum<kBlock>(acc, red);
   if (threadIdx.x == 0) atomicAdd(loss, tot);
 }
+
 
 }  // namespace
 
@@ -1134,21 +1130,15 @@ void launch_pack_wt(const float* w, int cin, int cout, int cz, int kpad_f, int k
                      0, st, w, cin, cout, cz, kpad_f, kpad_t, wt);
 }
 
-void launch_act_bwd(const float* dy, const uint16_t* y, long long nvox, int n, int c, int cz,
-                    int act, int planar, float slope, uint16_t* dz, hipStream_t st) {
-  hipLaunchKernelGGL(k_act_bwd, dim3(grid_1d(nvox * cz)), dim3(kBlock), 0, st, dy, y, nvox,
-                     nvox / n, c, cz, act, planar, slope, dz);
-}
-
 void launch_to_bf16(const float* in, uint16_t* out, long long count, hipStream_t st) {
   hipLaunchKernelGGL(k_to_bf16, dim3(grid_1d(count)), dim3(kBlock), 0, st, in, out, count);
 }
 
-void launch_vec_mse(const float* p, const float* t, long long count, double* loss, float* g,
-                    hipStream_t st) {
-  const uint32_t blocks = grid_1d(count) < 2048u ? grid_1d(count) : 2048u;
-  hipLaunchKernelGGL(k_vec_mse, dim3(blocks), dim3(kBlock), 0, st, p, t, count,
-                     1.0 / static_cast<double>(count), loss, g);
+void launch_mse_dz(const float* p, const float* t, int n, long long V, int c, int cz,
+                   double* loss, uint16_t* dz, hipStream_t st) {
+  const uint32_t bx = std::max(1u, std::min(grid_1d(V), 2048u / static_cast<uint32_t>(n)));
+  hipLaunchKernelGGL(k_mse_dz, dim3(bx, static_cast<uint32_t>(n)), dim3(kBlock), 0, st, p, t, V, c,
+                     cz, 1.0 / (static_cast<double>(n) * c * V), loss, dz);
 }
 
 int conv_kpad(int cin, int ntaps) {

@@ -384,6 +384,48 @@ __global__ __launch_bounds__(CNT) void k_conv3d_lds(const uint16_t* __restrict__
   }
   // epilogue: lane holds d2 offsets 4 kg .. 4 kg + 3 of channel column r
   const int z = oz + wave;
+  constexpr bool kVecOut = NT16 <= 2 && CWAVES * MT * 16 * 16 * sizeof(float) <= sizeof(brick);
+  if (kVecOut && y16 && cg.cout % 8 == 0) {
+    // BF16 outputs through the LDS brick (free since the loop's last
+    // barrier), one column tile at a time: each wave writes its MT x 16
+    // voxels x 16 channels as FP32 (bias and activation applied), then each
+    // lane converts 8 channels of one voxel and stores them with one 16-byte
+    // write
+    float* tb = reinterpret_cast<float*>(brick) + wave * (MT * 16 * 16);
+#pragma unroll
+    for (int t = 0; t < NT16; ++t) {
+      const int co = nco0 + t * 16 + r;
+      const float bb = bias && co < cg.cout ? bias[co] : 0.0f;
+#pragma unroll
+      for (int q2 = 0; q2 < MT; ++q2)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float val = acc[q2][t][i] + bb;
+          if (cg.act) val = val > 0.0f ? val : cg.slope * val;
+          tb[(q2 * 16 + 4 * kg + i) * 16 + r] = val;
+        }
+      __syncthreads();
+#pragma unroll
+      for (int k = 0; k < MT / 2; ++k) {
+        const int c = lane + 64 * k;  // voxel c / 2 of the wave, channels 8 (c % 2) ..
+        const int v = c >> 1, hh = c & 1;
+        const int y = oy + v / 16, x = ox + v % 16, co8 = nco0 + t * 16 + 8 * hh;
+        if (z < cg.o0 && y < cg.o1 && x < cg.o2 && co8 < cg.cout) {
+          const float4 lo = *reinterpret_cast<const float4*>(tb + v * 16 + 8 * hh);
+          const float4 hi = *reinterpret_cast<const float4*>(tb + v * 16 + 8 * hh + 4);
+          const uint4 pk = make_uint4(
+              static_cast<uint32_t>(to_bf16(lo.x)) | (static_cast<uint32_t>(to_bf16(lo.y)) << 16),
+              static_cast<uint32_t>(to_bf16(lo.z)) | (static_cast<uint32_t>(to_bf16(lo.w)) << 16),
+              static_cast<uint32_t>(to_bf16(hi.x)) | (static_cast<uint32_t>(to_bf16(hi.y)) << 16),
+              static_cast<uint32_t>(to_bf16(hi.z)) | (static_cast<uint32_t>(to_bf16(hi.w)) << 16));
+          const long long mo = s * per + (static_cast<long long>(z) * cg.o1 + y) * cg.o2 + x;
+          *reinterpret_cast<uint4*>(y16 + mo * cg.cout + co8) = pk;
+        }
+      }
+      __syncthreads();
+    }
+    return;
+  }
   if (cg.hpool) {
     // channels below csplit to half resolution: the lane's 2 (d1) x 2 (d2)
     // children of each pair of its row tiles and d2 offsets summed in

@@ -81,7 +81,10 @@ def test_pointwise_conv_is_a_gemm(dev):
     # of 48 (the second with two chunked channel groups, the third with an
     # odd number of input channel groups)
     (48, 16, 1, (9, 10, 35)), (32, 96, 1, (5, 13, 18)), (8, 16, 1, (12, 9, 33)),
-    (24, 48, 1, (5, 6, 18))])
+    (24, 48, 1, (5, 6, 18)),
+    # stride 2 over a larger volume: 32 x 32 x 64 outputs per subject, more
+    # than a thousand blocks of 64 output voxels
+    (8, 32, 2, (64, 64, 128)), (8, 64, 2, (64, 64, 128))])
 def test_conv3d_bf16_out(dev, cin, cout, stride, dims):
     rng = np.random.default_rng(501 + cin + stride)
     x = rand_bf16(rng, (2, cin) + dims)

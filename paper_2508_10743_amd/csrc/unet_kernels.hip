@@ -1137,11 +1137,12 @@ void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uin
     // decoder layers, six or more channel groups; as fast on its output
     // layer, two groups; slower on its first layer, one group of 8 channels
     // of which two are used); K steps (32-voxel row segments) per wave
-    // doubled from 8 up to 128 while at least 2048 waves remain
+    // doubled from 8 up to 256 while at least 2048 waves remain (longer runs
+    // mean fewer atomics on the same gradient entries)
     const uint32_t ngrp = static_cast<uint32_t>((cg.c0 + cg.c1) / 8);
     const long long nsteps = cg.nvox / cg.o2 * ((cg.o2 + 31) / 32);
     long long ws = 8;
-    while (ws < 128 && (nsteps + 2 * ws - 1) / (2 * ws) * ngrp * gz >= 2048) ws *= 2;
+    while (ws < 256 && (nsteps + 2 * ws - 1) / (2 * ws) * ngrp * gz >= 2048) ws *= 2;
     const dim3 grid(static_cast<uint32_t>((nsteps + ws - 1) / ws * ngrp * gz));
     const int w = static_cast<int>(ws);
     if (cg.up0)

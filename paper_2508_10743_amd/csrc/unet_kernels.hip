@@ -883,25 +883,28 @@ __global__ __launch_bounds__(64) void k_conv_wgrad(int wch, const uint16_t* __re
   }
 }
 
-// Weight gradients of a 27-tap layer, all taps of one input channel group at
-// once: a wave takes a co tile of 16, one group of 8 input channels and a
-// run of K steps, a K step being a row segment of 32 output voxels along d2.
-// The input positions that the 27 taps read for the segment (3 x 3 rows of
-// NXP positions, 8 channels each) are staged in LDS once per step; each of
-// the 14 column tiles (taps 2t and 2t + 1, 8 channels each) then reads its B
-// fragment there through the transposing LDS read, lane j of a 16-lane group
-// pointing at the 4 channels 4 (j % 4).. of tile column group j % 4 at voxel
-// base + j / 4.  A step stages about 10 (stride 1) or 18 (stride 2) input
-// positions per output voxel where the tap-by-tap kernel above loads 27.
-template <int X0, int STRIDE>
+// Weight gradients of a stride-1, 27-tap layer, all taps of one input
+// channel group at once: a wave takes a co tile of 16, one group of 8 input
+// channels and a run of K steps, a K step being 32 output voxels, R rows
+// (d1) of W = 32 / R along d2.  The input positions that the 27 taps read
+// for them (3 x (R + 2) rows of W + 2 positions, 8 channels each) are staged
+// in LDS once per step; each of the 14 column tiles (taps 2t and 2t + 1,
+// 8 channels each) then reads its B fragment there through the transposing
+// LDS read, lane j of a 16-lane group pointing at the 4 channels 4 (j % 4)..
+// of tile column group j % 4 at voxel base + j / 4.  A step stages 9.6
+// (R = 1), 6.8 (R = 2) or 5.6 (R = 4) input positions per output voxel
+// where the tap-by-tap kernel above loads 27.
+template <int X0, int R>
 __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
                                                         const uint16_t* __restrict__ dz, int cz,
                                                         const uint16_t* __restrict__ x0,
                                                         const uint16_t* __restrict__ x1,
                                                         ConvGeom cg, float* __restrict__ dw,
                                                         float* __restrict__ db) {
-  constexpr int NXP = 31 * STRIDE + 3;  // input positions along d2 for 32 outputs
-  constexpr int NPOS = 9 * NXP;
+  constexpr int W = 32 / R;    // output voxels per row of a step
+  constexpr int NXP = W + 2;   // input positions along d2
+  constexpr int NYP = R + 2;   // input rows along d1
+  constexpr int NPOS = 3 * NYP * NXP;
   constexpr int NLD = (NPOS + 63) / 64;  // staged positions per lane
   constexpr int NTT = 14;                // column tiles: 27 taps (and one empty) x 8 channels
   __shared__ __align__(16) uint16_t xs[NPOS * 8];  // [position][8 channels]
@@ -933,11 +936,14 @@ __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
 #pragma unroll
   for (int t = 0; t < NTT; ++t) {
     const int tap = min(2 * t + ((r & 3) >> 1), 26);  // tap 27 (empty columns): any valid row
-    toff[t] = (((tap / 9) * 3 + (tap / 3) % 3) * NXP + tap % 3) * 8 + (r & 1) * 4;
+    toff[t] = (((tap / 9) * NYP + (tap / 3) % 3) * NXP + tap % 3) * 8 + (r & 1) * 4;
   }
-  const int vrow = (8 * g + (r >> 2)) * STRIDE * 8;  // voxel 8 g + j / 4 of the segment
-  const int nseg = (cg.o2 + 31) / 32;
-  const long long nsteps = static_cast<long long>(cg.nvox / cg.o2) * nseg;
+  // voxel m = 8 g + j / 4 of the step (row m / W) and m + 4 (the same row)
+  const int mv = 8 * g + (r >> 2);
+  const int vrow = ((mv / W) * NXP + mv % W) * 8;
+  const int nseg = (cg.o2 + W - 1) / W;
+  const int nrg = (cg.o1 + R - 1) / R;  // groups of R rows per plane
+  const long long nsteps = static_cast<long long>(cg.nvox / (static_cast<long long>(cg.o1) * cg.o2)) * nrg * nseg;
   f32x4 acc[NTT];
 #pragma unroll
   for (int t = 0; t < NTT; ++t) acc[t] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -949,20 +955,20 @@ __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
   // first input voxel where the value is zero; the padding is applied when
   // staged).  A step's loads are issued before the previous step's
   // products; past the run the last step is loaded again and never staged.
-  // The step's row (subject sj, output voxel oz, oy) and segment are kept as
-  // counters (wave-uniform, advanced once per step: no division in the
-  // loop), and the per-lane offsets are 32-bit (the launch checks that every
-  // input tensor's subject holds fewer than 2^31 elements).
-  long long row = s0 / nseg;
-  int seg = static_cast<int>(s0 - row * nseg);
-  int oy = static_cast<int>(row % cg.o1);
-  int oz = static_cast<int>((row / cg.o1) % cg.o0);
-  int sj = static_cast<int>(row / cg.o1 / cg.o0);
+  // The step's rows (subject sj, output plane oz, first row oy) and segment
+  // are kept as counters (wave-uniform, advanced once per step: no division
+  // in the loop), and the per-lane offsets are 32-bit (the launch checks
+  // that every input tensor's subject holds fewer than 2^31 elements).
+  const long long rg0 = s0 / nseg;  // row group of the first step
+  int seg = static_cast<int>(s0 - rg0 * nseg);
+  int oy = static_cast<int>(rg0 % nrg) * R;
+  int oz = static_cast<int>((rg0 / nrg) % cg.o0);
+  int sj = static_cast<int>(rg0 / nrg / cg.o0);
   auto advance = [&]() {
     if (++seg == nseg) {
       seg = 0;
-      ++row;
-      if (++oy == cg.o1) {
+      oy += R;
+      if (oy >= cg.o1) {
         oy = 0;
         if (++oz == cg.o0) {
           oz = 0;
@@ -971,17 +977,19 @@ __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
       }
     }
   };
+  const int vy = vl / W, vx = vl % W;  // the dz voxel this lane stages
   auto issue = [&](uint4& a, bool& aok, uint4 (&xv)[NLD], bool (&xin)[NLD]) {
-    const int x0v = seg * 32;
-    aok = x0v + vl < cg.o2 && co0 + 8 * h < cz;
-    const uint16_t* drow = dz + row * cg.o2 * cz;
-    a = *reinterpret_cast<const uint4*>(drow + (aok ? (x0v + vl) * cz + co0 + 8 * h : 0));
-    const int qz = oz * STRIDE - 1, qy = oy * STRIDE - 1, qx = x0v * STRIDE - 1;
+    const int x0v = seg * W;
+    aok = oy + vy < cg.o1 && x0v + vx < cg.o2 && co0 + 8 * h < cz;
+    const uint16_t* dplane = dz + (static_cast<long long>(sj) * cg.o0 + oz) * cg.o1 * cg.o2 * cz;
+    a = *reinterpret_cast<const uint4*>(
+        dplane + (aok ? ((oy + vy) * cg.o2 + x0v + vx) * cz + co0 + 8 * h : 0));
+    const int qz = oz - 1, qy = oy - 1, qx = x0v - 1;
     const uint16_t* base = src + static_cast<long long>(sj) * vin * cstr + coff;
 #pragma unroll
     for (int k = 0; k < NLD; ++k) {
       const int i = lane + 64 * k;
-      const int pa = i / (3 * NXP), pb = (i / NXP) % 3, xi = i % NXP;
+      const int pa = i / (NYP * NXP), pb = (i / NXP) % NYP, xi = i % NXP;
       const int pz = qz + pa, py = qy + pb, px = qx + xi;
       xin[k] = i < NPOS && static_cast<unsigned>(pz) < static_cast<unsigned>(cg.i0) &&
                static_cast<unsigned>(py) < static_cast<unsigned>(cg.i1) &&
@@ -1023,7 +1031,7 @@ __global__ __launch_bounds__(64) void k_conv_wgrad_rows(int wsteps,
     for (int t = 0; t < NTT; ++t) {
       const uint16_t* p = xs + vrow + toff[t];
       const v4i16 lo = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4)(p));
-      const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4)(p + 4 * STRIDE * 8));
+      const v4i16 hi = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_v4)(p + 4 * 8));
       const bf16x8 bfrag =
           __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(afrag, bfrag, acc[t], 0, 0, 0);
@@ -1139,18 +1147,30 @@ void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uin
     // of which two are used); K steps (32-voxel row segments) per wave
     // doubled from 8 up to 256 while at least 2048 waves remain (longer runs
     // mean fewer atomics on the same gradient entries)
+    // Rows per K step: 4 (8 voxels each) where d2 is a multiple of 8, so
+    // that no lane of a step falls past the row, else one row of 32
+    const int rr = cg.o2 % 8 == 0 ? 4 : 1;
     const uint32_t ngrp = static_cast<uint32_t>((cg.c0 + cg.c1) / 8);
-    const long long nsteps = cg.nvox / cg.o2 * ((cg.o2 + 31) / 32);
+    const int wv = 32 / rr;
+    const long long nsteps = cg.nvox / (static_cast<long long>(cg.o1) * cg.o2) *
+                             ((cg.o1 + rr - 1) / rr) * ((cg.o2 + wv - 1) / wv);
     long long ws = 8;
     while (ws < 256 && (nsteps + 2 * ws - 1) / (2 * ws) * ngrp * gz >= 2048) ws *= 2;
     const dim3 grid(static_cast<uint32_t>((nsteps + ws - 1) / ws * ngrp * gz));
     const int w = static_cast<int>(ws);
-    if (cg.up0)
-      hipLaunchKernelGGL((k_conv_wgrad_rows<1, 1>), grid, dim3(64), 0, st, w, dz, cz, x0, x1, cg, dw,
-                         db);
-    else
-      hipLaunchKernelGGL((k_conv_wgrad_rows<0, 1>), grid, dim3(64), 0, st, w, dz, cz, x0, x1, cg, dw,
-                         db);
+    auto go = [&](auto xm, auto rm) {
+      constexpr int XM = decltype(xm)::value, RM = decltype(rm)::value;
+      hipLaunchKernelGGL((k_conv_wgrad_rows<XM, RM>), grid, dim3(64), 0, st, w, dz, cz, x0, x1, cg,
+                         dw, db);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I4 = std::integral_constant<int, 4>;
+    if (cg.up0) {
+      if (rr == 4) go(I1{}, I4{}); else go(I1{}, I1{});
+    } else {
+      if (rr == 4) go(I0{}, I4{}); else go(I0{}, I1{});
+    }
     prof_end(st, KC_MISC);
     return;
   }

@@ -156,8 +156,11 @@ def test_warm_start_feeds_a_sweep(dev):
     # input gradient) and 24 output channels (an odd number of channel groups)
     (96, 32, 2, False, (18, 12, 36)), (16, 24, 2, False, (10, 14, 34)),
     # the all-taps weight gradient (stride 1, six or more channel groups):
-    # rows of several 32-voxel segments with a ragged last one
-    (48, 16, 1, False, (6, 8, 70)), (96, 40, 1, True, (6, 10, 40))])
+    # rows of several 32-voxel segments with a ragged last one (d2 not a
+    # multiple of 8), and K steps of 4 rows x 8 voxels with a ragged last
+    # group of rows (d2 a multiple of 8)
+    (48, 16, 1, False, (6, 8, 70)), (96, 40, 1, True, (6, 10, 40)),
+    (48, 16, 1, False, (5, 7, 48))])
 def test_conv3d_gradients(dev, cin, cout, stride, up, dims):
     """One layer's weight, bias and input gradients from identical BF16
     inputs: FP32 accumulation against exact sums.  Stride-2 input gradients

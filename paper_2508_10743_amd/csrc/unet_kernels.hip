@@ -1138,15 +1138,15 @@ void launch_conv_wgrad(const uint16_t* dz, int cz, const uint16_t* x0, const uin
   // waves (two per SIMD) remain (measured on the warm-start network at
   // 96 x 112 x 96: longer chunks starve the low-resolution layers)
   const long long vfull = static_cast<long long>(cg.i0) * cg.i1 * cg.i2;
-  if (cg.ntaps == 27 && cg.stride == 1 && !cg.dil0 && cg.c0 + cg.c1 >= 48 &&
+  if (cg.ntaps == 27 && cg.stride == 1 && !cg.dil0 && cg.c0 + cg.c1 >= 16 &&
       vfull * std::max(cg.c0, cg.c1) < (1LL << 31)) {
     // all taps of a channel group per wave (measured on the warm-start
     // network at 96 x 112 x 96: faster than the tap-by-tap kernel on its
-    // decoder layers, six or more channel groups; as fast on its output
+    // decoder layers, six or more channel groups, and slightly on its output
     // layer, two groups; slower on its first layer, one group of 8 channels
-    // of which two are used); K steps (32-voxel row segments) per wave
-    // doubled from 8 up to 256 while at least 2048 waves remain (longer runs
-    // mean fewer atomics on the same gradient entries)
+    // of which two are used); K steps per wave doubled from 8 up to 256
+    // while at least 2048 waves remain (longer runs mean fewer atomics on
+    // the same gradient entries)
     // Rows per K step: 4 (8 voxels each) where d2 is a multiple of 8, so
     // that no lane of a step falls past the row, else one row of 32
     const int rr = cg.o2 % 8 == 0 ? 4 : 1;

@@ -426,6 +426,66 @@ __global__ __launch_bounds__(CNT) void k_conv3d_lds(const uint16_t* __restrict__
     }
     return;
   }
+  // rows of a wave's column tile that fit the brick at once as FP32
+  constexpr int kRP = static_cast<int>(sizeof(brick) / (CWAVES * 16 * 16 * sizeof(float))) >= MT
+                          ? MT
+                          : (sizeof(brick) >= CWAVES * 2 * 16 * 16 * sizeof(float) ? 2 : 0);
+  if (NT16 <= 2 && kRP > 0 && !y16 && cg.ycl32 && cg.dz16 && !cg.hpool && cg.csplit == 0 &&
+      cg.cout % 8 == 0) {
+    // the fused BF16 output gradient (the output layer's input gradient)
+    // through the LDS brick, kRP rows of one column tile at a time: each lane
+    // takes 8 channels of one voxel with 16-byte accesses (the FP32 sum it
+    // adds to, the activation it differentiates, the BF16 result)
+    float* tb = reinterpret_cast<float*>(brick) + wave * (kRP * 16 * 16);
+#pragma unroll
+    for (int t = 0; t < NT16; ++t) {
+#pragma unroll
+      for (int qb = 0; qb < MT; qb += kRP) {
+#pragma unroll
+        for (int q2 = 0; q2 < kRP; ++q2)
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            float val = acc[qb + q2][t][i];
+            if (cg.act) val = val > 0.0f ? val : cg.slope * val;
+            tb[(q2 * 16 + 4 * kg + i) * 16 + r] = val;
+          }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kRP / 2; ++k) {
+          const int c = lane + 64 * k;  // voxel c / 2 of the rows, channels 8 (c % 2) ..
+          const int v = c >> 1, hh = c & 1;
+          const int y = oy + qb + v / 16, x = ox + v % 16, co8 = nco0 + t * 16 + 8 * hh;
+          if (z < cg.o0 && y < cg.o1 && x < cg.o2 && co8 < cg.cout) {
+            const long long i0 =
+                (s * per + (static_cast<long long>(z) * cg.o1 + y) * cg.o2 + x) * cg.cout + co8;
+            const float4 lo = *reinterpret_cast<const float4*>(tb + v * 16 + 8 * hh);
+            const float4 hi = *reinterpret_cast<const float4*>(tb + v * 16 + 8 * hh + 4);
+            float tv[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+            if (cg.accum) {
+              const float4 a0 = *reinterpret_cast<const float4*>(y32 + i0);
+              const float4 a1 = *reinterpret_cast<const float4*>(y32 + i0 + 4);
+              const float av[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+#pragma unroll
+              for (int j = 0; j < 8; ++j) tv[j] = av[j] + tv[j];
+            }
+            const uint4 ay = *reinterpret_cast<const uint4*>(cg.acty + i0);
+            const uint32_t aw[4] = {ay.x, ay.y, ay.z, ay.w};
+            uint32_t ow[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              float e0 = tv[2 * j], e1 = tv[2 * j + 1];
+              if (!(__uint_as_float(aw[j] << 16) > 0.0f)) e0 *= cg.slope;
+              if (!(__uint_as_float(aw[j] & 0xFFFF0000u) > 0.0f)) e1 *= cg.slope;
+              ow[j] = static_cast<uint32_t>(to_bf16(e0)) | (static_cast<uint32_t>(to_bf16(e1)) << 16);
+            }
+            *reinterpret_cast<uint4*>(cg.dz16 + i0) = make_uint4(ow[0], ow[1], ow[2], ow[3]);
+          }
+        }
+        __syncthreads();
+      }
+    }
+    return;
+  }
   if (cg.hpool) {
     // channels below csplit to half resolution: the lane's 2 (d1) x 2 (d2)
     // children of each pair of its row tiles and d2 offsets summed in

@@ -607,7 +607,7 @@ __global__ __launch_bounds__(CNT) void k_conv3d_sub(const uint16_t* __restrict__
   const int n0 = 1 + pz, n1 = 1 + py, n2 = 1 + px;
   const int ntap = n0 * n1 * n2;
   const int npair = ntap * CG, nstep = (npair + 3) / 4;
-  if (threadIdx.x < 4 * nstep) {
+  if (static_cast<int>(threadIdx.x) < 4 * nstep) {
     const int q = threadIdx.x;
     int2 e = make_int2(0, -1);  // past the class's pairs: weight 0
     if (q < npair) {
